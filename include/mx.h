@@ -1,0 +1,188 @@
+/*
+ * mx.h -- C ABI of the MI355X (gfx950) time-harmonic Maxwell solver.
+ *
+ * The library solves, for every transmitting antenna, the lowest-order
+ * Nedelec edge-element discretisation of
+ *
+ *     curl curl E - k0^2 eps_r E = -j omega mu0 J          in Omega,
+ *     (curl E) x n + j k n x (E x n) = 0                   on dOmega,
+ *
+ * (time factor exp(+j omega t), k = k0 sqrt(eps_r)); this is the forward
+ * problem of the microwave-imaging method (paper Sec. III-B, eq. (1) and
+ * its weak form (2), with the open-side impedance condition on the whole
+ * outer boundary and point dipoles in place of the waveguide ports).  The
+ * linear systems A u_j = b_j (Sec. III-C) are solved with right-
+ * preconditioned flexible GMRES and a one-level Optimized Restricted Additive
+ * Schwarz preconditioner (Sec. III-C), with all transmitters as one block of
+ * right-hand sides.  Receiver responses S_ij = r_i^T u_j follow the
+ * scattering functional (eq. (3)) with point receivers.
+ *
+ * Conventions
+ *   - Every function returns an int: MX_OK (0) on success, a negative MX_E*
+ *     code on failure; mx_last_error() then returns a message (thread-local,
+ *     valid until the next call on the same thread).  No C++ exception
+ *     crosses this boundary.
+ *   - Units are SI (metres, hertz).  eps_r is dimensionless complex with
+ *     negative imaginary part for lossy media.
+ *   - Complex numbers are interleaved (re, im) pairs of doubles (mx_c128).
+ *   - Block vectors are DOF-major: X[e * nrhs + j] is DOF (edge) e of
+ *     right-hand side j.
+ *   - Pointers marked "host or device" may point to host memory or to
+ *     device memory of the context's GPU; the library detects which.  All
+ *     other pointers are host memory.  The caller owns every buffer it passes;
+ *     the library copies inputs before returning.
+ *   - A context is not thread-safe.  Work runs on the context's stream and
+ *     every call synchronises before returning.
+ *   - Call order: mx_create -> mx_assemble -> mx_setup_schwarz -> mx_solve...
+ *     mx_assemble invalidates the Schwarz factors (call mx_setup_schwarz
+ *     again); out-of-order calls return MX_ESTATE.
+ */
+#ifndef MX_H
+#define MX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MX_OK = 0,
+  MX_EINVAL = -1,   /* invalid argument (sizes, NaN permittivity, inverted tet, point outside) */
+  MX_ENOMEM = -2,   /* device or host allocation failed */
+  MX_ESTATE = -3,   /* call out of order */
+  MX_ENOTCONV = -4, /* FGMRES hit maxit; outputs hold the last iterate */
+  MX_EPIVOT = -5,   /* zero pivot in a subdomain factorisation */
+  MX_EHIP = -6      /* HIP runtime error */
+};
+
+enum { MX_EPS_P0 = 0 /* one value per tetrahedron */, MX_EPS_P1 = 1 /* one value per vertex */ };
+enum { MX_PREC_C128 = 0 /* complex128 subdomain factors */, MX_PREC_C64 = 1 /* complex64 factors on MFMA */ };
+
+typedef struct mx_ctx mx_ctx;
+
+typedef struct { double re, im; } mx_c128;
+
+/* Tetrahedral mesh: xyz [nv][3] coordinates, tet [nt][4] 0-based vertex ids
+ * (any orientation).  Global edges are the distinct (vmin, vmax) vertex pairs
+ * numbered in lexicographic order; they are the unknowns. */
+typedef struct {
+  int32_t nv, nt;
+  const double* xyz;
+  const int32_t* tet;
+} mx_mesh;
+
+/* Options of the Schwarz preconditioner and the Krylov solver. */
+typedef struct {
+  int32_t precision;   /* MX_PREC_C128 or MX_PREC_C64 */
+  int32_t restart;     /* FGMRES restart length m (default 30 when <= 0) */
+  int32_t maxit;       /* iteration cap (default 2000 when <= 0) */
+  int32_t factor;      /* 1: factor the subdomain matrices (normal use);
+                          0: keep them assembled (mx_get_local_matrix only) */
+} mx_schwarz_opts;
+
+/* Point dipoles: pos [n][3] positions, moment [n][3] complex moments (A m).
+ * A unit z-dipole has moment (0,0,1). */
+typedef struct {
+  int32_t n;
+  const double* pos;
+  const mx_c128* moment;
+} mx_sources;
+
+/* Per-solve diagnostics (arrays are caller-owned, length nrhs, may be NULL). */
+typedef struct {
+  int32_t* iters;      /* Krylov iterations per right-hand side */
+  double* relres;      /* final true relative residual ||b - A x|| / ||b|| */
+  int32_t iters_max;   /* max over right-hand sides */
+  int32_t cycles;      /* restart cycles */
+  double t_iter;       /* seconds spent in the Krylov iteration */
+} mx_solve_info;
+
+/* Sizes of the current discretisation and decomposition. */
+typedef struct {
+  int64_t nv, nt, ne, nnz, nbface;
+  int32_t nsub, overlap, ncolour;
+  int64_t sum_ni;      /* sum of subdomain DOF counts n_i */
+  int64_t sum_Ni2;     /* sum of padded dense sizes N_i^2 (factor entries) */
+  int32_t nb;          /* dense block size; N_i = n_i rounded up to nb */
+} mx_sizes;
+
+/* Create a context on HIP device `device` (own stream). */
+int mx_create(mx_ctx** out, int device);
+int mx_destroy(mx_ctx* ctx);
+
+/* Operator assembly (eq. (2)): A = sum_T (K_T - k0^2 eps M_T) + j k_b sum_F B_F
+ * over the tetrahedra T and the outer boundary faces F, k_b = k0 sqrt(eps_b).
+ *   mesh      host; NULL reuses the mesh (topology) of the previous call
+ *   eps       [nt] (MX_EPS_P0) or [nv] (MX_EPS_P1) relative permittivity;
+ *             host or device
+ *   freq_hz   frequency (> 0)
+ *   eps_b     permittivity used in the outer impedance condition
+ * Errors: MX_EINVAL for bad sizes, non-finite eps or a degenerate tet. */
+int mx_assemble(mx_ctx* ctx, const mx_mesh* mesh, const mx_c128* eps, int eps_kind,
+                double freq_hz, mx_c128 eps_b);
+
+/* ORAS set-up (Sec. III-C): recursive coordinate bisection into nsub = 2^L
+ * parts, `overlap` layers of vertex-adjacent tetrahedra, integer partition
+ * of unity, local matrices with impedance transmission conditions, and the
+ * batched dense LU of all subdomain matrices (one set of launches).  The
+ * partition is cached while the mesh, nsub and overlap are unchanged.
+ * opts may be NULL (complex128, restart 30, maxit 2000, factor 1).
+ * Errors: MX_EINVAL (nsub not a power of two, overlap < 1), MX_EPIVOT. */
+int mx_setup_schwarz(mx_ctx* ctx, int32_t nsub, int32_t overlap, const mx_schwarz_opts* opts);
+
+/* All-transmitter solve: b_j = -j omega mu0 p_j . N_e(x_j) for every source
+ * (a point on a shared face/edge/vertex averages over its tetrahedra), block
+ * FGMRES to relative true residual rtol, receiver responses
+ * S[i][j] = p_i . E_j(x_i) for the receivers rx (NULL: rx = tx).
+ *   E  [ne][ntx] fields, host or device, may be NULL
+ *   S  [nrx][ntx] host or device, may be NULL
+ * Returns MX_ENOTCONV (outputs still written) when maxit is reached. */
+int mx_solve(mx_ctx* ctx, const mx_sources* tx, const mx_sources* rx, double rtol,
+             mx_c128* E, mx_c128* S, mx_solve_info* info);
+
+/* Same solver on caller-supplied right-hand sides b [ne][nrhs] (host or
+ * device); solution x [ne][nrhs] (host or device). */
+int mx_solve_rhs(mx_ctx* ctx, const mx_c128* b, int32_t nrhs, double rtol,
+                 mx_c128* x, mx_solve_info* info);
+
+/* Y = A X for X, Y [ne][nrhs] (host or device). */
+int mx_apply_operator(mx_ctx* ctx, const mx_c128* X, mx_c128* Y, int32_t nrhs);
+
+/* Z = M^{-1} X = sum_i R_i^T D_i B_i^{-1} R_i X (one ORAS application;
+ * complex64 factors round R_i X to complex64).  X, Z host or device. */
+int mx_apply_preconditioner(mx_ctx* ctx, const mx_c128* X, mx_c128* Z, int32_t nrhs);
+
+/* Sizes of the current state (zeros for parts not yet built). */
+int mx_get_sizes(mx_ctx* ctx, mx_sizes* out);
+
+/* Copies of the topology (host buffers of the sizes in mx_sizes; any may be
+ * NULL): edges [ne][2], t2e [nt][6] (edges of the id-sorted tetrahedron in
+ * the order (01,02,03,12,13,23)), row_ptr [ne+1], col [nnz]. */
+int mx_get_topology(mx_ctx* ctx, int32_t* edges, int32_t* t2e, int64_t* row_ptr, int32_t* col);
+
+/* Copy of the assembled CSR values [nnz] (host). */
+int mx_get_matrix_values(mx_ctx* ctx, mx_c128* val);
+
+/* Copies of the decomposition (host, any may be NULL): part [nt] core
+ * subdomain of each tetrahedron, dof_ptr [nsub+1], dofs [sum_ni] (sorted
+ * global edges of each overlapping subdomain), pu_w [sum_ni] integer
+ * partition-of-unity weights, colour [nsub]. */
+int mx_get_partition(mx_ctx* ctx, int32_t* part, int64_t* dof_ptr, int32_t* dofs,
+                     int32_t* pu_w, int32_t* colour);
+
+/* Copy of the assembled (unfactored, opts.factor = 0) local matrix of
+ * subdomain i as a dense row-major [n_i][n_i] array (host). */
+int mx_get_local_matrix(mx_ctx* ctx, int32_t i, mx_c128* B);
+
+/* Point functionals r[e] = p . N_e(x) of the given points as a dense
+ * [ne][n] array (host); the same values build right-hand sides. */
+int mx_point_functionals(mx_ctx* ctx, const mx_sources* pts, mx_c128* R);
+
+const char* mx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MX_H */

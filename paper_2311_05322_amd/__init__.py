@@ -1,0 +1,269 @@
+"""Python binding of libmx.so, the MI355X (gfx950) Maxwell/Schwarz solver.
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Arrays may be numpy arrays (host) or torch tensors on the GPU
+(device pointers are passed straight through).  The C ABI is declared in
+include/mx.h; the names here mirror it.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmx.so")
+
+MX_OK, MX_EINVAL, MX_ENOMEM, MX_ESTATE, MX_ENOTCONV, MX_EPIVOT, MX_EHIP = 0, -1, -2, -3, -4, -5, -6
+MX_EPS_P0, MX_EPS_P1 = 0, 1
+MX_PREC_C128, MX_PREC_C64 = 0, 1
+
+EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_solve", "mx_solve_rhs",
+           "mx_apply_operator", "mx_apply_preconditioner", "mx_get_sizes", "mx_get_topology",
+           "mx_get_matrix_values", "mx_get_partition", "mx_get_local_matrix", "mx_point_functionals",
+           "mx_last_error"]
+
+
+class MxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class c128(ct.Structure):
+    _fields_ = [("re", ct.c_double), ("im", ct.c_double)]
+
+
+class Mesh(ct.Structure):
+    _fields_ = [("nv", ct.c_int32), ("nt", ct.c_int32), ("xyz", ct.c_void_p), ("tet", ct.c_void_p)]
+
+
+class SchwarzOpts(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("restart", ct.c_int32), ("maxit", ct.c_int32), ("factor", ct.c_int32)]
+
+
+class Sources(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("pos", ct.c_void_p), ("moment", ct.c_void_p)]
+
+
+class SolveInfo(ct.Structure):
+    _fields_ = [("iters", ct.c_void_p), ("relres", ct.c_void_p), ("iters_max", ct.c_int32),
+                ("cycles", ct.c_int32), ("t_iter", ct.c_double)]
+
+
+class Sizes(ct.Structure):
+    _fields_ = [("nv", ct.c_int64), ("nt", ct.c_int64), ("ne", ct.c_int64), ("nnz", ct.c_int64),
+                ("nbface", ct.c_int64), ("nsub", ct.c_int32), ("overlap", ct.c_int32), ("ncolour", ct.c_int32),
+                ("sum_ni", ct.c_int64), ("sum_Ni2", ct.c_int64), ("nb", ct.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_05322_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        vp, i32, dbl = ct.c_void_p, ct.c_int32, ct.c_double
+        sig = {
+            "mx_create": [ct.POINTER(vp), ct.c_int],
+            "mx_destroy": [vp],
+            "mx_assemble": [vp, ct.POINTER(Mesh), vp, ct.c_int, dbl, c128],
+            "mx_setup_schwarz": [vp, i32, i32, ct.POINTER(SchwarzOpts)],
+            "mx_solve": [vp, ct.POINTER(Sources), ct.POINTER(Sources), dbl, vp, vp, ct.POINTER(SolveInfo)],
+            "mx_solve_rhs": [vp, vp, i32, dbl, vp, ct.POINTER(SolveInfo)],
+            "mx_apply_operator": [vp, vp, vp, i32],
+            "mx_apply_preconditioner": [vp, vp, vp, i32],
+            "mx_get_sizes": [vp, ct.POINTER(Sizes)],
+            "mx_get_topology": [vp, vp, vp, vp, vp],
+            "mx_get_matrix_values": [vp, vp],
+            "mx_get_partition": [vp, vp, vp, vp, vp, vp],
+            "mx_get_local_matrix": [vp, i32, vp],
+            "mx_point_functionals": [vp, ct.POINTER(Sources), vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ct.c_int
+        L.mx_last_error.argtypes = []
+        L.mx_last_error.restype = ct.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, allow=()):
+    if rc != MX_OK and rc not in allow:
+        raise MxError(rc, lib().mx_last_error().decode())
+    return rc
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """Raw pointer of a contiguous numpy array or torch tensor (host or device)."""
+    if a is None:
+        return None
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ct.c_void_p(a.data_ptr())
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return ct.c_void_p(a.ctypes.data)
+
+
+def _sources(pos, mom):
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    mom = np.ascontiguousarray(mom, dtype=np.complex128)
+    s = Sources(pos.shape[0], pos.ctypes.data, mom.ctypes.data)
+    return s, (pos, mom)
+
+
+class Context:
+    """One solver context on one GPU (wraps mx_create / mx_destroy)."""
+
+    def __init__(self, device: int = 0):
+        h = ct.c_void_p()
+        _check(lib().mx_create(ct.byref(h), device))
+        self._h = h
+        self.ne = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- operator ------------------------------------------------------------
+    def assemble(self, xyz, tet, eps, eps_kind, freq, eps_b, reuse_mesh=False):
+        keep = []
+        if reuse_mesh:
+            mp = None
+        else:
+            xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+            tet = np.ascontiguousarray(tet, dtype=np.int32)
+            keep += [xyz, tet]
+            m = Mesh(xyz.shape[0], tet.shape[0], xyz.ctypes.data, tet.ctypes.data)
+            mp = ct.byref(m)
+        if not _is_torch(eps):
+            eps = np.ascontiguousarray(eps, dtype=np.complex128)
+        eb = complex(eps_b)
+        _check(lib().mx_assemble(self._h, mp, _ptr(eps), int(eps_kind), float(freq), c128(eb.real, eb.imag)))
+        self.ne = self.sizes().ne
+        del keep
+
+    def setup_schwarz(self, nsub, overlap, precision=MX_PREC_C128, restart=30, maxit=2000, factor=True):
+        o = SchwarzOpts(int(precision), int(restart), int(maxit), 1 if factor else 0)
+        _check(lib().mx_setup_schwarz(self._h, int(nsub), int(overlap), ct.byref(o)))
+
+    # -- solves ----------------------------------------------------------------
+    def solve(self, pos, mom, rx=None, rtol=1e-8, E=None, S=None, want_E=True):
+        """All-transmitter solve.  E/S may be preallocated host arrays or device
+        tensors ([ne][ntx], [nrx][ntx] complex128); returns (E, S, info)."""
+        tx, keep = _sources(pos, mom)
+        rxs = None
+        if rx is not None:
+            rxs, keep2 = _sources(*rx)
+            keep = keep + keep2
+        ntx = tx.n
+        nrx = rxs.n if rxs is not None else ntx
+        if E is None and want_E:
+            E = np.zeros((self.ne, ntx), dtype=np.complex128)
+        if S is None:
+            S = np.zeros((nrx, ntx), dtype=np.complex128)
+        iters = np.zeros(ntx, dtype=np.int32)
+        relres = np.zeros(ntx, dtype=np.float64)
+        info = SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        rc = lib().mx_solve(self._h, ct.byref(tx), ct.byref(rxs) if rxs is not None else None, float(rtol),
+                            _ptr(E), _ptr(S), ct.byref(info))
+        _check(rc, allow=(MX_ENOTCONV,))
+        return E, S, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
+                      "t_iter": info.t_iter, "converged": rc == MX_OK}
+
+    def solve_rhs(self, b, rtol=1e-8, x=None):
+        nrhs = b.shape[1]
+        if not _is_torch(b):
+            b = np.ascontiguousarray(b, dtype=np.complex128)
+        if x is None:
+            x = np.zeros((self.ne, nrhs), dtype=np.complex128)
+        iters = np.zeros(nrhs, dtype=np.int32)
+        relres = np.zeros(nrhs, dtype=np.float64)
+        info = SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        rc = lib().mx_solve_rhs(self._h, _ptr(b), nrhs, float(rtol), _ptr(x), ct.byref(info))
+        _check(rc, allow=(MX_ENOTCONV,))
+        return x, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
+                   "t_iter": info.t_iter, "converged": rc == MX_OK}
+
+    def apply_operator(self, X, Y=None):
+        X2 = X if _is_torch(X) else np.ascontiguousarray(X, dtype=np.complex128)
+        if Y is None:
+            Y = np.zeros_like(X2) if not _is_torch(X2) else X2.clone()
+        _check(lib().mx_apply_operator(self._h, _ptr(X2), _ptr(Y), X2.shape[1]))
+        return Y
+
+    def apply_preconditioner(self, X, Z=None):
+        X2 = X if _is_torch(X) else np.ascontiguousarray(X, dtype=np.complex128)
+        if Z is None:
+            Z = np.zeros_like(X2) if not _is_torch(X2) else X2.clone()
+        _check(lib().mx_apply_preconditioner(self._h, _ptr(X2), _ptr(Z), X2.shape[1]))
+        return Z
+
+    # -- inspection ------------------------------------------------------------
+    def sizes(self):
+        s = Sizes()
+        _check(lib().mx_get_sizes(self._h, ct.byref(s)))
+        return s
+
+    def topology(self):
+        s = self.sizes()
+        edges = np.zeros((s.ne, 2), np.int32)
+        t2e = np.zeros((s.nt, 6), np.int32)
+        rp = np.zeros(s.ne + 1, np.int64)
+        col = np.zeros(s.nnz, np.int32)
+        _check(lib().mx_get_topology(self._h, _ptr(edges), _ptr(t2e), _ptr(rp), _ptr(col)))
+        return edges, t2e, rp, col
+
+    def matrix_values(self):
+        v = np.zeros(self.sizes().nnz, np.complex128)
+        _check(lib().mx_get_matrix_values(self._h, _ptr(v)))
+        return v
+
+    def partition(self):
+        s = self.sizes()
+        part = np.zeros(s.nt, np.int32)
+        dp = np.zeros(s.nsub + 1, np.int64)
+        dofs = np.zeros(s.sum_ni, np.int32)
+        w = np.zeros(s.sum_ni, np.int32)
+        col = np.zeros(s.nsub, np.int32)
+        _check(lib().mx_get_partition(self._h, _ptr(part), _ptr(dp), _ptr(dofs), _ptr(w), _ptr(col)))
+        return part, dp, dofs, w, col
+
+    def local_matrix(self, i):
+        dp = self.partition()[1]
+        n = int(dp[i + 1] - dp[i])
+        B = np.zeros((n, n), np.complex128)
+        _check(lib().mx_get_local_matrix(self._h, int(i), _ptr(B)))
+        return B
+
+    def point_functionals(self, pos, mom):
+        s, keep = _sources(pos, mom)
+        R = np.zeros((self.ne, s.n), np.complex128)
+        _check(lib().mx_point_functionals(self._h, ct.byref(s), _ptr(R)))
+        return R

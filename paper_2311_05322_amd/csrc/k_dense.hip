@@ -1,0 +1,672 @@
+// Batched dense complex LU with partial pivoting of all subdomain matrices and
+// the batched multi-right-hand-side triangular solves, templated on the real
+// type (double: complex128 factors, float: complex64 factors on MFMA).
+//
+// Storage: subdomain s owns a row-major N_s x N_s block at pool + mat_off[s];
+// N_s is a multiple of NB = 64 (rows/columns past the real size hold an
+// identity).  The factorisation is P A = L U in LAPACK form (pivot k swaps
+// rows k and piv[k] across all columns).  On exit the diagonal 64x64 blocks
+// hold inverses: strictly lower part = strictly lower part of L_bb^{-1}
+// (unit diagonal implied), upper part incl. diagonal = U_bb^{-1}; the other
+// blocks hold L (below) and U (above).  The triangular solves then consist of
+// matrix products only, which run on the 16x16x4 matrix cores.
+//
+// One factorisation is a sequence of launches per 64-column panel:
+//   k_lu_panel     one 1024-thread workgroup per matrix: left-looking
+//                  factorisation of the 64-wide panel in register-resident
+//                  sub-panels of W columns, partial pivoting by workgroup
+//                  reduction, then L11 -> L11^{-1} in place and the composed
+//                  row permutation of the panel;
+//   k_lu_rowpanel  applies the permutation to the columns outside the panel
+//                  and forms U12 = L11^{-1} A12 (MFMA);
+//   k_lu_update    A22 -= L21 U12 on 64x64 tiles (MFMA, LDS-staged operands).
+#include "mx_device.h"
+#include "mx_kernels.h"
+
+namespace mx {
+
+namespace {
+
+constexpr int NB = 64;
+constexpr int PT = 1024;     // panel workgroup size
+constexpr int MAXSW = 128;   // max distinct rows touched by one panel's swaps
+
+template <typename R> struct PanelW;
+template <> struct PanelW<float> { static constexpr int W = 4; };
+template <> struct PanelW<double> { static constexpr int W = 2; };
+
+template <typename R> __device__ inline Acc_t<R> zacc() {
+  Acc_t<R> z;
+  z[0] = 0; z[1] = 0; z[2] = 0; z[3] = 0;
+  return z;
+}
+template <typename C> __device__ inline C czero() { C z; z.x = 0; z.y = 0; return z; }
+template <typename C> __device__ inline C cone() { C z; z.x = 1; z.y = 0; return z; }
+template <typename C> __device__ inline C cmulT(C a, C b) {
+  C z; z.x = a.x * b.x - a.y * b.y; z.y = a.x * b.y + a.y * b.x; return z;
+}
+template <typename C> __device__ inline C csubT(C a, C b) { C z; z.x = a.x - b.x; z.y = a.y - b.y; return z; }
+template <typename C> __device__ inline C crecip(C a) {
+  C one = cone<C>();
+  return cdiv(one, a);
+}
+
+// --------------------------------------------------------------------------
+// panel factorisation
+// --------------------------------------------------------------------------
+template <typename R, int RPT>
+__global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                                 const int32_t* __restrict__ Npad, const int32_t* __restrict__ order,
+                                                 int32_t* __restrict__ piv, const int64_t* __restrict__ vec_off,
+                                                 int32_t* __restrict__ status, int32_t* __restrict__ pswap, int k0) {
+  typedef C_t<R> C;
+  constexpr int W = PanelW<R>::W;
+  const int s = order[blockIdx.x];
+  const int N = Npad[s];
+  if (k0 >= N) return;
+  C* A = pool + mat_off[s];
+  int32_t* pv = piv + vec_off[s];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+
+  __shared__ C Utop[NB][W];
+  __shared__ C swp[2][W];
+  __shared__ R red_v[PT / 64];
+  __shared__ int red_r[PT / 64];
+  __shared__ int piv_row;
+  __shared__ R piv_abs;
+  __shared__ C Lt[NB][NB + 1];
+  __shared__ C Xt[NB][NB + 1];
+  __shared__ int sw_dst[MAXSW], sw_src[MAXSW];
+  __shared__ int sw_n;
+
+  C a[RPT][W];
+  for (int s0 = 0; s0 < NB; s0 += W) {
+    const int c0 = k0 + s0;
+    // (A) top rows of the sub-panel columns: U[k0:c0, c0:c0+W] = L11^{-1} A
+    if (tid < W) {
+      const int cc = c0 + tid;
+      for (int i = 0; i < s0; ++i) {
+        C x = A[(int64_t)(k0 + i) * N + cc];
+        for (int l = 0; l < i; ++l) x = csubT(x, cmulT(A[(int64_t)(k0 + i) * N + k0 + l], Utop[l][tid]));
+        Utop[i][tid] = x;
+        A[(int64_t)(k0 + i) * N + cc] = x;
+      }
+    }
+    __syncthreads();
+    // (B) load sub-panel rows [c0, N) and subtract L[r, k0:c0] U[k0:c0, sub]
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = c0 + tid + PT * i;
+      if (r < N) {
+        const C* row = A + (int64_t)r * N;
+#pragma unroll
+        for (int j = 0; j < W; ++j) a[i][j] = row[c0 + j];
+        for (int l = 0; l < s0; ++l) {
+          C lv = row[k0 + l];
+#pragma unroll
+          for (int j = 0; j < W; ++j) a[i][j] = csubT(a[i][j], cmulT(lv, Utop[l][j]));
+        }
+      }
+    }
+    // (C) factor the W columns with partial pivoting
+    for (int j = 0; j < W; ++j) {
+      const int c = c0 + j;
+      R best = -1;
+      int brow = 0x7fffffff;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = c0 + tid + PT * i;
+        if (r < N && r >= c) {
+          R v = fabs(a[i][j].x) + fabs(a[i][j].y);
+          if (v > best || (v == best && r < brow)) { best = v; brow = r; }
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        R ob = __shfl_xor(best, off);
+        int orow = __shfl_xor(brow, off);
+        if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
+      }
+      if (lane == 0) { red_v[wv] = best; red_r[wv] = brow; }
+      __syncthreads();
+      if (tid == 0) {
+        R b = red_v[0];
+        int br = red_r[0];
+        for (int w = 1; w < PT / 64; ++w)
+          if (red_v[w] > b || (red_v[w] == b && red_r[w] < br)) { b = red_v[w]; br = red_r[w]; }
+        // no usable pivot (zero or non-finite column): keep the row order so
+        // every later access stays inside the matrix, and report the column
+        if (!(b > 0) || br < c || br >= N) {
+          br = c;
+          b = 0;
+          if (status[s] == 0) status[s] = c + 1;
+        }
+        piv_row = br;
+        piv_abs = b;
+        pv[c] = br;
+      }
+      __syncthreads();
+      const int p = piv_row;
+      // swap rows c and p: registers of the sub-panel ...
+      const int oc = c - c0, op = p - c0;
+      if ((oc % PT) == tid) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (i == oc / PT)
+#pragma unroll
+            for (int jj = 0; jj < W; ++jj) swp[0][jj] = a[i][jj];
+      }
+      if ((op % PT) == tid) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (i == op / PT)
+#pragma unroll
+            for (int jj = 0; jj < W; ++jj) swp[1][jj] = a[i][jj];
+      }
+      // ... and the other columns of the panel in memory
+      if (p != c && tid < NB) {
+        const int col = k0 + tid;
+        if (col < c0 || col >= c0 + W) {
+          C t0 = A[(int64_t)c * N + col];
+          A[(int64_t)c * N + col] = A[(int64_t)p * N + col];
+          A[(int64_t)p * N + col] = t0;
+        }
+      }
+      __syncthreads();
+      if ((oc % PT) == tid) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (i == oc / PT)
+#pragma unroll
+            for (int jj = 0; jj < W; ++jj) a[i][jj] = swp[1][jj];
+      }
+      if ((op % PT) == tid && p != c) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (i == op / PT)
+#pragma unroll
+            for (int jj = 0; jj < W; ++jj) a[i][jj] = swp[0][jj];
+      }
+      // eliminate below the pivot (pivot row values are swp[1])
+      const bool ok = piv_abs > 0;
+      C inv = ok ? crecip(swp[1][j]) : czero<C>();
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = c0 + tid + PT * i;
+        if (r < N && r > c) {
+          C l = cmulT(a[i][j], inv);
+          a[i][j] = l;
+#pragma unroll
+          for (int jj = j + 1; jj < W; ++jj) a[i][jj] = csubT(a[i][jj], cmulT(l, swp[1][jj]));
+        }
+      }
+      __syncthreads();
+    }
+    // (D) write the sub-panel back
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = c0 + tid + PT * i;
+      if (r < N) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) A[(int64_t)r * N + c0 + j] = a[i][j];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- L11 -> L11^{-1} (unit lower, strictly lower part stored)
+  for (int e = tid; e < NB * NB; e += PT) {
+    int i = e / NB, j = e % NB;
+    Lt[i][j] = A[(int64_t)(k0 + i) * N + k0 + j];
+  }
+  __syncthreads();
+  if (tid < NB) {
+    // column j of X = L^{-1}: X[j][j] = 1, X[i][j] = -sum_{l=j}^{i-1} L[i][l] X[l][j]
+    const int j = tid;
+    Xt[j][j] = cone<C>();
+    for (int i = j + 1; i < NB; ++i) {
+      C acc = czero<C>();
+      for (int l = j; l < i; ++l) acc = csubT(acc, cmulT(Lt[i][l], Xt[l][j]));
+      Xt[i][j] = acc;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += PT) {
+    int i = e / NB, j = e % NB;
+    if (j < i) A[(int64_t)(k0 + i) * N + k0 + j] = Xt[i][j];
+  }
+  // ---- composed permutation of this panel's swaps (rows >= k0)
+  if (tid == 0) {
+    int n = NB;
+    for (int k = 0; k < NB; ++k) { sw_dst[k] = k0 + k; sw_src[k] = k0 + k; }
+    for (int k = 0; k < NB; ++k) {
+      const int p = pv[k0 + k];
+      if (p == k0 + k) continue;
+      int ib = -1;
+      if (p < k0 + NB) {
+        ib = p - k0;
+      } else {
+        for (int q = NB; q < n; ++q)
+          if (sw_dst[q] == p) { ib = q; break; }
+        if (ib < 0) { ib = n++; sw_dst[ib] = p; sw_src[ib] = p; }
+      }
+      int t = sw_src[k];
+      sw_src[k] = sw_src[ib];
+      sw_src[ib] = t;
+    }
+    sw_n = n;
+  }
+  __syncthreads();
+  int32_t* ps = pswap + (int64_t)s * (2 * MAXSW + 1);
+  if (tid == 0) ps[0] = sw_n;
+  for (int q = tid; q < sw_n; q += PT) {
+    ps[1 + q] = sw_dst[q];
+    ps[1 + MAXSW + q] = sw_src[q];
+  }
+}
+
+// --------------------------------------------------------------------------
+// row permutation outside the panel and U12 = L11^{-1} A12
+// --------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                                     const int32_t* __restrict__ Npad,
+                                                     const int32_t* __restrict__ order,
+                                                     const int32_t* __restrict__ pswap, int k0) {
+  typedef C_t<R> C;
+  typedef Acc_t<R> Acc;
+  const int s = order[blockIdx.y];
+  const int N = Npad[s];
+  const int cb = blockIdx.x * NB;
+  if (cb >= N || cb == k0 || k0 >= N) return;
+  C* A = pool + mat_off[s];
+  const int32_t* ps = pswap + (int64_t)s * (2 * MAXSW + 1);
+  const int n = ps[0];
+  __shared__ C X[MAXSW][NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * NB; e += 256) {
+    int q = e / NB, j = e % NB;
+    X[q][j] = A[(int64_t)ps[1 + MAXSW + q] * N + cb + j];
+  }
+  __syncthreads();
+  if (cb < k0) {
+    for (int e = tid; e < n * NB; e += 256) {
+      int q = e / NB, j = e % NB;
+      A[(int64_t)ps[1 + q] * N + cb + j] = X[q][j];
+    }
+    return;
+  }
+  // rows below the panel that received another row's content
+  for (int e = tid; e < (n - NB) * NB; e += 256) {
+    int q = NB + e / NB, j = e % NB;
+    A[(int64_t)ps[1 + q] * N + cb + j] = X[q][j];
+  }
+  // U12 = L11^{-1} X[0:64]; wave w computes rows 16w..16w+15, all 64 columns
+  const int lane = tid & 63, w = tid >> 6;
+  Acc cre[4], cim[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) { cre[ct] = zacc<R>(); cim[ct] = zacc<R>(); }
+  const int ar = 16 * w + (lane & 15);
+  for (int kk = 0; kk < NB; kk += 4) {
+    const int kcol = kk + (lane >> 4);
+    C av;
+    if (kcol < ar) av = A[(int64_t)(k0 + ar) * N + k0 + kcol];
+    else if (kcol == ar) av = cone<C>();
+    else av = czero<C>();
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      C bv = X[kk + (lane >> 4)][16 * ct + (lane & 15)];
+      cmfma<R>(av, bv, cre[ct], cim[ct]);
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * w + acc_row<R>(lane, r);
+      C v;
+      v.x = cre[ct][r];
+      v.y = cim[ct][r];
+      A[(int64_t)(k0 + row) * N + cb + 16 * ct + (lane & 15)] = v;
+    }
+}
+
+// --------------------------------------------------------------------------
+// trailing update A22 -= L21 U12 on 64x64 tiles
+// --------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                                   const int32_t* __restrict__ Npad,
+                                                   const int32_t* __restrict__ order, int k0) {
+  typedef C_t<R> C;
+  typedef Acc_t<R> Acc;
+  const int s = order[blockIdx.z];
+  const int N = Npad[s];
+  const int i0 = k0 + NB + blockIdx.y * NB;
+  const int j0 = k0 + NB + blockIdx.x * NB;
+  if (i0 >= N || j0 >= N) return;
+  C* A = pool + mat_off[s];
+  __shared__ C As[NB][NB + 1];
+  __shared__ C Bs[NB][NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += 256) {
+    int r = e / NB, c = e % NB;
+    As[r][c] = A[(int64_t)(i0 + r) * N + k0 + c];
+    Bs[r][c] = A[(int64_t)(k0 + r) * N + j0 + c];
+  }
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  Acc cre[2][2], cim[2][2];
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        C v = A[(int64_t)(i0 + wr + 16 * it + acc_row<R>(lane, r)) * N + j0 + wc + 16 * jt + (lane & 15)];
+        cre[it][jt][r] = v.x;
+        cim[it][jt][r] = v.y;
+      }
+  __syncthreads();
+  for (int kk = 0; kk < NB; kk += 4) {
+    C av[2], bv[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      C t = As[wr + 16 * it + (lane & 15)][kk + (lane >> 4)];
+      av[it].x = -t.x;
+      av[it].y = -t.y;
+    }
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) bv[jt] = Bs[kk + (lane >> 4)][wc + 16 * jt + (lane & 15)];
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) cmfma<R>(av[it], bv[jt], cre[it][jt], cim[it][jt]);
+  }
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        C v;
+        v.x = cre[it][jt][r];
+        v.y = cim[it][jt][r];
+        A[(int64_t)(i0 + wr + 16 * it + acc_row<R>(lane, r)) * N + j0 + wc + 16 * jt + (lane & 15)] = v;
+      }
+}
+
+// --------------------------------------------------------------------------
+// U_bb -> U_bb^{-1} in the upper part of every diagonal block
+// --------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(64) k_inv_upper(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                                  const int32_t* __restrict__ Npad,
+                                                  const int32_t* __restrict__ order) {
+  typedef C_t<R> C;
+  const int s = order[blockIdx.y];
+  const int N = Npad[s];
+  const int b0 = blockIdx.x * NB;
+  if (b0 >= N) return;
+  C* A = pool + mat_off[s];
+  __shared__ C U[NB][NB + 1];
+  __shared__ C Y[NB][NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += 64) {
+    int i = e / NB, j = e % NB;
+    U[i][j] = A[(int64_t)(b0 + i) * N + b0 + j];
+  }
+  __syncthreads();
+  const int j = tid;
+  // column j of Y = U^{-1}: Y[j][j] = 1/U[j][j],
+  // Y[i][j] = -(sum_{l=i+1}^{j} U[i][l] Y[l][j]) / U[i][i] for i < j
+  Y[j][j] = crecip(U[j][j]);
+  for (int i = j - 1; i >= 0; --i) {
+    C acc = czero<C>();
+    for (int l = i + 1; l <= j; ++l) acc = csubT(acc, cmulT(U[i][l], Y[l][j]));
+    Y[i][j] = cmulT(acc, crecip(U[i][i]));
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 64) {
+    int i = e / NB, jj = e % NB;
+    if (jj >= i) A[(int64_t)(b0 + i) * N + b0 + jj] = Y[i][jj];
+  }
+}
+
+// rowsrc[vec_off[s] + r] = dofs[dof_ptr[s] + perm[r]] (or -1 on padded rows),
+// perm = the row permutation P of P A = L U
+__global__ void __launch_bounds__(64) k_perm(int32_t nsub, const int32_t* __restrict__ Npad,
+                                             const int64_t* __restrict__ vec_off,
+                                             const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ dofs,
+                                             const int32_t* __restrict__ piv, int32_t* __restrict__ perm_scratch,
+                                             int32_t* __restrict__ rowsrc) {
+  const int s = blockIdx.x;
+  if (s >= nsub) return;
+  const int N = Npad[s];
+  int32_t* perm = perm_scratch + vec_off[s];
+  const int32_t* pv = piv + vec_off[s];
+  for (int r = threadIdx.x; r < N; r += 64) perm[r] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < N; ++k) {
+      int p = pv[k];
+      if (p != k) { int t = perm[k]; perm[k] = perm[p]; perm[p] = t; }
+    }
+  }
+  __syncthreads();
+  const int64_t n = dof_ptr[s + 1] - dof_ptr[s];
+  for (int r = threadIdx.x; r < N; r += 64) {
+    int q = perm[r];
+    rowsrc[vec_off[s] + r] = q < n ? dofs[dof_ptr[s] + q] : -1;
+  }
+}
+
+// --------------------------------------------------------------------------
+// triangular solves: X <- U^{-1} L^{-1} X on [N][nrhs] blocks, 32 right-hand
+// sides per workgroup, 256-row super-blocks, 64-row diagonal blocks applied
+// through their stored inverses
+// --------------------------------------------------------------------------
+constexpr int SB = 256;
+constexpr int KC = 32;
+constexpr int RC = 32;
+
+template <typename R, bool LOWER>
+__device__ inline C_t<R> diag_inv_elem(const C_t<R>* A, int N, int b0, int i, int k) {
+  typedef C_t<R> C;
+  if (LOWER) {
+    if (k < i) return A[(int64_t)(b0 + i) * N + b0 + k];
+    return k == i ? cone<C>() : czero<C>();
+  } else {
+    if (k >= i) return A[(int64_t)(b0 + i) * N + b0 + k];
+    return czero<C>();
+  }
+}
+
+template <typename R, bool LOWER>
+__global__ void __launch_bounds__(256) k_trsm(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                              const int32_t* __restrict__ Npad, const int64_t* __restrict__ vec_off,
+                                              C_t<R>* __restrict__ xloc, int nrhs) {
+  typedef C_t<R> C;
+  typedef Acc_t<R> Acc;
+  const int s = blockIdx.x;
+  const int N = Npad[s];
+  const C* A = pool + mat_off[s];
+  C* X = xloc + vec_off[s] * (int64_t)nrhs;
+  const int j0 = blockIdx.y * RC;
+  const int nc = min(RC, nrhs - j0);
+  __shared__ C Yb[KC][RC + 1];
+  __shared__ C Tb[SB][RC + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nsb = (N + SB - 1) / SB;
+  for (int q = 0; q < nsb; ++q) {
+    const int sbi = LOWER ? q : nsb - 1 - q;
+    const int b0 = sbi * SB;
+    const int sbn = min(SB, N - b0);
+    const int nd = sbn / NB;
+    // off-diagonal part: acc = A[rows, K] X[K]
+    const int kbeg = LOWER ? 0 : b0 + sbn;
+    const int kend = LOWER ? b0 : N;
+    Acc cre[4][2], cim[4][2];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) { cre[rt][ct] = zacc<R>(); cim[rt][ct] = zacc<R>(); }
+    for (int kc = kbeg; kc < kend; kc += KC) {
+      for (int e = tid; e < KC * RC; e += 256) {
+        int r = e / RC, c = e % RC;
+        Yb[r][c] = c < nc ? X[(int64_t)(kc + r) * nrhs + j0 + c] : czero<C>();
+      }
+      __syncthreads();
+      if (w < nd) {
+        for (int kk = 0; kk < KC; kk += 4) {
+          C bv[2];
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) bv[ct] = Yb[kk + (lane >> 4)][16 * ct + (lane & 15)];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            C av = A[(int64_t)(b0 + 64 * w + 16 * rt + (lane & 15)) * N + kc + kk + (lane >> 4)];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) cmfma<R>(av, bv[ct], cre[rt][ct], cim[rt][ct]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (w < nd) {
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 64 * w + 16 * rt + acc_row<R>(lane, r);
+            const int col = 16 * ct + (lane & 15);
+            C x = col < nc ? X[(int64_t)(b0 + row) * nrhs + j0 + col] : czero<C>();
+            x.x -= cre[rt][ct][r];
+            x.y -= cim[rt][ct][r];
+            Tb[row][col] = x;
+          }
+    }
+    __syncthreads();
+    // diagonal part
+    for (int dq = 0; dq < nd; ++dq) {
+      const int d = LOWER ? dq : nd - 1 - dq;
+      const int db = b0 + 64 * d;
+      Acc yre[2], yim[2];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) { yre[ct] = zacc<R>(); yim[ct] = zacc<R>(); }
+      for (int kk = 0; kk < NB; kk += 4) {
+        C av = diag_inv_elem<R, LOWER>(A, N, db, 16 * w + (lane & 15), kk + (lane >> 4));
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          C bv = Tb[64 * d + kk + (lane >> 4)][16 * ct + (lane & 15)];
+          cmfma<R>(av, bv, yre[ct], yim[ct]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * w + acc_row<R>(lane, r);
+          const int col = 16 * ct + (lane & 15);
+          C v;
+          v.x = yre[ct][r];
+          v.y = yim[ct][r];
+          Tb[64 * d + row][col] = v;
+          if (col < nc) X[(int64_t)(db + row) * nrhs + j0 + col] = v;
+        }
+      __syncthreads();
+      // update the remaining diagonal blocks of this super-block
+      const int nrem = LOWER ? (nd - 1 - d) : d;
+      for (int t = w; t < 4 * nrem; t += 4) {
+        const int dd = LOWER ? d + 1 + t / 4 : t / 4;
+        const int rt = t % 4;
+        Acc ure[2], uim[2];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) { ure[ct] = zacc<R>(); uim[ct] = zacc<R>(); }
+        for (int kk = 0; kk < NB; kk += 4) {
+          C av = A[(int64_t)(b0 + 64 * dd + 16 * rt + (lane & 15)) * N + db + kk + (lane >> 4)];
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            C bv = Tb[64 * d + kk + (lane >> 4)][16 * ct + (lane & 15)];
+            cmfma<R>(av, bv, ure[ct], uim[ct]);
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 64 * dd + 16 * rt + acc_row<R>(lane, r);
+            const int col = 16 * ct + (lane & 15);
+            Tb[row][col].x -= ure[ct][r];
+            Tb[row][col].y -= uim[ct][r];
+          }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+template <typename R>
+void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
+               int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
+               const std::vector<int32_t>& Nsorted) {
+  if (Nsorted.empty()) return;
+  const int Nmax = Nsorted[0];
+  for (int k0 = 0; k0 < Nmax; k0 += NB) {
+    int nact = 0;
+    while (nact < (int)Nsorted.size() && Nsorted[nact] > k0) ++nact;
+    const int m = Nmax - k0;
+    if (m <= PT * 1)
+      hipLaunchKernelGGL((k_lu_panel<R, 1>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
+                         status, pswap, k0);
+    else if (m <= PT * 2)
+      hipLaunchKernelGGL((k_lu_panel<R, 2>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
+                         status, pswap, k0);
+    else if (m <= PT * 4)
+      hipLaunchKernelGGL((k_lu_panel<R, 4>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
+                         status, pswap, k0);
+    else
+      hipLaunchKernelGGL((k_lu_panel<R, 8>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
+                         status, pswap, k0);
+    hipLaunchKernelGGL((k_lu_rowpanel<R>), dim3(ceil_div(Nmax, NB), nact), dim3(256), 0, st, pool, mat_off, Npad,
+                       order, pswap, k0);
+    const int nt = (Nmax - k0 - NB) / NB;
+    if (nt > 0)
+      hipLaunchKernelGGL((k_lu_update<R>), dim3(nt, nt, nact), dim3(256), 0, st, pool, mat_off, Npad, order, k0);
+  }
+  hipLaunchKernelGGL((k_inv_upper<R>), dim3(ceil_div(Nmax, NB), (unsigned)Nsorted.size()), dim3(64), 0, st, pool,
+                     mat_off, Npad, order);
+}
+template void launch_lu<float>(hipStream_t, float2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
+                               const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&);
+template void launch_lu<double>(hipStream_t, double2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
+                                const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&);
+
+void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int64_t* dof_ptr,
+                 const int32_t* dofs, const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc) {
+  if (nsub > 0)
+    hipLaunchKernelGGL(k_perm, dim3(nsub), dim3(64), 0, st, nsub, Npad, vec_off, dof_ptr, dofs, piv, perm_scratch,
+                       rowsrc);
+}
+
+template <typename R>
+void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
+                 const int64_t* vec_off, C_t<R>* xloc, int nsub, int nrhs) {
+  if (nsub <= 0 || nrhs <= 0) return;
+  dim3 grid(nsub, ceil_div(nrhs, RC));
+  hipLaunchKernelGGL((k_trsm<R, true>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, xloc, nrhs);
+  hipLaunchKernelGGL((k_trsm<R, false>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, xloc, nrhs);
+}
+template void launch_trsm<float>(hipStream_t, const float2*, const int64_t*, const int32_t*, const int64_t*, float2*,
+                                 int, int);
+template void launch_trsm<double>(hipStream_t, const double2*, const int64_t*, const int32_t*, const int64_t*,
+                                  double2*, int, int);
+
+int lu_max_swap_rows() { return MAXSW; }
+
+}  // namespace mx

@@ -1,0 +1,364 @@
+// Operator kernels: element and face blocks of the weak form (2), their
+// deterministic gather into the global CSR matrix and into the dense ORAS
+// subdomain matrices, the complex block SpMM, and the partition-of-unity
+// restriction / prolongation.
+#include "mx_device.h"
+#include "mx_kernels.h"
+
+namespace mx {
+
+namespace {
+
+__constant__ int cLE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+__constant__ int cLF[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+__constant__ int cFE2[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+
+__device__ inline void sub3(const double* a, const double* b, double* o) {
+  o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+__device__ inline void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ inline double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Barycentric gradients from face normals: grad l_k is parallel to the normal
+// N_k of the face opposite vertex k and grad l_k . (x_k - x_j) = 1 for any
+// vertex j of that face.  Returns the volume |T|.
+__device__ double tet_geometry(const double* xyz, const int32_t* v, double g[4][3]) {
+  double X[4][3];
+  for (int k = 0; k < 4; ++k)
+    for (int c = 0; c < 3; ++c) X[k][c] = xyz[3 * (size_t)v[k] + c];
+  for (int k = 0; k < 4; ++k) {
+    int j0 = (k + 1) & 3, j1 = (k + 2) & 3, j2 = (k + 3) & 3;
+    double u[3], w[3], n[3], d[3];
+    sub3(X[j1], X[j0], u);
+    sub3(X[j2], X[j0], w);
+    cross3(u, w, n);
+    sub3(X[k], X[j0], d);
+    double den = dot3(n, d);
+    for (int c = 0; c < 3; ++c) g[k][c] = n[c] / den;
+  }
+  double a[3], b[3], c[3], n[3];
+  sub3(X[1], X[0], a);
+  sub3(X[2], X[0], b);
+  sub3(X[3], X[0], c);
+  cross3(b, c, n);
+  return fabs(dot3(a, n)) / 6.0;
+}
+
+// int_T l_n l_i l_j / |T| = (1 + d_ni + d_nj + d_ij + 2 d_ni d_ij) / 120
+__device__ inline double lll(int n, int i, int j) {
+  int dni = n == i, dnj = n == j, dij = i == j;
+  return (1 + dni + dnj + dij + 2 * dni * dij) / 120.0;
+}
+
+__device__ inline double2 csqrt_principal(double2 z) {
+  double r = hypot(z.x, z.y);
+  double re = sqrt(0.5 * (r + z.x));
+  double im = sqrt(fmax(0.5 * (r - z.x), 0.0));
+  if (z.y < 0) im = -im;
+  return make_double2(re, im);
+}
+
+// Element block K_T - k0^2 (eps M)_T (6x6, mirrored upper triangle).
+__global__ void k_element(int32_t nt, const int32_t* __restrict__ ts, const double* __restrict__ xyz,
+                          const double2* __restrict__ eps, int eps_kind, double k0sq,
+                          double2* __restrict__ out) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  int32_t v[4];
+  for (int k = 0; k < 4; ++k) v[k] = ts[4 * (size_t)t + k];
+  double g[4][3];
+  double vol = tet_geometry(xyz, v, g);
+  double G[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) G[i][j] = dot3(g[i], g[j]);
+  // W_ij = int_T eps l_i l_j
+  double2 W[4][4];
+  if (eps_kind == 0) {
+    double2 e = eps[t];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        double f = vol * (1 + (i == j)) / 20.0;
+        W[i][j] = make_double2(e.x * f, e.y * f);
+      }
+  } else {
+    double2 ev[4];
+    for (int k = 0; k < 4; ++k) ev[k] = eps[v[k]];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        double re = 0, im = 0;
+        for (int n = 0; n < 4; ++n) {
+          double f = lll(n, i, j);
+          re += ev[n].x * f;
+          im += ev[n].y * f;
+        }
+        W[i][j] = make_double2(vol * re, vol * im);
+      }
+  }
+  double2* o = out + 36 * (size_t)t;
+  for (int p = 0; p < 6; ++p) {
+    int a = cLE[p][0], b = cLE[p][1];
+    for (int q = p; q < 6; ++q) {
+      int c = cLE[q][0], d = cLE[q][1];
+      double K = 4.0 * vol * (G[a][c] * G[b][d] - G[a][d] * G[b][c]);
+      double mre = W[a][c].x * G[b][d] - W[a][d].x * G[b][c] - W[b][c].x * G[a][d] + W[b][d].x * G[a][c];
+      double mim = W[a][c].y * G[b][d] - W[a][d].y * G[b][c] - W[b][c].y * G[a][d] + W[b][d].y * G[a][c];
+      double2 val = make_double2(K - k0sq * mre, -k0sq * mim);
+      o[6 * p + q] = val;
+      o[6 * q + p] = val;
+    }
+  }
+}
+
+// Face block j k B_F for (tet, local face) entries; k = kconst when
+// per_tet_k == 0, else k0 sqrt(eps of the tetrahedron).
+__global__ void k_face(int32_t n, const int32_t* __restrict__ ftet, const int32_t* __restrict__ flf,
+                       const int32_t* __restrict__ ts, const double* __restrict__ xyz,
+                       const double2* __restrict__ eps, int eps_kind, int per_tet_k, double k0,
+                       double2 kconst, double2* __restrict__ out) {
+  int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  int32_t t = ftet[f], lf = flf[f];
+  int32_t v[4];
+  for (int k = 0; k < 4; ++k) v[k] = ts[4 * (size_t)t + k];
+  double g[4][3];
+  tet_geometry(xyz, v, g);
+  int fv[3] = {cLF[lf][0], cLF[lf][1], cLF[lf][2]};
+  double P[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int c = 0; c < 3; ++c) P[k][c] = xyz[3 * (size_t)v[fv[k]] + c];
+  double u[3], w[3], nrm[3];
+  sub3(P[1], P[0], u);
+  sub3(P[2], P[0], w);
+  cross3(u, w, nrm);
+  double nn = sqrt(dot3(nrm, nrm));
+  double area = 0.5 * nn;
+  for (int c = 0; c < 3; ++c) nrm[c] /= nn;
+  double gs[3][3];
+  for (int k = 0; k < 3; ++k) {
+    double s = dot3(g[fv[k]], nrm);
+    for (int c = 0; c < 3; ++c) gs[k][c] = g[fv[k]][c] - s * nrm[c];
+  }
+  double G[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) G[i][j] = dot3(gs[i], gs[j]);
+  double2 kk = kconst;
+  if (per_tet_k) {
+    double2 e;
+    if (eps_kind == 0) {
+      e = eps[t];
+    } else {
+      double re = 0, im = 0;
+      for (int k = 0; k < 4; ++k) { re += eps[v[k]].x; im += eps[v[k]].y; }
+      e = make_double2(re / 4.0, im / 4.0);
+    }
+    double2 sq = csqrt_principal(e);
+    kk = make_double2(k0 * sq.x, k0 * sq.y);
+  }
+  // j k = (-k.y, k.x)
+  double2 jk = make_double2(-kk.y, kk.x);
+  double2* o = out + 9 * (size_t)f;
+  for (int p = 0; p < 3; ++p) {
+    int a = cFE2[p][0], b = cFE2[p][1];
+    for (int q = p; q < 3; ++q) {
+      int c = cFE2[q][0], d = cFE2[q][1];
+      double m = (1 + (a == c)) * G[b][d] - (1 + (a == d)) * G[b][c] - (1 + (b == c)) * G[a][d] +
+                 (1 + (b == d)) * G[a][c];
+      double B = area / 12.0 * m;
+      double2 val = make_double2(jk.x * B, jk.y * B);
+      o[3 * p + q] = val;
+      o[3 * q + p] = val;
+    }
+  }
+}
+
+// out[k] = sum of pool[src[j]] for j in [ptr[k], ptr[k+1]) (fixed order)
+__global__ void k_gather_csr(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ src,
+                             const double2* __restrict__ pool, double2* __restrict__ out) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double re = 0, im = 0;
+  for (int64_t j = ptr[k]; j < ptr[k + 1]; ++j) {
+    double2 v = pool[src[j]];
+    re += v.x;
+    im += v.y;
+  }
+  out[k] = make_double2(re, im);
+}
+
+template <typename C>
+__global__ void k_gather_dense(int64_t n, const int64_t* __restrict__ dest, const int64_t* __restrict__ ptr,
+                               const int32_t* __restrict__ src, const double2* __restrict__ pool,
+                               C* __restrict__ out) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double re = 0, im = 0;
+  for (int64_t j = ptr[k]; j < ptr[k + 1]; ++j) {
+    double2 v = pool[src[j]];
+    re += v.x;
+    im += v.y;
+  }
+  out[dest[k]] = from_c128<C>(make_double2(re, im));
+}
+
+template <typename C>
+__global__ void k_fill_zero(int64_t n, C* __restrict__ out) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += stride) {
+    C z;
+    z.x = 0;
+    z.y = 0;
+    out[k] = z;
+  }
+}
+
+// identity on the padded diagonal part of each dense subdomain matrix
+template <typename C>
+__global__ void k_pad_identity(int32_t nsub, const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ Npad,
+                               const int64_t* __restrict__ mat_off, C* __restrict__ A) {
+  int32_t s = blockIdx.x;
+  if (s >= nsub) return;
+  int64_t n = dof_ptr[s + 1] - dof_ptr[s];
+  int64_t N = Npad[s];
+  for (int64_t r = n + threadIdx.x; r < N; r += blockDim.x) {
+    C one;
+    one.x = 1;
+    one.y = 0;
+    A[mat_off[s] + r * N + r] = one;
+  }
+}
+
+// Y = A X, X and Y DOF-major [n][nrhs]; TPR threads per row, each handling
+// right-hand sides j = lane, lane + TPR, ...
+template <int TPR>
+__global__ void __launch_bounds__(256) k_spmm(int64_t nrows, const int64_t* __restrict__ rp,
+                                              const int32_t* __restrict__ col, const double2* __restrict__ val,
+                                              const double2* __restrict__ X, double2* __restrict__ Y, int nrhs) {
+  const int RPB = 256 / TPR;
+  int64_t row = blockIdx.x * (int64_t)RPB + threadIdx.x / TPR;
+  int lane = threadIdx.x % TPR;
+  if (row >= nrows) return;
+  int64_t k0 = rp[row], k1 = rp[row + 1];
+  for (int j = lane; j < nrhs; j += TPR) {
+    double re = 0, im = 0;
+    for (int64_t k = k0; k < k1; ++k) {
+      double2 a = val[k];
+      double2 x = X[(int64_t)col[k] * nrhs + j];
+      re += a.x * x.x - a.y * x.y;
+      im += a.x * x.y + a.y * x.x;
+    }
+    Y[row * nrhs + j] = make_double2(re, im);
+  }
+}
+
+// xloc[R][j] = v[rowsrc[R]][j] (0 for padded rows), cast to C
+template <typename C>
+__global__ void k_restrict(int64_t nrows, const int32_t* __restrict__ rowsrc, const double2* __restrict__ v,
+                           C* __restrict__ xloc, int nrhs) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= nrows * nrhs) return;
+  int64_t R = idx / nrhs;
+  int j = (int)(idx - R * nrhs);
+  int32_t e = rowsrc[R];
+  double2 x = e >= 0 ? v[(int64_t)e * nrhs + j] : make_double2(0.0, 0.0);
+  xloc[idx] = from_c128<C>(x);
+}
+
+// z[edge[k]][j] += w[k] * zloc[row[k]][j] for the entries of one colour
+// (edges of one colour are distinct, so there is no write conflict)
+template <typename C>
+__global__ void k_prolong(int64_t n, const int32_t* __restrict__ edge, const int64_t* __restrict__ row,
+                          const double* __restrict__ w, const C* __restrict__ zloc, double2* __restrict__ z,
+                          int nrhs) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n * nrhs) return;
+  int64_t k = idx / nrhs;
+  int j = (int)(idx - k * nrhs);
+  double2 s = to_c128(zloc[row[k] * nrhs + j]);
+  double wk = w[k];
+  int64_t o = (int64_t)edge[k] * nrhs + j;
+  double2 zz = z[o];
+  z[o] = make_double2(zz.x + wk * s.x, zz.y + wk * s.y);
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_element(hipStream_t s, int32_t nt, const int32_t* ts, const double* xyz, const double2* eps,
+                    int eps_kind, double k0sq, double2* out) {
+  if (nt > 0) hipLaunchKernelGGL(k_element, dim3(nblk(nt, 128)), dim3(128), 0, s, nt, ts, xyz, eps, eps_kind, k0sq, out);
+}
+void launch_face(hipStream_t s, int32_t n, const int32_t* ftet, const int32_t* flf, const int32_t* ts,
+                 const double* xyz, const double2* eps, int eps_kind, int per_tet_k, double k0, double2 kconst,
+                 double2* out) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_face, dim3(nblk(n, 128)), dim3(128), 0, s, n, ftet, flf, ts, xyz, eps, eps_kind,
+                       per_tet_k, k0, kconst, out);
+}
+void launch_gather_csr(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* src, const double2* pool,
+                       double2* out) {
+  if (n > 0) hipLaunchKernelGGL(k_gather_csr, dim3(nblk(n, 256)), dim3(256), 0, s, n, ptr, src, pool, out);
+}
+template <typename C>
+void launch_gather_dense(hipStream_t s, int64_t n, const int64_t* dest, const int64_t* ptr, const int32_t* src,
+                         const double2* pool, C* out) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_gather_dense<C>, dim3(nblk(n, 256)), dim3(256), 0, s, n, dest, ptr, src, pool, out);
+}
+template void launch_gather_dense<float2>(hipStream_t, int64_t, const int64_t*, const int64_t*, const int32_t*,
+                                          const double2*, float2*);
+template void launch_gather_dense<double2>(hipStream_t, int64_t, const int64_t*, const int64_t*, const int32_t*,
+                                           const double2*, double2*);
+template <typename C>
+void launch_fill_zero(hipStream_t s, int64_t n, C* out) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_zero<C>, dim3(4096), dim3(256), 0, s, n, out);
+}
+template void launch_fill_zero<float2>(hipStream_t, int64_t, float2*);
+template void launch_fill_zero<double2>(hipStream_t, int64_t, double2*);
+template <typename C>
+void launch_pad_identity(hipStream_t s, int32_t nsub, const int64_t* dof_ptr, const int32_t* Npad,
+                         const int64_t* mat_off, C* A) {
+  if (nsub > 0) hipLaunchKernelGGL(k_pad_identity<C>, dim3(nsub), dim3(64), 0, s, nsub, dof_ptr, Npad, mat_off, A);
+}
+template void launch_pad_identity<float2>(hipStream_t, int32_t, const int64_t*, const int32_t*, const int64_t*, float2*);
+template void launch_pad_identity<double2>(hipStream_t, int32_t, const int64_t*, const int32_t*, const int64_t*, double2*);
+
+void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t* col, const double2* val,
+                 const double2* X, double2* Y, int nrhs) {
+  if (nrows <= 0) return;
+  if (nrhs <= 8)
+    hipLaunchKernelGGL(k_spmm<8>, dim3(nblk(nrows, 32)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+  else if (nrhs <= 16)
+    hipLaunchKernelGGL(k_spmm<16>, dim3(nblk(nrows, 16)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+  else if (nrhs <= 32)
+    hipLaunchKernelGGL(k_spmm<32>, dim3(nblk(nrows, 8)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+  else
+    hipLaunchKernelGGL(k_spmm<64>, dim3(nblk(nrows, 4)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+}
+
+template <typename C>
+void launch_restrict(hipStream_t s, int64_t nrows, const int32_t* rowsrc, const double2* v, C* xloc, int nrhs) {
+  int64_t n = nrows * nrhs;
+  if (n > 0) hipLaunchKernelGGL(k_restrict<C>, dim3(nblk(n, 256)), dim3(256), 0, s, nrows, rowsrc, v, xloc, nrhs);
+}
+template void launch_restrict<float2>(hipStream_t, int64_t, const int32_t*, const double2*, float2*, int);
+template void launch_restrict<double2>(hipStream_t, int64_t, const int32_t*, const double2*, double2*, int);
+
+template <typename C>
+void launch_prolong(hipStream_t s, int64_t n, const int32_t* edge, const int64_t* row, const double* w,
+                    const C* zloc, double2* z, int nrhs) {
+  int64_t m = n * nrhs;
+  if (m > 0) hipLaunchKernelGGL(k_prolong<C>, dim3(nblk(m, 256)), dim3(256), 0, s, n, edge, row, w, zloc, z, nrhs);
+}
+template void launch_prolong<float2>(hipStream_t, int64_t, const int32_t*, const int64_t*, const double*,
+                                     const float2*, double2*, int);
+template void launch_prolong<double2>(hipStream_t, int64_t, const int32_t*, const int64_t*, const double*,
+                                      const double2*, double2*, int);
+
+}  // namespace mx

@@ -1,0 +1,787 @@
+// C ABI of the solver (declared in include/mx.h): context, state machine,
+// operator assembly, ORAS set-up, and the pseudo-block flexible GMRES driver.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mx.h"
+#include "host_mesh.h"
+#include "mx_device.h"
+#include "mx_kernels.h"
+
+namespace mx {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* expr, const char* file, int line) {
+  (void)hipGetLastError();
+  g_err = std::string("HIP error ") + hipGetErrorString(e) + " in " + expr + " (" + file + ":" +
+          std::to_string(line) + ")";
+  return e == hipErrorOutOfMemory ? MX_ENOMEM : MX_EHIP;
+}
+
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  int alloc(size_t count) {
+    if (p && count <= n) return MX_OK;
+    release();
+    if (count == 0) return MX_OK;
+    hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return set_err(MX_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+    return MX_OK;
+  }
+  int upload(const std::vector<T>& v, hipStream_t s) {
+    int rc = alloc(v.size());
+    if (rc) return rc;
+    if (!v.empty()) MX_HIP_CHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return MX_OK;
+  }
+};
+
+bool is_device_ptr(const void* ptr) {
+  if (!ptr) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
+
+const double C0 = 299792458.0;
+const double MU0 = 4.0e-7 * M_PI;
+
+double2 csqrt_host(double2 z) {
+  double r = std::hypot(z.x, z.y);
+  double re = std::sqrt(0.5 * (r + z.x));
+  double im = std::sqrt(std::max(0.5 * (r - z.x), 0.0));
+  if (z.y < 0) im = -im;
+  return make_double2(re, im);
+}
+
+__global__ void k_check_finite(int64_t n, const double2* v, int32_t* flag) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && !(isfinite(v[i].x) && isfinite(v[i].y))) *flag = 1;
+}
+__global__ void k_set_g0(int m, int nrhs, const double* beta, double2* g) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (m + 1) * nrhs) return;
+  g[idx] = idx < nrhs ? make_double2(beta[idx], 0.0) : make_double2(0.0, 0.0);
+}
+__global__ void k_zero_i32(int n, int32_t* a) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+template <typename C>
+__global__ void k_extract_local(int n, int N, const C* A, double2* out) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  int64_t i = idx / n, j = idx % n;
+  out[idx] = to_c128(A[i * N + j]);
+}
+
+struct SourceSet {
+  std::vector<double> pos;   // cached copy to detect changes
+  std::vector<double> mom;
+  std::vector<int64_t> ptr;  // per point
+  std::vector<int32_t> edge;
+  std::vector<double2> val;
+  bool same(const mx_sources* s) const {
+    if (!s || (size_t)s->n * 3 != pos.size()) return false;
+    return std::memcmp(pos.data(), s->pos, pos.size() * sizeof(double)) == 0 &&
+           std::memcmp(mom.data(), s->moment, mom.size() * sizeof(double)) == 0;
+  }
+};
+
+}  // namespace mx
+
+using namespace mx;
+
+struct mx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // mesh
+  Topology topo;
+  bool have_mesh = false;
+  DBuf<double> xyz;
+  DBuf<int32_t> ts, col, csrc, bf_tet, bf_lf;
+  DBuf<int64_t> row_ptr, cptr;
+  // operator
+  bool assembled = false;
+  int eps_kind = 0;
+  double freq = 0, k0 = 0, omega_mu0 = 0;
+  double2 kb = {0, 0};
+  DBuf<double2> eps, pool, val;
+  size_t pool_filled = 0;
+  // decomposition
+  Decomposition dec;
+  bool have_dec = false;
+  DBuf<int32_t> dofs, Npad, order, if_tet, if_lf, lsrc, p_edge, piv, status, pswap, perm, rowsrc;
+  DBuf<int64_t> dof_ptr, mat_off, vec_off, ldest, lptr, p_row;
+  DBuf<double> p_w;
+  std::vector<int32_t> Nsorted;
+  DBuf<char> factors;
+  int precision = MX_PREC_C128;
+  bool local_ready = false, factored = false;
+  int restart = 30, maxit = 2000;
+  // sources
+  SourceSet tx, rx;
+  DBuf<int32_t> s_edge, s_col, r_edge;
+  DBuf<double2> s_val, r_val;
+  DBuf<int64_t> r_ptr;
+  // workspace
+  int ws_nrhs = 0, ws_m = 0;
+  DBuf<double2> V, Z, x, b, r, H, sn, g, y, h1, h2, dotpart, S;
+  DBuf<double> cs, bnorm, hn, beta, normpart, res;
+  DBuf<int32_t> conv, kdone, flag;
+  DBuf<char> xloc;
+  int32_t* h_conv = nullptr;
+  double* h_vec = nullptr;
+  int32_t* h_kd = nullptr;
+  int h_cap = 0;
+};
+
+namespace {
+
+#define CK(expr)                 \
+  do {                           \
+    int _rc = (expr);            \
+    if (_rc != MX_OK) return _rc; \
+  } while (0)
+
+int use_device(mx_ctx* c) {
+  MX_HIP_CHECK(hipSetDevice(c->device));
+  return MX_OK;
+}
+
+// copies n elements between caller memory (host or device) and device memory
+int copy_in(mx_ctx* c, void* dst_dev, const void* src, size_t bytes) {
+  if (bytes == 0) return MX_OK;
+  hipMemcpyKind k = is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  MX_HIP_CHECK(hipMemcpyAsync(dst_dev, src, bytes, k, c->stream));
+  return MX_OK;
+}
+int copy_out(mx_ctx* c, void* dst, const void* src_dev, size_t bytes) {
+  if (bytes == 0 || !dst) return MX_OK;
+  hipMemcpyKind k = is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  MX_HIP_CHECK(hipMemcpyAsync(dst, src_dev, bytes, k, c->stream));
+  return MX_OK;
+}
+int sync(mx_ctx* c) {
+  MX_HIP_CHECK(hipStreamSynchronize(c->stream));
+  MX_HIP_CHECK(hipGetLastError());
+  return MX_OK;
+}
+
+size_t elem_bytes(int prec) { return prec == MX_PREC_C64 ? sizeof(float2) : sizeof(double2); }
+
+int ensure_host_pinned(mx_ctx* c, int n) {
+  if (n <= c->h_cap) return MX_OK;
+  if (c->h_conv) (void)hipHostFree(c->h_conv);
+  if (c->h_vec) (void)hipHostFree(c->h_vec);
+  if (c->h_kd) (void)hipHostFree(c->h_kd);
+  c->h_conv = nullptr; c->h_vec = nullptr; c->h_kd = nullptr; c->h_cap = 0;
+  MX_HIP_CHECK(hipHostMalloc((void**)&c->h_conv, n * sizeof(int32_t), hipHostMallocDefault));
+  MX_HIP_CHECK(hipHostMalloc((void**)&c->h_vec, n * sizeof(double), hipHostMallocDefault));
+  MX_HIP_CHECK(hipHostMalloc((void**)&c->h_kd, n * sizeof(int32_t), hipHostMallocDefault));
+  c->h_cap = n;
+  return MX_OK;
+}
+
+int ensure_workspace(mx_ctx* c, int nrhs, int m) {
+  const int64_t ne = c->topo.ne;
+  const size_t blk = (size_t)ne * nrhs;
+  if (nrhs > 256) return set_err(MX_EINVAL, "at most 256 right-hand sides per solve");
+  if (c->ws_nrhs != nrhs || c->ws_m != m) {
+    CK(c->V.alloc(blk * (m + 1)));
+    CK(c->Z.alloc(blk * m));
+    CK(c->x.alloc(blk));
+    CK(c->b.alloc(blk));
+    CK(c->r.alloc(blk));
+    CK(c->H.alloc((size_t)(m + 1) * m * nrhs));
+    CK(c->sn.alloc((size_t)m * nrhs));
+    CK(c->cs.alloc((size_t)m * nrhs));
+    CK(c->g.alloc((size_t)(m + 1) * nrhs));
+    CK(c->y.alloc((size_t)m * nrhs));
+    CK(c->h1.alloc((size_t)(m + 1) * nrhs));
+    CK(c->h2.alloc((size_t)(m + 1) * nrhs));
+    CK(c->dotpart.alloc((size_t)dot_blocks(ne) * 8 * nrhs));
+    CK(c->normpart.alloc((size_t)dot_blocks(ne) * nrhs));
+    CK(c->bnorm.alloc(nrhs));
+    CK(c->hn.alloc(nrhs));
+    CK(c->beta.alloc(nrhs));
+    CK(c->res.alloc(nrhs));
+    CK(c->conv.alloc(nrhs));
+    CK(c->kdone.alloc(nrhs));
+    c->ws_nrhs = nrhs;
+    c->ws_m = m;
+  }
+  if (c->have_dec) CK(c->xloc.alloc((size_t)c->dec.vec_off[c->dec.nsub] * nrhs * elem_bytes(c->precision)));
+  CK(c->flag.alloc(4));
+  CK(ensure_host_pinned(c, std::max(nrhs, 4)));
+  return MX_OK;
+}
+
+// z = M^{-1} v (one ORAS application), v and z device blocks [ne][nrhs]
+int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs) {
+  const Decomposition& D = c->dec;
+  const int64_t nrows = D.vec_off[D.nsub];
+  if (c->precision == MX_PREC_C64) {
+    float2* xl = (float2*)c->xloc.p;
+    launch_restrict<float2>(c->stream, nrows, c->rowsrc.p, v, xl, nrhs);
+    launch_trsm<float>(c->stream, (const float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, xl, D.nsub,
+                       nrhs);
+    launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, z);
+    for (int col = 0; col < D.ncolour; ++col) {
+      int64_t a = D.pcol_ptr[col], b = D.pcol_ptr[col + 1];
+      launch_prolong<float2>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xl, z, nrhs);
+    }
+  } else {
+    double2* xl = (double2*)c->xloc.p;
+    launch_restrict<double2>(c->stream, nrows, c->rowsrc.p, v, xl, nrhs);
+    launch_trsm<double>(c->stream, (const double2*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, xl, D.nsub,
+                        nrhs);
+    launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, z);
+    for (int col = 0; col < D.ncolour; ++col) {
+      int64_t a = D.pcol_ptr[col], b = D.pcol_ptr[col + 1];
+      launch_prolong<double2>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xl, z, nrhs);
+    }
+  }
+  MX_HIP_CHECK(hipGetLastError());
+  return MX_OK;
+}
+
+int spmm(mx_ctx* c, const double2* X, double2* Y, int nrhs) {
+  launch_spmm(c->stream, c->topo.ne, c->row_ptr.p, c->col.p, c->val.p, X, Y, nrhs);
+  MX_HIP_CHECK(hipGetLastError());
+  return MX_OK;
+}
+
+// Right-preconditioned pseudo-block FGMRES on b (device) -> x (device, ctx->x).
+int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info) {
+  const int m = c->ws_m;
+  const int64_t ne = c->topo.ne;
+  const int64_t blk = ne * (int64_t)nrhs;
+  hipStream_t s = c->stream;
+  auto t0 = std::chrono::steady_clock::now();
+  launch_norm(s, ne, nrhs, c->b.p, c->normpart.p, c->bnorm.p);
+  launch_fill_zero<double2>(s, blk, c->x.p);
+  MX_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, blk * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  std::vector<double> bn(nrhs), rr(nrhs);
+  MX_HIP_CHECK(hipMemcpyAsync(c->h_vec, c->bnorm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  CK(sync(c));
+  for (int j = 0; j < nrhs; ++j) bn[j] = c->h_vec[j];
+  std::vector<int32_t> iters(nrhs, 0);
+  std::vector<char> done(nrhs, 0);
+  int total = 0, cycles = 0;
+  int rc = MX_OK;
+  // relative residual of the current r
+  auto true_residual = [&]() -> int {
+    launch_norm(s, ne, nrhs, c->r.p, c->normpart.p, c->beta.p);
+    MX_HIP_CHECK(hipMemcpyAsync(c->h_vec, c->beta.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    CK(sync(c));
+    for (int j = 0; j < nrhs; ++j) rr[j] = bn[j] > 0 ? c->h_vec[j] / bn[j] : 0.0;
+    return MX_OK;
+  };
+  CK(true_residual());
+  for (;;) {
+    bool all = true;
+    for (int j = 0; j < nrhs; ++j) {
+      if (rr[j] <= rtol) done[j] = 1;
+      all = all && done[j];
+    }
+    if (all) break;
+    if (total >= c->maxit) {
+      rc = set_err(MX_ENOTCONV, "FGMRES reached maxit=" + std::to_string(c->maxit));
+      break;
+    }
+    // new cycle: V_0 = r / beta, g = beta e_1
+    launch_scale(s, ne, nrhs, c->r.p, c->beta.p, c->V.p);
+    hipLaunchKernelGGL(k_set_g0, dim3((unsigned)(((m + 1) * nrhs + 255) / 256)), dim3(256), 0, s, m, nrhs,
+                       c->beta.p, c->g.p);
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nrhs + 255) / 256)), dim3(256), 0, s, nrhs, c->conv.p);
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nrhs + 255) / 256)), dim3(256), 0, s, nrhs, c->kdone.p);
+    int ksteps = 0;
+    for (int k = 0; k < m; ++k) {
+      double2* vk = c->V.p + k * blk;
+      double2* zk = c->Z.p + k * blk;
+      double2* w = c->V.p + (k + 1) * blk;
+      CK(apply_precond(c, vk, zk, nrhs));
+      CK(spmm(c, zk, w, nrhs));
+      launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h1.p);
+      launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w);
+      launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h2.p);
+      launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h2.p, w);
+      launch_norm(s, ne, nrhs, w, c->normpart.p, c->hn.p);
+      launch_scale(s, ne, nrhs, w, c->hn.p, w);
+      launch_givens(s, k, m, nrhs, c->h1.p, c->h2.p, c->hn.p, c->H.p, c->cs.p, c->sn.p, c->g.p, c->bnorm.p, rtol,
+                    c->conv.p, c->kdone.p, c->res.p);
+      MX_HIP_CHECK(hipMemcpyAsync(c->h_conv, c->conv.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      CK(sync(c));
+      ksteps = k + 1;
+      ++total;
+      int nconv = 0;
+      for (int j = 0; j < nrhs; ++j) nconv += c->h_conv[j] != 0 || done[j];
+      if (nconv == nrhs || total >= c->maxit) break;
+    }
+    launch_lsq(s, ksteps, m, nrhs, c->H.p, c->g.p, c->conv.p, c->kdone.p, c->y.p);
+    launch_xupdate(s, ne, nrhs, c->Z.p, blk, c->y.p, c->kdone.p, c->x.p);
+    CK(spmm(c, c->x.p, c->r.p, nrhs));
+    launch_bminus(s, blk, c->b.p, c->r.p);
+    MX_HIP_CHECK(hipMemcpyAsync(c->h_kd, c->kdone.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CK(true_residual());
+    for (int j = 0; j < nrhs; ++j)
+      if (!done[j]) iters[j] += c->h_kd[j];
+    ++cycles;
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    int mx_ = 0;
+    for (int j = 0; j < nrhs; ++j) {
+      if (info->iters) info->iters[j] = iters[j];
+      if (info->relres) info->relres[j] = rr[j];
+      mx_ = std::max(mx_, iters[j]);
+    }
+    info->iters_max = mx_;
+    info->cycles = cycles;
+    info->t_iter = std::chrono::duration<double>(t1 - t0).count();
+  }
+  return rc;
+}
+
+int fill_pool(mx_ctx* c) {
+  const Topology& T = c->topo;
+  const size_t need = 36 * (size_t)T.nt + 9 * (size_t)T.nbf + (c->have_dec ? 9 * c->dec.if_tet.size() : 0);
+  CK(c->pool.alloc(need));
+  launch_element(c->stream, T.nt, c->ts.p, c->xyz.p, c->eps.p, c->eps_kind, c->k0 * c->k0, c->pool.p);
+  launch_face(c->stream, (int32_t)T.nbf, c->bf_tet.p, c->bf_lf.p, c->ts.p, c->xyz.p, c->eps.p, c->eps_kind, 0,
+              c->k0, c->kb, c->pool.p + 36 * (size_t)T.nt);
+  if (c->have_dec && !c->dec.if_tet.empty())
+    launch_face(c->stream, (int32_t)c->dec.if_tet.size(), c->if_tet.p, c->if_lf.p, c->ts.p, c->xyz.p, c->eps.p,
+                c->eps_kind, 1, c->k0, c->kb, c->pool.p + 36 * (size_t)T.nt + 9 * (size_t)T.nbf);
+  MX_HIP_CHECK(hipGetLastError());
+  c->pool_filled = need;
+  return MX_OK;
+}
+
+int build_sources(mx_ctx* c, const mx_sources* src, SourceSet& out) {
+  if (!src || src->n <= 0 || !src->pos || !src->moment) return set_err(MX_EINVAL, "empty source set");
+  if (out.same(src)) return MX_OK;
+  out.pos.assign(src->pos, src->pos + 3 * (size_t)src->n);
+  out.mom.assign((const double*)src->moment, (const double*)src->moment + 6 * (size_t)src->n);
+  out.ptr.assign(1, 0);
+  out.edge.clear();
+  out.val.clear();
+  std::vector<int32_t> e;
+  std::vector<double> v;
+  for (int j = 0; j < src->n; ++j) {
+    double pr[3], pi[3];
+    for (int d = 0; d < 3; ++d) {
+      pr[d] = src->moment[3 * j + d].re;
+      pi[d] = src->moment[3 * j + d].im;
+    }
+    if (!point_functional(c->topo, &src->pos[3 * (size_t)j], pr, pi, e, v)) {
+      out.pos.clear();
+      return set_err(MX_EINVAL, "source/receiver " + std::to_string(j) + " lies outside the mesh");
+    }
+    for (size_t k = 0; k < e.size(); ++k) {
+      out.edge.push_back(e[k]);
+      out.val.push_back(make_double2(v[2 * k], v[2 * k + 1]));
+    }
+    out.ptr.push_back((int64_t)out.edge.size());
+  }
+  return MX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mx_last_error(void) { return g_err.c_str(); }
+
+int mx_create(mx_ctx** out, int device) {
+  if (!out) return set_err(MX_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  MX_HIP_CHECK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return set_err(MX_EINVAL, "no such HIP device");
+  mx_ctx* c = new mx_ctx();
+  c->device = device;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipStreamCreate", __FILE__, __LINE__);
+  }
+  *out = c;
+  return MX_OK;
+}
+
+int mx_destroy(mx_ctx* c) {
+  if (!c) return MX_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->h_conv) (void)hipHostFree(c->h_conv);
+  if (c->h_vec) (void)hipHostFree(c->h_vec);
+  if (c->h_kd) (void)hipHostFree(c->h_kd);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return MX_OK;
+}
+
+int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind, double freq_hz, mx_c128 eps_b) {
+  if (!c || !eps) return set_err(MX_EINVAL, "NULL argument");
+  if (eps_kind != MX_EPS_P0 && eps_kind != MX_EPS_P1) return set_err(MX_EINVAL, "bad eps_kind");
+  if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return set_err(MX_EINVAL, "frequency must be positive");
+  if (!std::isfinite(eps_b.re) || !std::isfinite(eps_b.im)) return set_err(MX_EINVAL, "non-finite eps_b");
+  CK(use_device(c));
+  if (mesh) {
+    Topology T;
+    std::string err = build_topology(mesh->nv, mesh->nt, mesh->xyz, mesh->tet, T);
+    if (!err.empty()) return set_err(MX_EINVAL, err);
+    c->topo = std::move(T);
+    c->have_mesh = true;
+    c->have_dec = false;
+    c->local_ready = c->factored = false;
+    c->tx = SourceSet();
+    c->rx = SourceSet();
+    c->ws_nrhs = 0;
+    const Topology& t = c->topo;
+    CK(c->xyz.upload(t.xyz, c->stream));
+    CK(c->ts.upload(t.ts, c->stream));
+    CK(c->col.upload(t.col, c->stream));
+    CK(c->row_ptr.upload(t.row_ptr, c->stream));
+    CK(c->cptr.upload(t.cptr, c->stream));
+    CK(c->csrc.upload(t.csrc, c->stream));
+    CK(c->bf_tet.upload(t.bf_tet, c->stream));
+    CK(c->bf_lf.upload(t.bf_lf, c->stream));
+    CK(c->val.alloc(t.nnz));
+  } else if (!c->have_mesh) {
+    return set_err(MX_ESTATE, "mesh is NULL and no mesh was given before");
+  }
+  const Topology& T = c->topo;
+  const int64_t ne_eps = eps_kind == MX_EPS_P0 ? T.nt : T.nv;
+  CK(c->eps.alloc(ne_eps));
+  CK(copy_in(c, c->eps.p, eps, ne_eps * sizeof(double2)));
+  CK(c->flag.alloc(4));
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, 1, c->flag.p);
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((ne_eps + 255) / 256)), dim3(256), 0, c->stream, ne_eps,
+                     c->eps.p, c->flag.p);
+  int32_t hflag = 0;
+  MX_HIP_CHECK(hipMemcpyAsync(&hflag, c->flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  CK(sync(c));
+  if (hflag) return set_err(MX_EINVAL, "non-finite permittivity");
+  c->eps_kind = eps_kind;
+  c->freq = freq_hz;
+  c->k0 = 2.0 * M_PI * freq_hz / C0;
+  c->omega_mu0 = 2.0 * M_PI * freq_hz * MU0;
+  double2 sq = csqrt_host(make_double2(eps_b.re, eps_b.im));
+  c->kb = make_double2(c->k0 * sq.x, c->k0 * sq.y);
+  CK(fill_pool(c));
+  launch_gather_csr(c->stream, T.nnz, c->cptr.p, c->csrc.p, c->pool.p, c->val.p);
+  MX_HIP_CHECK(hipGetLastError());
+  CK(sync(c));
+  c->assembled = true;
+  c->local_ready = c->factored = false;
+  return MX_OK;
+}
+
+int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_opts* opts) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  if (!c->assembled) return set_err(MX_ESTATE, "mx_assemble must come first");
+  mx_schwarz_opts o = {MX_PREC_C128, 30, 2000, 1};
+  if (opts) o = *opts;
+  if (o.precision != MX_PREC_C128 && o.precision != MX_PREC_C64) return set_err(MX_EINVAL, "bad precision");
+  CK(use_device(c));
+  c->restart = o.restart > 0 ? o.restart : 30;
+  c->maxit = o.maxit > 0 ? o.maxit : 2000;
+  if (!c->have_dec || c->dec.nsub != nsub || c->dec.overlap != overlap) {
+    Decomposition D;
+    std::string err = build_decomposition(c->topo, nsub, overlap, 64, D);
+    if (!err.empty()) return set_err(MX_EINVAL, err);
+    for (int i = 0; i < nsub; ++i)
+      if (D.Npad[i] > 8192)
+        return set_err(MX_EINVAL, "subdomain " + std::to_string(i) + " has more than 8192 unknowns; use more subdomains");
+    c->dec = std::move(D);
+    const Decomposition& d = c->dec;
+    CK(c->dofs.upload(d.dofs, c->stream));
+    CK(c->dof_ptr.upload(d.dof_ptr, c->stream));
+    CK(c->Npad.upload(d.Npad, c->stream));
+    CK(c->mat_off.upload(d.mat_off, c->stream));
+    CK(c->vec_off.upload(d.vec_off, c->stream));
+    CK(c->if_tet.upload(d.if_tet, c->stream));
+    CK(c->if_lf.upload(d.if_lf, c->stream));
+    CK(c->ldest.upload(d.ldest, c->stream));
+    CK(c->lptr.upload(d.lptr, c->stream));
+    CK(c->lsrc.upload(d.lsrc, c->stream));
+    CK(c->p_edge.upload(d.p_edge, c->stream));
+    CK(c->p_row.upload(d.p_row, c->stream));
+    CK(c->p_w.upload(d.p_w, c->stream));
+    std::vector<int32_t> ord(nsub);
+    for (int i = 0; i < nsub; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d.Npad[a] > d.Npad[b]; });
+    c->Nsorted.resize(nsub);
+    for (int i = 0; i < nsub; ++i) c->Nsorted[i] = d.Npad[ord[i]];
+    CK(c->order.upload(ord, c->stream));
+    CK(c->piv.alloc(d.vec_off[nsub]));
+    CK(c->perm.alloc(d.vec_off[nsub]));
+    CK(c->rowsrc.alloc(d.vec_off[nsub]));
+    CK(c->status.alloc(nsub));
+    CK(c->pswap.alloc((size_t)nsub * (2 * lu_max_swap_rows() + 1)));
+    c->have_dec = true;
+    c->ws_nrhs = 0;
+  }
+  const Decomposition& D = c->dec;
+  c->local_ready = c->factored = false;
+  CK(fill_pool(c));  // interface-face blocks for this permittivity
+  const size_t nent = (size_t)D.mat_off[D.nsub];
+  if (c->precision != o.precision) c->factors.release();
+  c->precision = o.precision;
+  CK(c->factors.alloc(nent * elem_bytes(o.precision)));
+  const int64_t nloc = (int64_t)D.ldest.size();
+  if (o.precision == MX_PREC_C64) {
+    float2* F = (float2*)c->factors.p;
+    launch_fill_zero<float2>(c->stream, nent, F);
+    launch_gather_dense<float2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
+    launch_pad_identity<float2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
+  } else {
+    double2* F = (double2*)c->factors.p;
+    launch_fill_zero<double2>(c->stream, nent, F);
+    launch_gather_dense<double2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
+    launch_pad_identity<double2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
+  }
+  MX_HIP_CHECK(hipGetLastError());
+  c->local_ready = true;
+  if (o.factor) {
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((D.nsub + 255) / 256)), dim3(256), 0, c->stream, D.nsub,
+                       c->status.p);
+    if (o.precision == MX_PREC_C64)
+      launch_lu<float>(c->stream, (float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
+                       c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted);
+    else
+      launch_lu<double>(c->stream, (double2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
+                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted);
+    launch_perm(c->stream, D.nsub, c->Npad.p, c->vec_off.p, c->dof_ptr.p, c->dofs.p, c->piv.p, c->perm.p,
+                c->rowsrc.p);
+    MX_HIP_CHECK(hipGetLastError());
+    std::vector<int32_t> st(D.nsub);
+    MX_HIP_CHECK(hipMemcpyAsync(st.data(), c->status.p, D.nsub * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    CK(sync(c));
+    for (int i = 0; i < D.nsub; ++i)
+      if (st[i] != 0)
+        return set_err(MX_EPIVOT, "zero pivot in subdomain " + std::to_string(i) + " at column " +
+                                      std::to_string(st[i] - 1));
+    c->factored = true;
+  }
+  CK(sync(c));
+  return MX_OK;
+}
+
+int mx_solve_rhs(mx_ctx* c, const mx_c128* b, int32_t nrhs, double rtol, mx_c128* x, mx_solve_info* info) {
+  if (!c || !b || nrhs <= 0) return set_err(MX_EINVAL, "bad arguments");
+  if (!(rtol > 0)) return set_err(MX_EINVAL, "rtol must be positive");
+  if (!c->factored) return set_err(MX_ESTATE, "mx_setup_schwarz (with factor=1) must come first");
+  CK(use_device(c));
+  CK(ensure_workspace(c, nrhs, c->restart));
+  const size_t bytes = (size_t)c->topo.ne * nrhs * sizeof(double2);
+  CK(copy_in(c, c->b.p, b, bytes));
+  int rc = fgmres(c, nrhs, rtol, info);
+  if (rc != MX_OK && rc != MX_ENOTCONV) return rc;
+  CK(copy_out(c, x, c->x.p, bytes));
+  CK(sync(c));
+  if (rc == MX_ENOTCONV) g_err = "FGMRES reached maxit";
+  return rc;
+}
+
+int mx_solve(mx_ctx* c, const mx_sources* tx, const mx_sources* rx, double rtol, mx_c128* E, mx_c128* S,
+             mx_solve_info* info) {
+  if (!c || !tx) return set_err(MX_EINVAL, "bad arguments");
+  if (!(rtol > 0)) return set_err(MX_EINVAL, "rtol must be positive");
+  if (!c->factored) return set_err(MX_ESTATE, "mx_setup_schwarz (with factor=1) must come first");
+  CK(use_device(c));
+  const int ntx = tx->n;
+  if (!c->tx.same(tx)) {
+    CK(build_sources(c, tx, c->tx));
+    std::vector<int32_t> colv(c->tx.edge.size());
+    for (int j = 0; j < ntx; ++j)
+      for (int64_t k = c->tx.ptr[j]; k < c->tx.ptr[j + 1]; ++k) colv[k] = j;
+    CK(c->s_edge.upload(c->tx.edge, c->stream));
+    CK(c->s_col.upload(colv, c->stream));
+    CK(c->s_val.upload(c->tx.val, c->stream));
+  }
+  const mx_sources* rxs = rx ? rx : tx;
+  if (!c->rx.same(rxs)) {
+    CK(build_sources(c, rxs, c->rx));
+    CK(c->r_edge.upload(c->rx.edge, c->stream));
+    CK(c->r_val.upload(c->rx.val, c->stream));
+    CK(c->r_ptr.upload(c->rx.ptr, c->stream));
+  }
+  CK(ensure_workspace(c, ntx, c->restart));
+  const int64_t blk = c->topo.ne * (int64_t)ntx;
+  launch_fill_zero<double2>(c->stream, blk, c->b.p);
+  launch_scatter_rhs(c->stream, (int64_t)c->tx.edge.size(), c->s_edge.p, c->s_col.p, c->s_val.p,
+                     make_double2(0.0, -c->omega_mu0), ntx, c->b.p);
+  MX_HIP_CHECK(hipGetLastError());
+  int rc = fgmres(c, ntx, rtol, info);
+  if (rc != MX_OK && rc != MX_ENOTCONV) return rc;
+  const int nrx = rxs->n;
+  if (S) {
+    CK(c->S.alloc((size_t)nrx * ntx));
+    launch_receivers(c->stream, nrx, ntx, c->r_ptr.p, c->r_edge.p, c->r_val.p, c->x.p, c->S.p);
+    MX_HIP_CHECK(hipGetLastError());
+    CK(copy_out(c, S, c->S.p, (size_t)nrx * ntx * sizeof(double2)));
+  }
+  if (E) CK(copy_out(c, E, c->x.p, blk * sizeof(double2)));
+  CK(sync(c));
+  if (rc == MX_ENOTCONV) g_err = "FGMRES reached maxit";
+  return rc;
+}
+
+int mx_apply_operator(mx_ctx* c, const mx_c128* X, mx_c128* Y, int32_t nrhs) {
+  if (!c || !X || !Y || nrhs <= 0) return set_err(MX_EINVAL, "bad arguments");
+  if (!c->assembled) return set_err(MX_ESTATE, "mx_assemble must come first");
+  CK(use_device(c));
+  const size_t bytes = (size_t)c->topo.ne * nrhs * sizeof(double2);
+  DBuf<double2> xin, yout;
+  CK(xin.alloc((size_t)c->topo.ne * nrhs));
+  CK(yout.alloc((size_t)c->topo.ne * nrhs));
+  CK(copy_in(c, xin.p, X, bytes));
+  CK(spmm(c, xin.p, yout.p, nrhs));
+  CK(copy_out(c, Y, yout.p, bytes));
+  CK(sync(c));
+  return MX_OK;
+}
+
+int mx_apply_preconditioner(mx_ctx* c, const mx_c128* X, mx_c128* Zo, int32_t nrhs) {
+  if (!c || !X || !Zo || nrhs <= 0) return set_err(MX_EINVAL, "bad arguments");
+  if (!c->factored) return set_err(MX_ESTATE, "mx_setup_schwarz (with factor=1) must come first");
+  if (nrhs > 256) return set_err(MX_EINVAL, "at most 256 right-hand sides");
+  CK(use_device(c));
+  const size_t bytes = (size_t)c->topo.ne * nrhs * sizeof(double2);
+  DBuf<double2> xin, zout;
+  CK(xin.alloc((size_t)c->topo.ne * nrhs));
+  CK(zout.alloc((size_t)c->topo.ne * nrhs));
+  CK(c->xloc.alloc((size_t)c->dec.vec_off[c->dec.nsub] * nrhs * elem_bytes(c->precision)));
+  CK(copy_in(c, xin.p, X, bytes));
+  CK(apply_precond(c, xin.p, zout.p, nrhs));
+  CK(copy_out(c, Zo, zout.p, bytes));
+  CK(sync(c));
+  return MX_OK;
+}
+
+int mx_get_sizes(mx_ctx* c, mx_sizes* o) {
+  if (!c || !o) return set_err(MX_EINVAL, "NULL argument");
+  std::memset(o, 0, sizeof(*o));
+  if (c->have_mesh) {
+    o->nv = c->topo.nv;
+    o->nt = c->topo.nt;
+    o->ne = c->topo.ne;
+    o->nnz = c->topo.nnz;
+    o->nbface = c->topo.nbf;
+  }
+  if (c->have_dec) {
+    o->nsub = c->dec.nsub;
+    o->overlap = c->dec.overlap;
+    o->ncolour = c->dec.ncolour;
+    o->sum_ni = c->dec.dof_ptr[c->dec.nsub];
+    o->sum_Ni2 = c->dec.mat_off[c->dec.nsub];
+    o->nb = c->dec.nb;
+  }
+  return MX_OK;
+}
+
+int mx_get_topology(mx_ctx* c, int32_t* edges, int32_t* t2e, int64_t* row_ptr, int32_t* col) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  if (!c->have_mesh) return set_err(MX_ESTATE, "no mesh");
+  const Topology& T = c->topo;
+  if (edges) std::memcpy(edges, T.edges.data(), T.edges.size() * sizeof(int32_t));
+  if (t2e) std::memcpy(t2e, T.t2e.data(), T.t2e.size() * sizeof(int32_t));
+  if (row_ptr) std::memcpy(row_ptr, T.row_ptr.data(), T.row_ptr.size() * sizeof(int64_t));
+  if (col) std::memcpy(col, T.col.data(), T.col.size() * sizeof(int32_t));
+  return MX_OK;
+}
+
+int mx_get_matrix_values(mx_ctx* c, mx_c128* v) {
+  if (!c || !v) return set_err(MX_EINVAL, "NULL argument");
+  if (!c->assembled) return set_err(MX_ESTATE, "not assembled");
+  CK(use_device(c));
+  MX_HIP_CHECK(hipMemcpyAsync(v, c->val.p, c->topo.nnz * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+int mx_get_partition(mx_ctx* c, int32_t* part, int64_t* dof_ptr, int32_t* dofs, int32_t* pu_w, int32_t* colour) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  if (!c->have_dec) return set_err(MX_ESTATE, "no decomposition");
+  const Decomposition& D = c->dec;
+  if (part) std::memcpy(part, D.part.data(), D.part.size() * sizeof(int32_t));
+  if (dof_ptr) std::memcpy(dof_ptr, D.dof_ptr.data(), D.dof_ptr.size() * sizeof(int64_t));
+  if (dofs) std::memcpy(dofs, D.dofs.data(), D.dofs.size() * sizeof(int32_t));
+  if (pu_w) std::memcpy(pu_w, D.w.data(), D.w.size() * sizeof(int32_t));
+  if (colour) std::memcpy(colour, D.colour.data(), D.colour.size() * sizeof(int32_t));
+  return MX_OK;
+}
+
+int mx_get_local_matrix(mx_ctx* c, int32_t i, mx_c128* B) {
+  if (!c || !B) return set_err(MX_EINVAL, "NULL argument");
+  if (!c->have_dec || !c->local_ready || c->factored)
+    return set_err(MX_ESTATE, "needs mx_setup_schwarz with factor = 0");
+  if (i < 0 || i >= c->dec.nsub) return set_err(MX_EINVAL, "subdomain index out of range");
+  CK(use_device(c));
+  const Decomposition& D = c->dec;
+  const int n = (int)(D.dof_ptr[i + 1] - D.dof_ptr[i]);
+  const int N = D.Npad[i];
+  DBuf<double2> tmp;
+  CK(tmp.alloc((size_t)n * n));
+  const unsigned g = (unsigned)(((int64_t)n * n + 255) / 256);
+  if (c->precision == MX_PREC_C64)
+    hipLaunchKernelGGL(k_extract_local<float2>, dim3(g), dim3(256), 0, c->stream, n, N,
+                       (const float2*)c->factors.p + D.mat_off[i], tmp.p);
+  else
+    hipLaunchKernelGGL(k_extract_local<double2>, dim3(g), dim3(256), 0, c->stream, n, N,
+                       (const double2*)c->factors.p + D.mat_off[i], tmp.p);
+  MX_HIP_CHECK(hipGetLastError());
+  MX_HIP_CHECK(hipMemcpyAsync(B, tmp.p, (size_t)n * n * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+int mx_point_functionals(mx_ctx* c, const mx_sources* pts, mx_c128* R) {
+  if (!c || !pts || !R) return set_err(MX_EINVAL, "NULL argument");
+  if (!c->have_mesh) return set_err(MX_ESTATE, "no mesh");
+  SourceSet s;
+  CK(build_sources(c, pts, s));
+  const int n = pts->n;
+  std::memset(R, 0, (size_t)c->topo.ne * n * sizeof(mx_c128));
+  for (int j = 0; j < n; ++j)
+    for (int64_t k = s.ptr[j]; k < s.ptr[j + 1]; ++k) {
+      R[(size_t)s.edge[k] * n + j].re = s.val[k].x;
+      R[(size_t)s.edge[k] * n + j].im = s.val[k].y;
+    }
+  return MX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Host-callable launchers of the gfx950 kernels (all enqueue on stream s).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <vector>
+
+namespace mx {
+
+template <typename R> struct cplx_t;
+template <typename R> using C_t = typename cplx_t<R>::type;
+
+// operator assembly
+void launch_element(hipStream_t s, int32_t nt, const int32_t* ts, const double* xyz, const double2* eps,
+                    int eps_kind, double k0sq, double2* out);
+void launch_face(hipStream_t s, int32_t n, const int32_t* ftet, const int32_t* flf, const int32_t* ts,
+                 const double* xyz, const double2* eps, int eps_kind, int per_tet_k, double k0, double2 kconst,
+                 double2* out);
+void launch_gather_csr(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* src, const double2* pool,
+                       double2* out);
+template <typename C>
+void launch_gather_dense(hipStream_t s, int64_t n, const int64_t* dest, const int64_t* ptr, const int32_t* src,
+                         const double2* pool, C* out);
+template <typename C> void launch_fill_zero(hipStream_t s, int64_t n, C* out);
+template <typename C>
+void launch_pad_identity(hipStream_t s, int32_t nsub, const int64_t* dof_ptr, const int32_t* Npad,
+                         const int64_t* mat_off, C* A);
+
+// operator application and Schwarz transfer
+void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t* col, const double2* val,
+                 const double2* X, double2* Y, int nrhs);
+template <typename C>
+void launch_restrict(hipStream_t s, int64_t nrows, const int32_t* rowsrc, const double2* v, C* xloc, int nrhs);
+template <typename C>
+void launch_prolong(hipStream_t s, int64_t n, const int32_t* edge, const int64_t* row, const double* w,
+                    const C* zloc, double2* z, int nrhs);
+
+// dense subdomain factorisation and solves
+template <typename R>
+void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
+               int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
+               const std::vector<int32_t>& Nsorted);
+void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int64_t* dof_ptr,
+                 const int32_t* dofs, const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc);
+template <typename R>
+void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
+                 const int64_t* vec_off, C_t<R>* xloc, int nsub, int nrhs);
+int lu_max_swap_rows();
+
+// Krylov
+int dot_blocks(int64_t nrows);
+void launch_dot(hipStream_t s, int64_t nrows, int nrhs, const double2* V, int64_t vstride, int nvec,
+                const double2* w, double2* part, double2* out);
+void launch_update(hipStream_t s, int64_t nrows, int nrhs, const double2* V, int64_t vstride, int nv,
+                   const double2* h, double2* w);
+void launch_norm(hipStream_t s, int64_t nrows, int nrhs, const double2* w, double* part, double* out);
+void launch_scale(hipStream_t s, int64_t nrows, int nrhs, const double2* src, const double* nrm, double2* dst);
+void launch_bminus(hipStream_t s, int64_t n, const double2* b, double2* r);
+void launch_givens(hipStream_t s, int k, int m, int nrhs, const double2* h1, const double2* h2, const double* hn,
+                   double2* H, double* cs, double2* sn, double2* g, const double* bnorm, double rtol, int32_t* conv,
+                   int32_t* kdone, double* res);
+void launch_lsq(hipStream_t s, int ksteps, int m, int nrhs, const double2* H, const double2* g, const int32_t* conv,
+                int32_t* kdone, double2* y);
+void launch_xupdate(hipStream_t s, int64_t nrows, int nrhs, const double2* Z, int64_t vstride, const double2* y,
+                    const int32_t* kd, double2* x);
+void launch_scatter_rhs(hipStream_t s, int64_t n, const int32_t* edge, const int32_t* col, const double2* val,
+                        double2 scale, int nrhs, double2* B);
+void launch_receivers(hipStream_t s, int nrx, int nrhs, const int64_t* ptr, const int32_t* edge, const double2* val,
+                      const double2* U, double2* S);
+
+}  // namespace mx
