@@ -107,9 +107,41 @@ typedef struct {
   int32_t nb;          /* dense block size; N_i = n_i rounded up to nb */
 } mx_sizes;
 
+/* Kernel classes timed by mx_set_profiling / mx_get_kernel_times. */
+enum {
+  MX_K_LU_PANEL = 0,    /* panel factorisation (one launch per 64 columns)   */
+  MX_K_LU_ROWPANEL = 1, /* row interchanges + U12 block row                  */
+  MX_K_LU_UPDATE = 2,   /* trailing-matrix update A22 -= L21 U12 (MFMA)       */
+  MX_K_LU_INV = 3,      /* diagonal-block inversion + permutation            */
+  MX_K_TRSM_LOWER = 4,  /* batched multi-RHS forward solve (MFMA)            */
+  MX_K_TRSM_UPPER = 5,  /* batched multi-RHS backward solve (MFMA)           */
+  MX_K_SPMM = 6,        /* complex CSR block SpMM                           */
+  MX_K_RESTRICT = 7,    /* restriction R_i (gather + cast)                  */
+  MX_K_PROLONG = 8,     /* prolongation sum_i R_i^T D_i (all colours)         */
+  MX_K_CGS = 9,         /* classical Gram-Schmidt x2 + norm + Givens, per step */
+  MX_K_ASSEMBLE = 10,   /* element/face blocks + CSR gather                  */
+  MX_K_LOCAL = 11,      /* dense subdomain assembly (zero fill + gather)     */
+  MX_K_NCLASS = 16
+};
+typedef struct {
+  double ms[MX_K_NCLASS];       /* summed device time per class (milliseconds) */
+  int64_t launches[MX_K_NCLASS]; /* number of timed intervals per class         */
+} mx_kernel_times;
+
 /* Create a context on HIP device `device` (own stream). */
 int mx_create(mx_ctx** out, int device);
 int mx_destroy(mx_ctx* ctx);
+
+/* Run all further work of the context on the caller's HIP stream
+ * (hipStream_t passed as void*; NULL returns to the context's own stream).
+ * The caller keeps the stream alive while the context uses it. */
+int mx_set_stream(mx_ctx* ctx, void* hip_stream);
+
+/* enable != 0: bracket every launch of the classes above with HIP events on
+ * the context's stream (small overhead) and reset the totals; 0: stop. */
+int mx_set_profiling(mx_ctx* ctx, int enable);
+/* Totals since profiling was enabled (synchronises the stream). */
+int mx_get_kernel_times(mx_ctx* ctx, mx_kernel_times* out);
 
 /* Operator assembly (eq. (2)): A = sum_T (K_T - k0^2 eps M_T) + j k_b sum_F B_F
  * over the tetrahedra T and the outer boundary faces F, k_b = k0 sqrt(eps_b).

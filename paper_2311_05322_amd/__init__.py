@@ -22,7 +22,10 @@ MX_PREC_C128, MX_PREC_C64 = 0, 1
 EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_solve", "mx_solve_rhs",
            "mx_apply_operator", "mx_apply_preconditioner", "mx_get_sizes", "mx_get_topology",
            "mx_get_matrix_values", "mx_get_partition", "mx_get_local_matrix", "mx_point_functionals",
-           "mx_last_error"]
+           "mx_set_stream", "mx_set_profiling", "mx_get_kernel_times", "mx_last_error"]
+
+KERNEL_CLASSES = ["lu_panel", "lu_rowpanel", "lu_update", "lu_inv", "trsm_lower", "trsm_upper", "spmm",
+                  "restrict", "prolong", "cgs", "assemble", "local"]
 
 
 class MxError(RuntimeError):
@@ -58,6 +61,10 @@ class Sizes(ct.Structure):
                 ("sum_ni", ct.c_int64), ("sum_Ni2", ct.c_int64), ("nb", ct.c_int32)]
 
 
+class KernelTimes(ct.Structure):
+    _fields_ = [("ms", ct.c_double * 16), ("launches", ct.c_int64 * 16)]
+
+
 _lib = None
 
 
@@ -84,6 +91,9 @@ def lib():
             "mx_get_partition": [vp, vp, vp, vp, vp, vp],
             "mx_get_local_matrix": [vp, i32, vp],
             "mx_point_functionals": [vp, ct.POINTER(Sources), vp],
+            "mx_set_stream": [vp, vp],
+            "mx_set_profiling": [vp, ct.c_int],
+            "mx_get_kernel_times": [vp, ct.POINTER(KernelTimes)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -150,6 +160,20 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    def set_stream(self, stream):
+        """Run on a caller HIP stream (integer handle, e.g. torch's
+        Stream.cuda_stream); None returns to the context's own stream."""
+        _check(lib().mx_set_stream(self._h, ct.c_void_p(stream) if stream else None))
+
+    def set_profiling(self, enable=True):
+        _check(lib().mx_set_profiling(self._h, 1 if enable else 0))
+
+    def kernel_times(self):
+        """{class: (milliseconds, launches)} since profiling was enabled."""
+        k = KernelTimes()
+        _check(lib().mx_get_kernel_times(self._h, ct.byref(k)))
+        return {name: (k.ms[i], int(k.launches[i])) for i, name in enumerate(KERNEL_CLASSES)}
 
     # -- operator ------------------------------------------------------------
     def assemble(self, xyz, tet, eps, eps_kind, freq, eps_b, reuse_mesh=False):

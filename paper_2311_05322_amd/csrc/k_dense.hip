@@ -611,16 +611,22 @@ inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) /
 
 }  // namespace
 
+#define MX_TB(cls) \
+  if (tm) tm->begin(cls)
+#define MX_TE(cls) \
+  if (tm) tm->end(cls)
+
 template <typename R>
 void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
                int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
-               const std::vector<int32_t>& Nsorted) {
+               const std::vector<int32_t>& Nsorted, KTimer* tm) {
   if (Nsorted.empty()) return;
   const int Nmax = Nsorted[0];
   for (int k0 = 0; k0 < Nmax; k0 += NB) {
     int nact = 0;
     while (nact < (int)Nsorted.size() && Nsorted[nact] > k0) ++nact;
     const int m = Nmax - k0;
+    MX_TB(K_LU_PANEL);
     if (m <= PT * 1)
       hipLaunchKernelGGL((k_lu_panel<R, 1>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
                          status, pswap, k0);
@@ -633,19 +639,27 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
     else
       hipLaunchKernelGGL((k_lu_panel<R, 8>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
                          status, pswap, k0);
+    MX_TE(K_LU_PANEL);
+    MX_TB(K_LU_ROWPANEL);
     hipLaunchKernelGGL((k_lu_rowpanel<R>), dim3(ceil_div(Nmax, NB), nact), dim3(256), 0, st, pool, mat_off, Npad,
                        order, pswap, k0);
+    MX_TE(K_LU_ROWPANEL);
     const int nt = (Nmax - k0 - NB) / NB;
-    if (nt > 0)
+    if (nt > 0) {
+      MX_TB(K_LU_UPDATE);
       hipLaunchKernelGGL((k_lu_update<R>), dim3(nt, nt, nact), dim3(256), 0, st, pool, mat_off, Npad, order, k0);
+      MX_TE(K_LU_UPDATE);
+    }
   }
+  MX_TB(K_LU_INV);
   hipLaunchKernelGGL((k_inv_upper<R>), dim3(ceil_div(Nmax, NB), (unsigned)Nsorted.size()), dim3(64), 0, st, pool,
                      mat_off, Npad, order);
+  MX_TE(K_LU_INV);
 }
 template void launch_lu<float>(hipStream_t, float2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
-                               const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&);
+                               const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, KTimer*);
 template void launch_lu<double>(hipStream_t, double2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
-                                const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&);
+                                const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, KTimer*);
 
 void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int64_t* dof_ptr,
                  const int32_t* dofs, const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc) {
@@ -656,16 +670,20 @@ void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_
 
 template <typename R>
 void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
-                 const int64_t* vec_off, C_t<R>* xloc, int nsub, int nrhs) {
+                 const int64_t* vec_off, C_t<R>* xloc, int nsub, int nrhs, KTimer* tm) {
   if (nsub <= 0 || nrhs <= 0) return;
   dim3 grid(nsub, ceil_div(nrhs, RC));
+  MX_TB(K_TRSM_LOWER);
   hipLaunchKernelGGL((k_trsm<R, true>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, xloc, nrhs);
+  MX_TE(K_TRSM_LOWER);
+  MX_TB(K_TRSM_UPPER);
   hipLaunchKernelGGL((k_trsm<R, false>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, xloc, nrhs);
+  MX_TE(K_TRSM_UPPER);
 }
 template void launch_trsm<float>(hipStream_t, const float2*, const int64_t*, const int32_t*, const int64_t*, float2*,
-                                 int, int);
+                                 int, int, KTimer*);
 template void launch_trsm<double>(hipStream_t, const double2*, const int64_t*, const int32_t*, const int64_t*,
-                                  double2*, int, int);
+                                  double2*, int, int, KTimer*);
 
 int lu_max_swap_rows() { return MAXSW; }
 

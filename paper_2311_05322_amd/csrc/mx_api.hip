@@ -118,6 +118,65 @@ struct SourceSet {
   }
 };
 
+// HIP-event bracketing of kernel launches, per kernel class.
+struct Profiler : KTimer {
+  hipStream_t* stream = nullptr;
+  bool on = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> open, done;
+  std::vector<hipEvent_t> pool;
+  double ms[K_NCLASS] = {0};
+  int64_t n[K_NCLASS] = {0};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(int cls) override {
+    if (!on) return;
+    hipEvent_t a = get();
+    (void)hipEventRecord(a, *stream);
+    open.push_back({cls, {a, nullptr}});
+  }
+  void end(int cls) override {
+    if (!on) return;
+    for (size_t i = open.size(); i-- > 0;)
+      if (open[i].first == cls) {
+        hipEvent_t b = get();
+        (void)hipEventRecord(b, *stream);
+        open[i].second.second = b;
+        done.push_back(open[i]);
+        open.erase(open.begin() + i);
+        break;
+      }
+    if (done.size() > 4096) resolve();
+  }
+  void resolve() {
+    for (auto& d : done) {
+      float t = 0;
+      (void)hipEventSynchronize(d.second.second);
+      (void)hipEventElapsedTime(&t, d.second.first, d.second.second);
+      ms[d.first] += t;
+      n[d.first] += 1;
+      pool.push_back(d.second.first);
+      pool.push_back(d.second.second);
+    }
+    done.clear();
+  }
+  void reset() {
+    resolve();
+    for (int i = 0; i < K_NCLASS; ++i) { ms[i] = 0; n[i] = 0; }
+  }
+  ~Profiler() {
+    for (auto& d : done) { pool.push_back(d.second.first); pool.push_back(d.second.second); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 }  // namespace mx
 
 using namespace mx;
@@ -125,6 +184,8 @@ using namespace mx;
 struct mx_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  Profiler prof;
   // mesh
   Topology topo;
   bool have_mesh = false;
@@ -248,36 +309,39 @@ int ensure_workspace(mx_ctx* c, int nrhs, int m) {
 }
 
 // z = M^{-1} v (one ORAS application), v and z device blocks [ne][nrhs]
-int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs) {
+template <typename R>
+void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs) {
+  typedef C_t<R> C;
   const Decomposition& D = c->dec;
   const int64_t nrows = D.vec_off[D.nsub];
-  if (c->precision == MX_PREC_C64) {
-    float2* xl = (float2*)c->xloc.p;
-    launch_restrict<float2>(c->stream, nrows, c->rowsrc.p, v, xl, nrhs);
-    launch_trsm<float>(c->stream, (const float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, xl, D.nsub,
-                       nrhs);
-    launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, z);
-    for (int col = 0; col < D.ncolour; ++col) {
-      int64_t a = D.pcol_ptr[col], b = D.pcol_ptr[col + 1];
-      launch_prolong<float2>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xl, z, nrhs);
-    }
-  } else {
-    double2* xl = (double2*)c->xloc.p;
-    launch_restrict<double2>(c->stream, nrows, c->rowsrc.p, v, xl, nrhs);
-    launch_trsm<double>(c->stream, (const double2*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, xl, D.nsub,
-                        nrhs);
-    launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, z);
-    for (int col = 0; col < D.ncolour; ++col) {
-      int64_t a = D.pcol_ptr[col], b = D.pcol_ptr[col + 1];
-      launch_prolong<double2>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xl, z, nrhs);
-    }
+  C* xl = (C*)c->xloc.p;
+  c->prof.begin(K_RESTRICT);
+  launch_restrict<C>(c->stream, nrows, c->rowsrc.p, v, xl, nrhs);
+  c->prof.end(K_RESTRICT);
+  launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, xl, D.nsub, nrhs,
+                 &c->prof);
+  c->prof.begin(K_PROLONG);
+  launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, z);
+  for (int col = 0; col < D.ncolour; ++col) {
+    int64_t a = D.pcol_ptr[col], b = D.pcol_ptr[col + 1];
+    launch_prolong<C>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xl, z, nrhs);
   }
+  c->prof.end(K_PROLONG);
+}
+
+int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs) {
+  if (c->precision == MX_PREC_C64)
+    apply_precond_t<float>(c, v, z, nrhs);
+  else
+    apply_precond_t<double>(c, v, z, nrhs);
   MX_HIP_CHECK(hipGetLastError());
   return MX_OK;
 }
 
 int spmm(mx_ctx* c, const double2* X, double2* Y, int nrhs) {
+  c->prof.begin(K_SPMM);
   launch_spmm(c->stream, c->topo.ne, c->row_ptr.p, c->col.p, c->val.p, X, Y, nrhs);
+  c->prof.end(K_SPMM);
   MX_HIP_CHECK(hipGetLastError());
   return MX_OK;
 }
@@ -333,6 +397,7 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info) {
       double2* w = c->V.p + (k + 1) * blk;
       CK(apply_precond(c, vk, zk, nrhs));
       CK(spmm(c, zk, w, nrhs));
+      c->prof.begin(K_CGS);
       launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h1.p);
       launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w);
       launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h2.p);
@@ -341,6 +406,7 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info) {
       launch_scale(s, ne, nrhs, w, c->hn.p, w);
       launch_givens(s, k, m, nrhs, c->h1.p, c->h2.p, c->hn.p, c->H.p, c->cs.p, c->sn.p, c->g.p, c->bnorm.p, rtol,
                     c->conv.p, c->kdone.p, c->res.p);
+      c->prof.end(K_CGS);
       MX_HIP_CHECK(hipMemcpyAsync(c->h_conv, c->conv.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       CK(sync(c));
       ksteps = k + 1;
@@ -433,7 +499,9 @@ int mx_create(mx_ctx** out, int device) {
   mx_ctx* c = new mx_ctx();
   c->device = device;
   hipError_t e = hipSetDevice(device);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
+  c->stream = c->own_stream;
+  c->prof.stream = &c->stream;
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "hipStreamCreate", __FILE__, __LINE__);
@@ -449,8 +517,39 @@ int mx_destroy(mx_ctx* c) {
   if (c->h_conv) (void)hipHostFree(c->h_conv);
   if (c->h_vec) (void)hipHostFree(c->h_vec);
   if (c->h_kd) (void)hipHostFree(c->h_kd);
-  if (c->stream) (void)hipStreamDestroy(c->stream);
+  c->prof.reset();
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
+  return MX_OK;
+}
+
+int mx_set_stream(mx_ctx* c, void* hip_stream) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  CK(use_device(c));
+  CK(sync(c));
+  c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
+  return MX_OK;
+}
+
+int mx_set_profiling(mx_ctx* c, int enable) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  CK(use_device(c));
+  CK(sync(c));
+  c->prof.reset();
+  c->prof.on = enable != 0;
+  return MX_OK;
+}
+
+int mx_get_kernel_times(mx_ctx* c, mx_kernel_times* out) {
+  if (!c || !out) return set_err(MX_EINVAL, "NULL argument");
+  CK(use_device(c));
+  CK(sync(c));
+  c->prof.resolve();
+  std::memset(out, 0, sizeof(*out));
+  for (int i = 0; i < K_NCLASS && i < MX_K_NCLASS; ++i) {
+    out->ms[i] = c->prof.ms[i];
+    out->launches[i] = c->prof.n[i];
+  }
   return MX_OK;
 }
 
@@ -502,8 +601,10 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
   c->omega_mu0 = 2.0 * M_PI * freq_hz * MU0;
   double2 sq = csqrt_host(make_double2(eps_b.re, eps_b.im));
   c->kb = make_double2(c->k0 * sq.x, c->k0 * sq.y);
+  c->prof.begin(K_ASSEMBLE);
   CK(fill_pool(c));
   launch_gather_csr(c->stream, T.nnz, c->cptr.p, c->csrc.p, c->pool.p, c->val.p);
+  c->prof.end(K_ASSEMBLE);
   MX_HIP_CHECK(hipGetLastError());
   CK(sync(c));
   c->assembled = true;
@@ -564,6 +665,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
   c->precision = o.precision;
   CK(c->factors.alloc(nent * elem_bytes(o.precision)));
   const int64_t nloc = (int64_t)D.ldest.size();
+  c->prof.begin(K_LOCAL);
   if (o.precision == MX_PREC_C64) {
     float2* F = (float2*)c->factors.p;
     launch_fill_zero<float2>(c->stream, nent, F);
@@ -575,6 +677,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     launch_gather_dense<double2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
     launch_pad_identity<double2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
   }
+  c->prof.end(K_LOCAL);
   MX_HIP_CHECK(hipGetLastError());
   c->local_ready = true;
   if (o.factor) {
@@ -582,12 +685,14 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
                        c->status.p);
     if (o.precision == MX_PREC_C64)
       launch_lu<float>(c->stream, (float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
-                       c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted);
+                       c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, &c->prof);
     else
       launch_lu<double>(c->stream, (double2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
-                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted);
+                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, &c->prof);
+    c->prof.begin(K_LU_INV);
     launch_perm(c->stream, D.nsub, c->Npad.p, c->vec_off.p, c->dof_ptr.p, c->dofs.p, c->piv.p, c->perm.p,
                 c->rowsrc.p);
+    c->prof.end(K_LU_INV);
     MX_HIP_CHECK(hipGetLastError());
     std::vector<int32_t> st(D.nsub);
     MX_HIP_CHECK(hipMemcpyAsync(st.data(), c->status.p, D.nsub * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));

@@ -9,6 +9,19 @@ namespace mx {
 template <typename R> struct cplx_t;
 template <typename R> using C_t = typename cplx_t<R>::type;
 
+// Kernel classes (same numbering as the MX_K_* enum of mx.h).
+enum KClass {
+  K_LU_PANEL = 0, K_LU_ROWPANEL = 1, K_LU_UPDATE = 2, K_LU_INV = 3, K_TRSM_LOWER = 4, K_TRSM_UPPER = 5,
+  K_SPMM = 6, K_RESTRICT = 7, K_PROLONG = 8, K_CGS = 9, K_ASSEMBLE = 10, K_LOCAL = 11, K_NCLASS = 16
+};
+
+// Optional launch bracketing used for per-kernel-class device timing.
+struct KTimer {
+  virtual void begin(int cls) = 0;
+  virtual void end(int cls) = 0;
+  virtual ~KTimer() {}
+};
+
 // operator assembly
 void launch_element(hipStream_t s, int32_t nt, const int32_t* ts, const double* xyz, const double2* eps,
                     int eps_kind, double k0sq, double2* out);
@@ -38,12 +51,12 @@ void launch_prolong(hipStream_t s, int64_t n, const int32_t* edge, const int64_t
 template <typename R>
 void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
                int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
-               const std::vector<int32_t>& Nsorted);
+               const std::vector<int32_t>& Nsorted, KTimer* tm);
 void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int64_t* dof_ptr,
                  const int32_t* dofs, const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc);
 template <typename R>
 void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
-                 const int64_t* vec_off, C_t<R>* xloc, int nsub, int nrhs);
+                 const int64_t* vec_off, C_t<R>* xloc, int nsub, int nrhs, KTimer* tm);
 int lu_max_swap_rows();
 
 // Krylov
