@@ -173,6 +173,24 @@ int mx_setup_schwarz(mx_ctx* ctx, int32_t nsub, int32_t overlap, const mx_schwar
 int mx_solve(mx_ctx* ctx, const mx_sources* tx, const mx_sources* rx, double rtol,
              mx_c128* E, mx_c128* S, mx_solve_info* info);
 
+/* Cost and adjoint-state gradient of the inverse problem (Sec. III-D, eq. (4)):
+ *   J = 1/2 sum_ij w_ij |S_ij - S_meas_ij|^2 + alpha/2 int |grad kappa|^2,
+ *   kappa = k0^2 eps, eps piecewise linear (MX_EPS_P1),
+ * for the transmitters and receivers of the immediately preceding mx_solve
+ * (same operator and factors).  The adjoint fields solve A lambda_j =
+ * sum_i w_ij conj(d_ij) r_i with the same preconditioner (A is complex
+ * symmetric), and
+ *   grad_n = dJ/dRe eps_n + j dJ/dIm eps_n
+ *          = conj(k0^2 sum_j lambda_j^T M_n u_j) + alpha k0^4 (K1 eps)_n,
+ * M_n = int lambda_n N_e . N_f, K1 the P1 stiffness matrix.
+ *   S_meas [nrx][ntx] host;  w [nrx][ntx] host weights (1/|S_empty|^2, 0 on
+ *   entries to ignore);  grad [nv] host or device;  J host;  info may be NULL
+ *   (adjoint iteration counts).
+ * Errors: MX_ESTATE without a preceding mx_solve, MX_EINVAL for per-tetrahedron
+ * permittivity or a negative alpha. */
+int mx_gradient(mx_ctx* ctx, const mx_c128* S_meas, const double* w, double alpha, mx_c128* grad, double* J,
+                mx_solve_info* info);
+
 /* Same solver on caller-supplied right-hand sides b [ne][nrhs] (host or
  * device); solution x [ne][nrhs] (host or device). */
 int mx_solve_rhs(mx_ctx* ctx, const mx_c128* b, int32_t nrhs, double rtol,

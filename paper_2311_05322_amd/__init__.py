@@ -22,7 +22,7 @@ MX_PREC_C128, MX_PREC_C64 = 0, 1
 EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_solve", "mx_solve_rhs",
            "mx_apply_operator", "mx_apply_preconditioner", "mx_get_sizes", "mx_get_topology",
            "mx_get_matrix_values", "mx_get_partition", "mx_get_local_matrix", "mx_point_functionals",
-           "mx_set_stream", "mx_set_profiling", "mx_get_kernel_times", "mx_last_error"]
+           "mx_set_stream", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_last_error"]
 
 KERNEL_CLASSES = ["lu_panel", "lu_rowpanel", "lu_update", "lu_inv", "trsm_lower", "trsm_upper", "spmm",
                   "restrict", "prolong", "cgs", "assemble", "local"]
@@ -94,6 +94,7 @@ def lib():
             "mx_set_stream": [vp, vp],
             "mx_set_profiling": [vp, ct.c_int],
             "mx_get_kernel_times": [vp, ct.POINTER(KernelTimes)],
+            "mx_gradient": [vp, vp, vp, dbl, vp, ct.POINTER(dbl), ct.POINTER(SolveInfo)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -220,6 +221,23 @@ class Context:
         _check(rc, allow=(MX_ENOTCONV,))
         return E, S, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
                       "t_iter": info.t_iter, "converged": rc == MX_OK}
+
+    def gradient(self, S_meas, w, alpha, grad=None):
+        """Cost J and complex gradient dJ/dRe eps + j dJ/dIm eps (per vertex)
+        for the transmitters/receivers of the last solve; returns (J, grad, info)."""
+        S_meas = np.ascontiguousarray(S_meas, dtype=np.complex128)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        if grad is None:
+            grad = np.zeros(self.sizes().nv, np.complex128)
+        ntx = S_meas.shape[1]
+        iters = np.zeros(ntx, dtype=np.int32)
+        relres = np.zeros(ntx, dtype=np.float64)
+        info = SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        J = ct.c_double(0.0)
+        rc = lib().mx_gradient(self._h, _ptr(S_meas), _ptr(w), float(alpha), _ptr(grad), ct.byref(J), ct.byref(info))
+        _check(rc, allow=(MX_ENOTCONV,))
+        return J.value, grad, {"iters": iters, "relres": relres, "iters_max": info.iters_max,
+                               "converged": rc == MX_OK}
 
     def solve_rhs(self, b, rtol=1e-8, x=None):
         nrhs = b.shape[1]

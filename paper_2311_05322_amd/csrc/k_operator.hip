@@ -286,9 +286,102 @@ __global__ void k_prolong(int64_t n, const int32_t* __restrict__ edge, const int
   z[o] = make_double2(zz.x + wk * s.x, zz.y + wk * s.y);
 }
 
+// Per tetrahedron: gt[T][n] = k0^2 sum_pq M_{T,n}[p][q] W[p][q] with
+// W[p][q] = sum_j lam[e_p][j] u[e_q][j] (transmitter sum of the adjoint and
+// forward fields), and rt[T][n] = |T| sum_m (grad l_n . grad l_m) eps_m
+// (the P1 stiffness applied to the nodal permittivity).
+__global__ void k_grad_tet(int32_t nt, const int32_t* __restrict__ ts, const double* __restrict__ xyz,
+                           const int32_t* __restrict__ t2e, const double2* __restrict__ lam,
+                           const double2* __restrict__ u, int nrhs, const double2* __restrict__ eps, double k0sq,
+                           double2* __restrict__ gt, double2* __restrict__ rt) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  int32_t v[4], e[6];
+  for (int k = 0; k < 4; ++k) v[k] = ts[4 * (size_t)t + k];
+  for (int k = 0; k < 6; ++k) e[k] = t2e[6 * (size_t)t + k];
+  double g[4][3];
+  double vol = tet_geometry(xyz, v, g);
+  double G[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) G[i][j] = dot3(g[i], g[j]);
+  double2 W[6][6];
+  for (int p = 0; p < 6; ++p)
+    for (int q = 0; q < 6; ++q) W[p][q] = make_double2(0.0, 0.0);
+  for (int j = 0; j < nrhs; ++j) {
+    double2 lv[6], uv[6];
+    for (int p = 0; p < 6; ++p) {
+      lv[p] = lam[(int64_t)e[p] * nrhs + j];
+      uv[p] = u[(int64_t)e[p] * nrhs + j];
+    }
+    for (int p = 0; p < 6; ++p)
+      for (int q = 0; q < 6; ++q) {
+        W[p][q].x += lv[p].x * uv[q].x - lv[p].y * uv[q].y;
+        W[p][q].y += lv[p].x * uv[q].y + lv[p].y * uv[q].x;
+      }
+  }
+  for (int n = 0; n < 4; ++n) {
+    double re = 0, im = 0;
+    for (int p = 0; p < 6; ++p) {
+      int a = cLE[p][0], b = cLE[p][1];
+      for (int q = 0; q < 6; ++q) {
+        int c = cLE[q][0], d = cLE[q][1];
+        double m = vol * (lll(n, a, c) * G[b][d] - lll(n, a, d) * G[b][c] - lll(n, b, c) * G[a][d] +
+                          lll(n, b, d) * G[a][c]);
+        re += m * W[p][q].x;
+        im += m * W[p][q].y;
+      }
+    }
+    gt[4 * (size_t)t + n] = make_double2(k0sq * re, k0sq * im);
+    double kr = 0, ki = 0;
+    for (int m = 0; m < 4; ++m) {
+      double2 em = eps[v[m]];
+      kr += G[n][m] * em.x;
+      ki += G[n][m] * em.y;
+    }
+    rt[4 * (size_t)t + n] = make_double2(vol * kr, vol * ki);
+  }
+}
+
+// Per vertex n (tetrahedra in ascending order): G_n = sum gt, (K1 eps)_n = sum rt,
+// grad_n = conj(G_n) + reg * (K1 eps)_n.
+__global__ void k_grad_vertex(int32_t nv, const int64_t* __restrict__ v2t_ptr, const int32_t* __restrict__ v2t,
+                              const int32_t* __restrict__ ts, const double2* __restrict__ gt,
+                              const double2* __restrict__ rt, double reg, double2* __restrict__ grad,
+                              double2* __restrict__ keps) {
+  int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nv) return;
+  double gr = 0, gi = 0, kr = 0, ki = 0;
+  for (int64_t k = v2t_ptr[n]; k < v2t_ptr[n + 1]; ++k) {
+    int32_t t = v2t[k];
+    int loc = 0;
+    while (loc < 3 && ts[4 * (size_t)t + loc] != n) ++loc;
+    double2 a = gt[4 * (size_t)t + loc], b = rt[4 * (size_t)t + loc];
+    gr += a.x;
+    gi += a.y;
+    kr += b.x;
+    ki += b.y;
+  }
+  grad[n] = make_double2(gr + reg * kr, -gi + reg * ki);
+  keps[n] = make_double2(kr, ki);
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
+
+void launch_grad_tet(hipStream_t s, int32_t nt, const int32_t* ts, const double* xyz, const int32_t* t2e,
+                     const double2* lam, const double2* u, int nrhs, const double2* eps, double k0sq, double2* gt,
+                     double2* rt) {
+  if (nt > 0)
+    hipLaunchKernelGGL(k_grad_tet, dim3(nblk(nt, 128)), dim3(128), 0, s, nt, ts, xyz, t2e, lam, u, nrhs, eps, k0sq,
+                       gt, rt);
+}
+void launch_grad_vertex(hipStream_t s, int32_t nv, const int64_t* v2t_ptr, const int32_t* v2t, const int32_t* ts,
+                        const double2* gt, const double2* rt, double reg, double2* grad, double2* keps) {
+  if (nv > 0)
+    hipLaunchKernelGGL(k_grad_vertex, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, v2t_ptr, v2t, ts, gt, rt, reg, grad,
+                       keps);
+}
 
 void launch_element(hipStream_t s, int32_t nt, const int32_t* ts, const double* xyz, const double2* eps,
                     int eps_kind, double k0sq, double2* out) {

@@ -215,6 +215,13 @@ struct mx_ctx {
   DBuf<int32_t> s_edge, s_col, r_edge;
   DBuf<double2> s_val, r_val;
   DBuf<int64_t> r_ptr;
+  // adjoint gradient
+  bool have_forward = false;
+  int last_ntx = 0, last_nrx = 0;
+  double last_rtol = 1e-8;
+  DBuf<int32_t> a_edge, a_col, t2e, v2t;
+  DBuf<int64_t> v2t_ptr;
+  DBuf<double2> a_val, U_fwd, gt, rt, gradv, keps;
   // workspace
   int ws_nrhs = 0, ws_m = 0;
   DBuf<double2> V, Z, x, b, r, H, sn, g, y, h1, h2, dotpart, S;
@@ -566,6 +573,9 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
     c->topo = std::move(T);
     c->have_mesh = true;
     c->have_dec = false;
+    c->t2e.release();
+    c->v2t.release();
+    c->v2t_ptr.release();
     c->local_ready = c->factored = false;
     c->tx = SourceSet();
     c->rx = SourceSet();
@@ -609,6 +619,7 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
   CK(sync(c));
   c->assembled = true;
   c->local_ready = c->factored = false;
+  c->have_forward = false;
   return MX_OK;
 }
 
@@ -659,6 +670,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
   }
   const Decomposition& D = c->dec;
   c->local_ready = c->factored = false;
+  c->have_forward = false;
   CK(fill_pool(c));  // interface-face blocks for this permittivity
   const size_t nent = (size_t)D.mat_off[D.nsub];
   if (c->precision != o.precision) c->factors.release();
@@ -755,15 +767,103 @@ int mx_solve(mx_ctx* c, const mx_sources* tx, const mx_sources* rx, double rtol,
   int rc = fgmres(c, ntx, rtol, info);
   if (rc != MX_OK && rc != MX_ENOTCONV) return rc;
   const int nrx = rxs->n;
-  if (S) {
-    CK(c->S.alloc((size_t)nrx * ntx));
-    launch_receivers(c->stream, nrx, ntx, c->r_ptr.p, c->r_edge.p, c->r_val.p, c->x.p, c->S.p);
-    MX_HIP_CHECK(hipGetLastError());
-    CK(copy_out(c, S, c->S.p, (size_t)nrx * ntx * sizeof(double2)));
-  }
+  CK(c->S.alloc((size_t)nrx * ntx));
+  launch_receivers(c->stream, nrx, ntx, c->r_ptr.p, c->r_edge.p, c->r_val.p, c->x.p, c->S.p);
+  MX_HIP_CHECK(hipGetLastError());
+  if (S) CK(copy_out(c, S, c->S.p, (size_t)nrx * ntx * sizeof(double2)));
   if (E) CK(copy_out(c, E, c->x.p, blk * sizeof(double2)));
   CK(sync(c));
+  c->have_forward = true;
+  c->last_ntx = ntx;
+  c->last_nrx = nrx;
+  c->last_rtol = rtol;
   if (rc == MX_ENOTCONV) g_err = "FGMRES reached maxit";
+  return rc;
+}
+
+int mx_gradient(mx_ctx* c, const mx_c128* S_meas, const double* w, double alpha, mx_c128* grad, double* J,
+                mx_solve_info* info) {
+  if (!c || !S_meas || !w || !grad || !J) return set_err(MX_EINVAL, "NULL argument");
+  if (!c->have_forward || !c->factored) return set_err(MX_ESTATE, "mx_gradient needs a preceding mx_solve");
+  if (c->eps_kind != MX_EPS_P1) return set_err(MX_EINVAL, "the gradient is defined for per-vertex permittivity");
+  if (!(alpha >= 0) || !std::isfinite(alpha)) return set_err(MX_EINVAL, "alpha must be finite and >= 0");
+  CK(use_device(c));
+  const Topology& T = c->topo;
+  const int ntx = c->last_ntx, nrx = c->last_nrx;
+  const int64_t blk = T.ne * (int64_t)ntx;
+  // misfit d = S - S_meas and its cost (host, nrx x ntx)
+  std::vector<double2> Sh((size_t)nrx * ntx);
+  MX_HIP_CHECK(hipMemcpyAsync(Sh.data(), c->S.p, Sh.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  CK(sync(c));
+  double Jm = 0;
+  std::vector<std::pair<int64_t, double2>> acc;
+  for (int i = 0; i < nrx; ++i)
+    for (int j = 0; j < ntx; ++j) {
+      const size_t o = (size_t)i * ntx + j;
+      const double dr = Sh[o].x - S_meas[o].re, di = Sh[o].y - S_meas[o].im;
+      Jm += 0.5 * w[o] * (dr * dr + di * di);
+      // adjoint source of transmitter j: w_ij conj(d_ij) r_i
+      const double cr = w[o] * dr, ci = -w[o] * di;
+      for (int64_t k = c->rx.ptr[i]; k < c->rx.ptr[i + 1]; ++k) {
+        const double2 v = c->rx.val[k];
+        acc.push_back({(int64_t)c->rx.edge[k] * ntx + j, make_double2(cr * v.x - ci * v.y, cr * v.y + ci * v.x)});
+      }
+    }
+  std::stable_sort(acc.begin(), acc.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  std::vector<int32_t> ae, ac;
+  std::vector<double2> av;
+  for (size_t a = 0; a < acc.size();) {
+    size_t b = a;
+    double2 v = make_double2(0, 0);
+    while (b < acc.size() && acc[b].first == acc[a].first) {
+      v.x += acc[b].second.x;
+      v.y += acc[b].second.y;
+      ++b;
+    }
+    ae.push_back((int32_t)(acc[a].first / ntx));
+    ac.push_back((int32_t)(acc[a].first % ntx));
+    av.push_back(v);
+    a = b;
+  }
+  CK(c->a_edge.upload(ae, c->stream));
+  CK(c->a_col.upload(ac, c->stream));
+  CK(c->a_val.upload(av, c->stream));
+  // keep the forward fields, solve the adjoint problems with the same factors
+  CK(c->U_fwd.alloc(blk));
+  MX_HIP_CHECK(hipMemcpyAsync(c->U_fwd.p, c->x.p, blk * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+  launch_fill_zero<double2>(c->stream, blk, c->b.p);
+  launch_scatter_rhs(c->stream, (int64_t)ae.size(), c->a_edge.p, c->a_col.p, c->a_val.p, make_double2(1.0, 0.0),
+                     ntx, c->b.p);
+  MX_HIP_CHECK(hipGetLastError());
+  int rc = fgmres(c, ntx, c->last_rtol, info);
+  if (rc != MX_OK && rc != MX_ENOTCONV) return rc;
+  // gradient: per-tetrahedron contraction, then a per-vertex gather
+  if (!c->t2e.p) CK(c->t2e.upload(T.t2e, c->stream));
+  if (!c->v2t.p) {
+    CK(c->v2t.upload(T.v2t, c->stream));
+    CK(c->v2t_ptr.upload(T.v2t_ptr, c->stream));
+  }
+  CK(c->gt.alloc(4 * (size_t)T.nt));
+  CK(c->rt.alloc(4 * (size_t)T.nt));
+  CK(c->gradv.alloc((size_t)T.nv));
+  CK(c->keps.alloc((size_t)T.nv));
+  const double k0sq = c->k0 * c->k0;
+  launch_grad_tet(c->stream, T.nt, c->ts.p, c->xyz.p, c->t2e.p, c->x.p, c->U_fwd.p, ntx, c->eps.p, k0sq, c->gt.p,
+                  c->rt.p);
+  launch_grad_vertex(c->stream, T.nv, c->v2t_ptr.p, c->v2t.p, c->ts.p, c->gt.p, c->rt.p, alpha * k0sq * k0sq,
+                     c->gradv.p, c->keps.p);
+  MX_HIP_CHECK(hipGetLastError());
+  CK(copy_out(c, grad, c->gradv.p, (size_t)T.nv * sizeof(double2)));
+  std::vector<double2> ke(T.nv), ep(T.nv);
+  MX_HIP_CHECK(hipMemcpyAsync(ke.data(), c->keps.p, T.nv * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  MX_HIP_CHECK(hipMemcpyAsync(ep.data(), c->eps.p, T.nv * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  // restore the forward fields as the current solution
+  MX_HIP_CHECK(hipMemcpyAsync(c->x.p, c->U_fwd.p, blk * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+  CK(sync(c));
+  double R = 0;
+  for (int64_t n = 0; n < T.nv; ++n) R += ep[n].x * ke[n].x + ep[n].y * ke[n].y;
+  *J = Jm + alpha * 0.5 * k0sq * k0sq * R;
+  if (rc == MX_ENOTCONV) g_err = "adjoint FGMRES reached maxit";
   return rc;
 }
 

@@ -38,6 +38,13 @@ template <typename C>
 void launch_pad_identity(hipStream_t s, int32_t nsub, const int64_t* dof_ptr, const int32_t* Npad,
                          const int64_t* mat_off, C* A);
 
+// adjoint gradient
+void launch_grad_tet(hipStream_t s, int32_t nt, const int32_t* ts, const double* xyz, const int32_t* t2e,
+                     const double2* lam, const double2* u, int nrhs, const double2* eps, double k0sq, double2* gt,
+                     double2* rt);
+void launch_grad_vertex(hipStream_t s, int32_t nv, const int64_t* v2t_ptr, const int32_t* v2t, const int32_t* ts,
+                        const double2* gt, const double2* rt, double reg, double2* grad, double2* keps);
+
 // operator application and Schwarz transfer
 void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t* col, const double2* val,
                  const double2* X, double2* Y, int nrhs);
