@@ -71,14 +71,14 @@ def algorithmic_work(kind, n_i, nnz, ne, nrhs, elem_bytes, kt):
     return None, None
 
 
-def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=True):
+def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=True, coarse=False):
     import torch
     import paper_2311_05322_amd as mx
     S = np.zeros((len(p.src_pos), len(p.src_pos)), np.complex128)
 
     def step():
         ctx.assemble(None, None, eps_dev, p.eps_kind, p.freq, p.eps_b, reuse_mesh=True)
-        ctx.setup_schwarz(p.nsub, p.overlap, precision=prec, restart=restart)
+        ctx.setup_schwarz(p.nsub, p.overlap, precision=prec, restart=restart, coarse=coarse)
         _, _, info = ctx.solve(p.src_pos, p.src_mom, rtol=p.rtol, E=E_dev, S=S)
         return info
 
@@ -92,7 +92,8 @@ def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=Tr
     infos = []
     for k in range(steps):
         infos.append(step())
-        log(f"  step {k}: iters {infos[-1]['iters_max']} relres {infos[-1]['relres'].max():.2e}")
+        log(f"  step {k}: iters {infos[-1]['iters_max']} relres {infos[-1]['relres'].max():.2e} "
+            f"fallback {infos[-1]['fallback']}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = ctx.kernel_times() if profile else None
@@ -161,6 +162,7 @@ def main():
     ap.add_argument("--workload", default="chamber1m", choices=sorted(WORKLOADS))
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference variant")
+    ap.add_argument("--no-learned", action="store_true", help="headline without the learned coarse term")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
@@ -190,19 +192,33 @@ def main():
     eps_dev = torch.from_numpy(np.ascontiguousarray(p.eps)).to(dev)
     E_dev = torch.empty((sz.ne, nrhs), dtype=torch.complex128, device=dev)
 
-    log("variant: complex64 factors (matrix cores) + FP64 FGMRES")
-    ms_mix, infos_mix, kt_mix, S_mix = run_variant(ctx, p, eps_dev, E_dev, mx.MX_PREC_C64, args.steps,
-                                                   args.warmup, args.restart)
-    ref = None
+    wfile = os.path.join(ROOT, "paper_2311_05322_amd", "weights", f"coarse_{args.workload}.npz")
+    learned = os.path.exists(wfile) and not args.no_learned
+    if learned:
+        from paper_2311_05322_amd.train_coarse import load_weights
+        ctx.setup_schwarz(p.nsub, p.overlap, factor=False, coarse=True)
+        load_weights(ctx, wfile)
+    variants = {}
+    order = ([("c64_learned", mx.MX_PREC_C64, True)] if learned else []) + [("c64_plain", mx.MX_PREC_C64, False)]
     if not args.no_fp64:
-        log("variant: complex128 factors + FP64 FGMRES (plain one-level Schwarz)")
-        ms_64, infos_64, kt_64, S_64 = run_variant(ctx, p, eps_dev, E_dev, mx.MX_PREC_C128, args.steps,
-                                                   args.warmup, args.restart)
-        ref = {"solves_per_s": 1.0 / ms_64, "ms_per_step": ms_64 * 1e3,
-               "iters": int(infos_64[-1]["iters_max"]),
-               "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt_64.items() if v[1]},
-               "S_rel_diff_vs_mixed": float(np.abs(S_mix - S_64).max() / np.abs(S_64).max())}
+        order.append(("c128_plain", mx.MX_PREC_C128, False))
+    for name, prec, co in order:
+        log(f"variant {name}")
+        ms, infos, kt, S = run_variant(ctx, p, eps_dev, E_dev, prec, args.steps, args.warmup, args.restart,
+                                       coarse=co)
+        variants[name] = {"ms": ms, "infos": infos, "kt": kt, "S": S}
     ctx.close()
+    head = "c64_learned" if learned else "c64_plain"
+    ms_mix, infos_mix, kt_mix, S_mix = (variants[head][k] for k in ("ms", "infos", "kt", "S"))
+    ref = None
+    if "c128_plain" in variants:
+        v = variants["c128_plain"]
+        ref = {"solves_per_s": 1.0 / v["ms"], "ms_per_step": v["ms"] * 1e3,
+               "iters": int(v["infos"][-1]["iters_max"]),
+               "kernel_ms_per_step": {k: x[0] / args.steps for k, x in v["kt"].items() if x[1]},
+               "S_rel_diff_vs_headline": float(np.abs(S_mix - v["S"]).max() / np.abs(v["S"]).max())}
+    others = {k: {"solves_per_s": 1.0 / v["ms"], "iters": int(v["infos"][-1]["iters_max"]),
+                  "fallback": int(v["infos"][-1]["fallback"])} for k, v in variants.items()}
 
     # dominant kernel of the headline variant and its roofline
     kt = kt_mix
@@ -234,7 +250,9 @@ def main():
         "dtype": "c64/c128", "data": "synthetic",
         "config": {"workload": args.workload, "ne": int(sz.ne), "nnz": int(sz.nnz), "nsub": int(sz.nsub),
                    "overlap": p.overlap, "n_i_max": int(n_i.max()), "nrhs": nrhs, "rtol": p.rtol,
-                   "restart": args.restart, "coarse": "none", "precision": "complex64 LU + FP64 FGMRES"},
+                   "restart": args.restart, "coarse": "learned" if head == "c64_learned" else "none",
+                   "precision": "complex64 LU + FP64 FGMRES"},
+        "variants": others,
         "iters": iters,
         "speedup_vs_fp64_gpu": (value / ref["solves_per_s"]) if ref else None,
         "fp64_reference": ref,

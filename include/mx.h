@@ -79,6 +79,8 @@ typedef struct {
   int32_t maxit;       /* iteration cap (default 2000 when <= 0) */
   int32_t factor;      /* 1: factor the subdomain matrices (normal use);
                           0: keep them assembled (mx_get_local_matrix only) */
+  int32_t coarse;      /* 1: add the learned coarse correction (needs weights:
+                          mx_coarse_init / mx_coarse_set_weights); 0: one-level ORAS */
 } mx_schwarz_opts;
 
 /* Point dipoles: pos [n][3] positions, moment [n][3] complex moments (A m).
@@ -96,6 +98,8 @@ typedef struct {
   int32_t iters_max;   /* max over right-hand sides */
   int32_t cycles;      /* restart cycles */
   double t_iter;       /* seconds spent in the Krylov iteration */
+  int32_t fallback;    /* 1/2: the learned coarse term was switched off during the
+                          solve (non-finite output / a cycle with < 10% reduction) */
 } mx_solve_info;
 
 /* Sizes of the current discretisation and decomposition. */
@@ -121,6 +125,7 @@ enum {
   MX_K_CGS = 9,         /* classical Gram-Schmidt x2 + norm + Givens, per step */
   MX_K_ASSEMBLE = 10,   /* element/face blocks + CSR gather                  */
   MX_K_LOCAL = 11,      /* dense subdomain assembly (zero fill + gather)     */
+  MX_K_COARSE = 12,     /* learned coarse correction (pooling, network, prolongation) */
   MX_K_NCLASS = 16
 };
 typedef struct {
@@ -228,6 +233,43 @@ int mx_get_local_matrix(mx_ctx* ctx, int32_t i, mx_c128* B);
 /* Point functionals r[e] = p . N_e(x) of the given points as a dense
  * [ne][n] array (host); the same values build right-hand sides. */
 int mx_point_functionals(mx_ctx* ctx, const mx_sources* pts, mx_c128* R);
+
+/* ---- learned coarse-space correction -------------------------------------
+ * An additive correction to the one-level ORAS preconditioner (not in the
+ * paper; the solver's own addition): for a block v, features
+ * x_i = P_i^T R_i v / s (s = ||v|| / sqrt(ne) per column; P_i the 4x4x4
+ * lattice prolongation of subdomain i, 192 complex = 384 real channels),
+ * a per-subdomain network (MLP 384-256-256-256-256 with GELU, two message-
+ * passing layers over subdomain adjacency, 384 outputs) with bf16 operands and
+ * FP32 accumulation, and q = s * out_scale * sum_i R_i^T D_i P_i c_i added to
+ * M^{-1} v.  FGMRES tolerates the nonlinear preconditioner; the solver falls
+ * back to plain ORAS on non-finite output or a stagnating cycle.
+ * Parameters: flat FP32 vector of mx_coarse_num_params() values in the order
+ * W1 b1 W2 b2 W3 b3 W4 b4 Ws1 Wn1 b5 Ws2 Wn2 b6 (W row-major [out][in]);
+ * inputs are divided by in_scale, outputs multiplied by out_scale. */
+int64_t mx_coarse_num_params(void);
+/* Random initial weights (seeded; normal, 1/fan_in variance, output layers x0.1). */
+int mx_coarse_init(mx_ctx* ctx, uint64_t seed);
+int mx_coarse_set_weights(mx_ctx* ctx, const float* theta, int64_t n, double in_scale, double out_scale);
+int mx_coarse_get_weights(mx_ctx* ctx, float* theta, int64_t n, double* in_scale, double* out_scale);
+/* Pooled features X [nrhs][nsub][384] (host) of v [ne][nrhs] (host or device). */
+int mx_coarse_features(mx_ctx* ctx, const mx_c128* v, int32_t nrhs, float* X);
+/* Network outputs out [ngraph][nsub][384] for inputs X [ngraph][nsub][384]
+ * (host; scales not applied). */
+int mx_coarse_forward(mx_ctx* ctx, const float* X, int32_t ngraph, float* out);
+/* Mean squared error against Y and its parameter gradient (host buffers). */
+int mx_coarse_loss_grad(mx_ctx* ctx, const float* X, const float* Y, int32_t ngraph, double* loss, float* grad);
+/* Training data from the plain solver on the current operator: solves the
+ * transmitters to rtol_exact, then re-runs with restart length snap_every and
+ * records, at every restart, the features of the residual r and the
+ * least-squares lattice fit of R_i (e - M^{-1} r)/s (e = exact - current
+ * iterate), up to max_snapshots restarts; appends to the context's data set. */
+int mx_coarse_collect(mx_ctx* ctx, const mx_sources* tx, int32_t snap_every, int32_t max_snapshots,
+                      double rtol_exact, int32_t* nsnap);
+int mx_coarse_clear(mx_ctx* ctx);
+/* Adam on the collected data (mean squared error in scaled units), batches of
+ * batch_graphs (snapshot, transmitter) graphs; loss_hist [epochs] may be NULL. */
+int mx_coarse_train(mx_ctx* ctx, int32_t epochs, int32_t batch_graphs, double lr, uint64_t seed, double* loss_hist);
 
 const char* mx_last_error(void);
 

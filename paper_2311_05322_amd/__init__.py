@@ -22,10 +22,12 @@ MX_PREC_C128, MX_PREC_C64 = 0, 1
 EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_solve", "mx_solve_rhs",
            "mx_apply_operator", "mx_apply_preconditioner", "mx_get_sizes", "mx_get_topology",
            "mx_get_matrix_values", "mx_get_partition", "mx_get_local_matrix", "mx_point_functionals",
-           "mx_set_stream", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_last_error"]
+           "mx_set_stream", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_coarse_num_params", "mx_coarse_init",
+           "mx_coarse_set_weights", "mx_coarse_get_weights", "mx_coarse_features", "mx_coarse_forward",
+           "mx_coarse_loss_grad", "mx_coarse_collect", "mx_coarse_clear", "mx_coarse_train", "mx_last_error"]
 
 KERNEL_CLASSES = ["lu_panel", "lu_rowpanel", "lu_update", "lu_inv", "trsm_lower", "trsm_upper", "spmm",
-                  "restrict", "prolong", "cgs", "assemble", "local"]
+                  "restrict", "prolong", "cgs", "assemble", "local", "coarse"]
 
 
 class MxError(RuntimeError):
@@ -43,7 +45,8 @@ class Mesh(ct.Structure):
 
 
 class SchwarzOpts(ct.Structure):
-    _fields_ = [("precision", ct.c_int32), ("restart", ct.c_int32), ("maxit", ct.c_int32), ("factor", ct.c_int32)]
+    _fields_ = [("precision", ct.c_int32), ("restart", ct.c_int32), ("maxit", ct.c_int32), ("factor", ct.c_int32),
+                ("coarse", ct.c_int32)]
 
 
 class Sources(ct.Structure):
@@ -52,7 +55,7 @@ class Sources(ct.Structure):
 
 class SolveInfo(ct.Structure):
     _fields_ = [("iters", ct.c_void_p), ("relres", ct.c_void_p), ("iters_max", ct.c_int32),
-                ("cycles", ct.c_int32), ("t_iter", ct.c_double)]
+                ("cycles", ct.c_int32), ("t_iter", ct.c_double), ("fallback", ct.c_int32)]
 
 
 class Sizes(ct.Structure):
@@ -95,11 +98,22 @@ def lib():
             "mx_set_profiling": [vp, ct.c_int],
             "mx_get_kernel_times": [vp, ct.POINTER(KernelTimes)],
             "mx_gradient": [vp, vp, vp, dbl, vp, ct.POINTER(dbl), ct.POINTER(SolveInfo)],
+            "mx_coarse_init": [vp, ct.c_uint64],
+            "mx_coarse_set_weights": [vp, vp, ct.c_int64, dbl, dbl],
+            "mx_coarse_get_weights": [vp, vp, ct.c_int64, ct.POINTER(dbl), ct.POINTER(dbl)],
+            "mx_coarse_features": [vp, vp, i32, vp],
+            "mx_coarse_forward": [vp, vp, i32, vp],
+            "mx_coarse_loss_grad": [vp, vp, vp, i32, ct.POINTER(dbl), vp],
+            "mx_coarse_collect": [vp, ct.POINTER(Sources), i32, i32, dbl, ct.POINTER(i32)],
+            "mx_coarse_clear": [vp],
+            "mx_coarse_train": [vp, i32, i32, dbl, ct.c_uint64, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ct.c_int
+        L.mx_coarse_num_params.argtypes = []
+        L.mx_coarse_num_params.restype = ct.c_int64
         L.mx_last_error.argtypes = []
         L.mx_last_error.restype = ct.c_char_p
         _lib = L
@@ -194,8 +208,9 @@ class Context:
         self.ne = self.sizes().ne
         del keep
 
-    def setup_schwarz(self, nsub, overlap, precision=MX_PREC_C128, restart=30, maxit=2000, factor=True):
-        o = SchwarzOpts(int(precision), int(restart), int(maxit), 1 if factor else 0)
+    def setup_schwarz(self, nsub, overlap, precision=MX_PREC_C128, restart=30, maxit=2000, factor=True,
+                      coarse=False):
+        o = SchwarzOpts(int(precision), int(restart), int(maxit), 1 if factor else 0, 1 if coarse else 0)
         _check(lib().mx_setup_schwarz(self._h, int(nsub), int(overlap), ct.byref(o)))
 
     # -- solves ----------------------------------------------------------------
@@ -220,7 +235,7 @@ class Context:
                             _ptr(E), _ptr(S), ct.byref(info))
         _check(rc, allow=(MX_ENOTCONV,))
         return E, S, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
-                      "t_iter": info.t_iter, "converged": rc == MX_OK}
+                      "t_iter": info.t_iter, "converged": rc == MX_OK, "fallback": info.fallback}
 
     def gradient(self, S_meas, w, alpha, grad=None):
         """Cost J and complex gradient dJ/dRe eps + j dJ/dIm eps (per vertex)
@@ -251,7 +266,7 @@ class Context:
         rc = lib().mx_solve_rhs(self._h, _ptr(b), nrhs, float(rtol), _ptr(x), ct.byref(info))
         _check(rc, allow=(MX_ENOTCONV,))
         return x, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
-                   "t_iter": info.t_iter, "converged": rc == MX_OK}
+                   "t_iter": info.t_iter, "converged": rc == MX_OK, "fallback": info.fallback}
 
     def apply_operator(self, X, Y=None):
         X2 = X if _is_torch(X) else np.ascontiguousarray(X, dtype=np.complex128)
@@ -303,6 +318,57 @@ class Context:
         B = np.zeros((n, n), np.complex128)
         _check(lib().mx_get_local_matrix(self._h, int(i), _ptr(B)))
         return B
+
+    # -- learned coarse correction -------------------------------------------
+    def coarse_init(self, seed=0):
+        _check(lib().mx_coarse_init(self._h, int(seed)))
+
+    def coarse_weights(self):
+        n = lib().mx_coarse_num_params()
+        th = np.zeros(n, np.float32)
+        sx, sy = ct.c_double(), ct.c_double()
+        _check(lib().mx_coarse_get_weights(self._h, _ptr(th), n, ct.byref(sx), ct.byref(sy)))
+        return th, sx.value, sy.value
+
+    def coarse_set_weights(self, theta, in_scale=1.0, out_scale=1.0):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(lib().mx_coarse_set_weights(self._h, _ptr(th), th.size, float(in_scale), float(out_scale)))
+
+    def coarse_features(self, v):
+        v2 = v if _is_torch(v) else np.ascontiguousarray(v, dtype=np.complex128)
+        nrhs = v2.shape[1]
+        X = np.zeros((nrhs, self.sizes().nsub, 384), np.float32)
+        _check(lib().mx_coarse_features(self._h, _ptr(v2), nrhs, _ptr(X)))
+        return X
+
+    def coarse_forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        out = np.zeros_like(X)
+        _check(lib().mx_coarse_forward(self._h, _ptr(X), X.shape[0], _ptr(out)))
+        return out
+
+    def coarse_loss_grad(self, X, Y):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.ascontiguousarray(Y, dtype=np.float32)
+        g = np.zeros(lib().mx_coarse_num_params(), np.float32)
+        loss = ct.c_double()
+        _check(lib().mx_coarse_loss_grad(self._h, _ptr(X), _ptr(Y), X.shape[0], ct.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def coarse_collect(self, pos, mom, snap_every=3, max_snapshots=20, rtol_exact=1e-12):
+        tx, keep = _sources(pos, mom)
+        n = ct.c_int32()
+        _check(lib().mx_coarse_collect(self._h, ct.byref(tx), int(snap_every), int(max_snapshots),
+                                       float(rtol_exact), ct.byref(n)))
+        return n.value
+
+    def coarse_clear(self):
+        _check(lib().mx_coarse_clear(self._h))
+
+    def coarse_train(self, epochs, batch_graphs=8, lr=1e-3, seed=0):
+        hist = np.zeros(epochs, np.float64)
+        _check(lib().mx_coarse_train(self._h, int(epochs), int(batch_graphs), float(lr), int(seed), _ptr(hist)))
+        return hist
 
     def point_functionals(self, pos, mom):
         s, keep = _sources(pos, mom)

@@ -1,0 +1,461 @@
+// Learned coarse-space correction: per-subdomain 4x4x4 lattice prolongation,
+// pooling of block vectors onto the lattice, the per-subdomain network
+// (4-layer MLP + 2 message-passing layers) and its training kernels.
+//
+// Network arithmetic: the operands of every matrix product are rounded to
+// bfloat16 (round to nearest even) as they are staged into LDS and multiplied
+// on the 16x16x4 FP32 matrix cores with FP32 accumulation; biases, GELU, the
+// loss and the Adam update run in FP32 on FP32 master weights.
+#include "mx_device.h"
+#include "mx_kernels.h"
+
+namespace mx {
+
+namespace {
+
+constexpr int NCO = 192;   // complex lattice coefficients (64 nodes x 3 components)
+constexpr int NIN = 384;   // real channels [Re | Im]
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__device__ inline float bf16r(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return x;  // inf / nan unchanged
+  u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+  return __uint_as_float(u);
+}
+
+__device__ inline float gelu_f(float z) {
+  const float a = 0.7978845608028654f;
+  return 0.5f * z * (1.f + tanhf(a * (z + 0.044715f * z * z * z)));
+}
+__device__ inline float gelu_grad_f(float z) {
+  const float a = 0.7978845608028654f;
+  float t = tanhf(a * (z + 0.044715f * z * z * z));
+  return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * a * (1.f + 3.f * 0.044715f * z * z);
+}
+
+// P[row][3 node + k] = sum_q w_q phi_node(x_a + s_q t) t_k  (3-point Gauss)
+__global__ void k_coarse_P(int64_t nrows, const int32_t* __restrict__ row_sub, const int32_t* __restrict__ dofs,
+                           const int32_t* __restrict__ edges, const double* __restrict__ xyz,
+                           const double* __restrict__ box, float* __restrict__ P) {
+  int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  const int s = row_sub[row];
+  const int e = dofs[row];
+  double xa[3], t[3], lo[3], span[3];
+  for (int c = 0; c < 3; ++c) {
+    xa[c] = xyz[3 * (size_t)edges[2 * (size_t)e] + c];
+    t[c] = xyz[3 * (size_t)edges[2 * (size_t)e + 1] + c] - xa[c];
+    lo[c] = box[6 * (size_t)s + c];
+    span[c] = (box[6 * (size_t)s + 3 + c] - lo[c]) / 3.0;
+  }
+  float* pr = P + row * NCO;
+  for (int k = 0; k < NCO; ++k) pr[k] = 0.f;
+  const double sq[3] = {0.1127016653792583, 0.5, 0.8872983346207417};
+  const double wq[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  for (int q = 0; q < 3; ++q) {
+    double psi[3][4];
+    for (int c = 0; c < 3; ++c) {
+      double xi = (xa[c] + sq[q] * t[c] - lo[c]) / span[c];
+      for (int a = 0; a < 4; ++a) psi[c][a] = fmax(0.0, 1.0 - fabs(xi - a));
+    }
+    for (int cz = 0; cz < 4; ++cz) {
+      if (psi[2][cz] == 0.0) continue;
+      for (int by = 0; by < 4; ++by) {
+        if (psi[1][by] == 0.0) continue;
+        for (int ax = 0; ax < 4; ++ax) {
+          double phi = psi[0][ax] * psi[1][by] * psi[2][cz];
+          if (phi == 0.0) continue;
+          const int node = ax + 4 * by + 16 * cz;
+          for (int k = 0; k < 3; ++k) pr[3 * node + k] += (float)(wq[q] * phi * t[k]);
+        }
+      }
+    }
+  }
+}
+
+// X[(j*nsub + i)][k] (+192 for Im) = sum_l w_l P[l][k] v[dofs[l]][j] / s_j for the
+// right-hand sides j0 .. j0+nj-1 (nj <= 32); w = D weights or 1.
+__global__ void __launch_bounds__(256) k_pool(int nsub, const int64_t* __restrict__ dof_ptr,
+                                              const int32_t* __restrict__ dofs, const float* __restrict__ P,
+                                              const double* __restrict__ wts, const double2* __restrict__ v,
+                                              int nrhs, int j0, int nj, const double* __restrict__ scale,
+                                              float* __restrict__ X, int64_t xrows_stride) {
+  const int i = blockIdx.x;
+  const int k = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int jg = threadIdx.x >> 6;   // 0..3
+  float ar[8], ai[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) { ar[q] = 0.f; ai[q] = 0.f; }
+  const int64_t r0 = dof_ptr[i], r1 = dof_ptr[i + 1];
+  for (int64_t l = r0; l < r1; ++l) {
+    float pw = P[l * NCO + k];
+    if (wts) pw *= (float)wts[l];
+    const double2* vr = v + (int64_t)dofs[l] * nrhs + j0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = jg + 4 * q;
+      if (j < nj) {
+        double2 x = vr[j];
+        ar[q] += pw * (float)x.x;
+        ai[q] += pw * (float)x.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int j = jg + 4 * q;
+    if (j < nj) {
+      const double sj = scale[j0 + j];
+      const float inv = sj > 0 ? (float)(1.0 / sj) : 0.f;
+      float* xr = X + ((int64_t)(j0 + j) * nsub + i) * xrows_stride;
+      xr[k] = ar[q] * inv;
+      xr[NCO + k] = ai[q] * inv;
+    }
+  }
+}
+
+// xloc[vec_off[i] + l][j] += alpha * s_j * sum_k P[l][k] (c_re[k] + j c_im[k])
+template <typename C>
+__global__ void __launch_bounds__(256) k_coarse_apply(int64_t nrows, const int32_t* __restrict__ row_sub,
+                                                      const int64_t* __restrict__ dof_ptr,
+                                                      const int64_t* __restrict__ vec_off, const float* __restrict__ P,
+                                                      const float* __restrict__ Cn, int nsub, int nrhs,
+                                                      const double* __restrict__ scale, float alpha,
+                                                      C* __restrict__ xloc) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= nrows * nrhs) return;
+  const int64_t row = idx / nrhs;
+  const int j = (int)(idx - row * nrhs);
+  const int i = row_sub[row];
+  const float* pr = P + row * NCO;
+  const float* cr = Cn + ((int64_t)j * nsub + i) * NIN;
+  float re = 0.f, im = 0.f;
+  for (int k = 0; k < NCO; ++k) {
+    float p = pr[k];
+    re += p * cr[k];
+    im += p * cr[NCO + k];
+  }
+  const float f = alpha * (float)scale[j];
+  const int64_t o = (vec_off[i] + (row - dof_ptr[i])) * nrhs + j;
+  C x = xloc[o];
+  x.x += f * re;
+  x.y += f * im;
+  xloc[o] = x;
+}
+
+// G-apply: out[(j*nsub+i)][0:384] = G_i (in[(j*nsub+i)][0:192] , [192:384]) (real G on Re and Im)
+__global__ void __launch_bounds__(192) k_gapply(int nsub, int nrhs, const double* __restrict__ G,
+                                                const float* __restrict__ in, float* __restrict__ out) {
+  const int i = blockIdx.x, j = blockIdx.y, k = threadIdx.x;
+  const double* g = G + (int64_t)i * NCO * NCO + (int64_t)k * NCO;
+  const float* x = in + ((int64_t)j * nsub + i) * NIN;
+  double re = 0, im = 0;
+  for (int m = 0; m < NCO; ++m) {
+    re += g[m] * x[m];
+    im += g[m] * x[NCO + m];
+  }
+  float* y = out + ((int64_t)j * nsub + i) * NIN;
+  y[k] = (float)re;
+  y[NCO + k] = (float)im;
+}
+
+// PDP_i = P_i^T diag(D_i) P_i  (192 x 192 per subdomain, FP64 accumulation)
+__global__ void __launch_bounds__(192) k_pdp(const int64_t* __restrict__ dof_ptr, const float* __restrict__ P,
+                                             const double* __restrict__ D, double* __restrict__ out) {
+  const int i = blockIdx.x, a = blockIdx.y, b = threadIdx.x;
+  double acc = 0;
+  for (int64_t l = dof_ptr[i]; l < dof_ptr[i + 1]; ++l) acc += D[l] * (double)P[l * NCO + a] * (double)P[l * NCO + b];
+  out[((int64_t)i * NCO + a) * NCO + b] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: C[m][n] (= or +=) sum_k a(m,k) b(k,n) (+ bias[n]), optional GELU with
+// the pre-activation kept in Z; a(m,k) = TA ? A[k*lda+m] : A[m*lda+k],
+// b(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n].  64x64 tiles, 16-deep K steps staged
+// in LDS (rounded to bf16 when rnd), 4 waves x (2x2) 16x16x4 MFMA tiles.
+// gridDim.z > 1 splits K; each split writes its own slice C + z*M*ldc.
+// ---------------------------------------------------------------------------
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
+                                              const float* __restrict__ B, int ldb, float* __restrict__ Cm, int ldc,
+                                              int beta, const float* __restrict__ bias, int act,
+                                              float* __restrict__ Z, int rnd) {
+  __shared__ float As[64][17];
+  __shared__ float Bs[16][65];
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int nsplit = gridDim.z;
+  const int kchunk = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    for (int e = tid; e < 64 * 16; e += 256) {
+      int mm = e / 16, kk = e % 16;
+      int gm = m0 + mm, gk = k0 + kk;
+      float va = 0.f;
+      if (gm < M && gk < ke) va = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      As[mm][kk] = rnd ? bf16r(va) : va;
+      int kk2 = e / 64, nn = e % 64;
+      int gk2 = k0 + kk2, gn = n0 + nn;
+      float vb = 0.f;
+      if (gn < N && gk2 < ke) vb = TB ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
+      Bs[kk2][nn] = rnd ? bf16r(vb) : vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      float av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[wr + 16 * a + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wc + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  float* Cz = Cm + (int64_t)blockIdx.z * M * ldc;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wr + 16 * a + acc_row<float>(lane, r);
+        const int gn = n0 + wc + 16 * b + (lane & 15);
+        if (gm < M && gn < N) {
+          float v = acc[a][b][r];
+          float* cp = Cz + (int64_t)gm * ldc + gn;
+          if (beta) v += *cp;
+          if (bias) v += bias[gn];
+          if (act) {
+            if (Z) Z[(int64_t)gm * ldc + gn] = v;
+            v = gelu_f(v);
+          }
+          *cp = v;
+        }
+      }
+}
+
+// sum of split-K slices: C[e] = sum_z W[z][e] (+ C[e] if beta)
+__global__ void k_sum_splits(int64_t n, int nsplit, const float* __restrict__ W, float* __restrict__ C, int beta) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float s = beta ? C[e] : 0.f;
+  for (int z = 0; z < nsplit; ++z) s += W[(int64_t)z * n + e];
+  C[e] = s;
+}
+
+// neighbour mean over subdomain adjacency within each graph (rows g*nsub + i)
+__global__ void k_nbr_mean(int ngraph, int nsub, int F, const int64_t* __restrict__ nptr,
+                           const int32_t* __restrict__ nbrs, const float* __restrict__ in, float* __restrict__ out) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ngraph * nsub * F) return;
+  int f = (int)(idx % F);
+  int64_t node = idx / F;
+  int i = (int)(node % nsub);
+  int64_t g = node / nsub;
+  int64_t a = nptr[i], b = nptr[i + 1];
+  float s = 0.f;
+  for (int64_t q = a; q < b; ++q) s += in[(g * nsub + nbrs[q]) * F + f];
+  out[idx] = b > a ? s / (float)(b - a) : 0.f;
+}
+
+// adjoint of the neighbour mean: out[j] (+)= sum_{i in N(j)} in[i] / |N(i)|
+__global__ void k_nbr_mean_T(int ngraph, int nsub, int F, const int64_t* __restrict__ nptr,
+                             const int32_t* __restrict__ nbrs, const float* __restrict__ in, float* __restrict__ out,
+                             int accumulate) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ngraph * nsub * F) return;
+  int f = (int)(idx % F);
+  int64_t node = idx / F;
+  int j = (int)(node % nsub);
+  int64_t g = node / nsub;
+  float s = 0.f;
+  for (int64_t q = nptr[j]; q < nptr[j + 1]; ++q) {
+    int i = nbrs[q];
+    float cnt = (float)(nptr[i + 1] - nptr[i]);
+    s += in[(g * nsub + i) * F + f] / cnt;
+  }
+  out[idx] = accumulate ? out[idx] + s : s;
+}
+
+__global__ void k_gelu_back(int64_t n, const float* __restrict__ dh, const float* __restrict__ z,
+                            float* __restrict__ dz) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) dz[e] = dh[e] * gelu_grad_f(z[e]);
+}
+
+// d = 2 (out - y) / n, per-block partial sums of (out - y)^2
+__global__ void __launch_bounds__(256) k_mse(int64_t n, const float* __restrict__ out, const float* __restrict__ y,
+                                             float* __restrict__ d, double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    float diff = out[e] - y[e];
+    d[e] = 2.f * diff / (float)n;
+    s += (double)diff * diff;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// column sums: out[f] = sum_r in[r][f]  (bias gradients), fixed order
+__global__ void k_colsum(int rows, int F, const float* __restrict__ in, float* __restrict__ out) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  double s = 0;
+  for (int r = 0; r < rows; ++r) s += in[(int64_t)r * F + f];
+  out[f] = (float)s;
+}
+
+__global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float gg = g[e];
+  float mm = b1 * m[e] + (1.f - b1) * gg;
+  float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+  m[e] = mm;
+  v[e] = vv;
+  w[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+__global__ void k_gather_rows(int nrows_out, int F, const int32_t* __restrict__ graphs, int nsub,
+                              const float* __restrict__ src, float* __restrict__ dst) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nrows_out * F) return;
+  int f = (int)(idx % F);
+  int64_t r = idx / F;
+  int64_t g = r / nsub, i = r % nsub;
+  dst[idx] = src[((int64_t)graphs[g] * nsub + i) * F + f];
+}
+
+__global__ void k_scale_f(int64_t n, float* __restrict__ x, float s) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) x[e] *= s;
+}
+
+__global__ void k_nonfinite(int64_t n, const float* __restrict__ x, int32_t* __restrict__ flag) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n && !isfinite(x[e])) *flag = 1;
+}
+
+}  // namespace
+
+void launch_coarse_P(hipStream_t s, int64_t nrows, const int32_t* row_sub, const int32_t* dofs, const int32_t* edges,
+                     const double* xyz, const double* box, float* P) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_coarse_P, dim3(nblk(nrows, 128)), dim3(128), 0, s, nrows, row_sub, dofs, edges, xyz, box, P);
+}
+
+void launch_pool(hipStream_t s, int nsub, const int64_t* dof_ptr, const int32_t* dofs, const float* P,
+                 const double* wts, const double2* v, int nrhs, const double* scale, float* X) {
+  for (int j0 = 0; j0 < nrhs; j0 += 32) {
+    int nj = nrhs - j0 < 32 ? nrhs - j0 : 32;
+    hipLaunchKernelGGL(k_pool, dim3(nsub, NCO / 64), dim3(256), 0, s, nsub, dof_ptr, dofs, P, wts, v, nrhs, j0, nj,
+                       scale, X, (int64_t)NIN);
+  }
+}
+
+template <typename C>
+void launch_coarse_apply(hipStream_t s, int64_t nrows, const int32_t* row_sub, const int64_t* dof_ptr,
+                         const int64_t* vec_off, const float* P, const float* Cn, int nsub, int nrhs,
+                         const double* scale, float alpha, C* xloc) {
+  int64_t n = nrows * nrhs;
+  if (n > 0)
+    hipLaunchKernelGGL(k_coarse_apply<C>, dim3(nblk(n, 256)), dim3(256), 0, s, nrows, row_sub, dof_ptr, vec_off, P,
+                       Cn, nsub, nrhs, scale, alpha, xloc);
+}
+template void launch_coarse_apply<float2>(hipStream_t, int64_t, const int32_t*, const int64_t*, const int64_t*,
+                                          const float*, const float*, int, int, const double*, float, float2*);
+template void launch_coarse_apply<double2>(hipStream_t, int64_t, const int32_t*, const int64_t*, const int64_t*,
+                                           const float*, const float*, int, int, const double*, float, double2*);
+
+void launch_gapply(hipStream_t s, int nsub, int nrhs, const double* G, const float* in, float* out) {
+  hipLaunchKernelGGL(k_gapply, dim3(nsub, nrhs), dim3(NCO), 0, s, nsub, nrhs, G, in, out);
+}
+void launch_pdp(hipStream_t s, int nsub, const int64_t* dof_ptr, const float* P, const double* D, double* out) {
+  hipLaunchKernelGGL(k_pdp, dim3(nsub, NCO), dim3(NCO), 0, s, dof_ptr, P, D, out);
+}
+
+void launch_gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B,
+                 int ldb, float* C, int ldc, int beta, const float* bias, int act, float* Z, int rnd, int nsplit,
+                 float* work) {
+  if (M <= 0 || N <= 0) return;
+  dim3 grid(nblk(N, 64), nblk(M, 64), 1);
+  float* out = C;
+  int b = beta;
+  if (nsplit > 1) {
+    grid.z = nsplit;
+    out = work;
+    b = 0;
+  }
+#define MXG(TA_, TB_) \
+  hipLaunchKernelGGL((k_gemm<TA_, TB_>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, ldc, b, \
+                     nsplit > 1 ? nullptr : bias, nsplit > 1 ? 0 : act, Z, rnd)
+  if (!ta && !tb) MXG(false, false);
+  else if (!ta && tb) MXG(false, true);
+  else if (ta && !tb) MXG(true, false);
+  else MXG(true, true);
+#undef MXG
+  if (nsplit > 1) {
+    int64_t n = (int64_t)M * ldc;
+    hipLaunchKernelGGL(k_sum_splits, dim3(nblk(n, 256)), dim3(256), 0, s, n, nsplit, work, C, beta);
+  }
+}
+
+void launch_nbr_mean(hipStream_t s, int ngraph, int nsub, int F, const int64_t* nptr, const int32_t* nbrs,
+                     const float* in, float* out) {
+  int64_t n = (int64_t)ngraph * nsub * F;
+  if (n > 0) hipLaunchKernelGGL(k_nbr_mean, dim3(nblk(n, 256)), dim3(256), 0, s, ngraph, nsub, F, nptr, nbrs, in, out);
+}
+void launch_nbr_mean_T(hipStream_t s, int ngraph, int nsub, int F, const int64_t* nptr, const int32_t* nbrs,
+                       const float* in, float* out, int accumulate) {
+  int64_t n = (int64_t)ngraph * nsub * F;
+  if (n > 0)
+    hipLaunchKernelGGL(k_nbr_mean_T, dim3(nblk(n, 256)), dim3(256), 0, s, ngraph, nsub, F, nptr, nbrs, in, out,
+                       accumulate);
+}
+void launch_gelu_back(hipStream_t s, int64_t n, const float* dh, const float* z, float* dz) {
+  if (n > 0) hipLaunchKernelGGL(k_gelu_back, dim3(nblk(n, 256)), dim3(256), 0, s, n, dh, z, dz);
+}
+int mse_blocks() { return 256; }
+void launch_mse(hipStream_t s, int64_t n, const float* out, const float* y, float* d, double* part) {
+  hipLaunchKernelGGL(k_mse, dim3(256), dim3(256), 0, s, n, out, y, d, part);
+}
+void launch_colsum(hipStream_t s, int rows, int F, const float* in, float* out) {
+  hipLaunchKernelGGL(k_colsum, dim3(nblk(F, 128)), dim3(128), 0, s, rows, F, in, out);
+}
+void launch_adam(hipStream_t s, int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2,
+                 float eps, int t) {
+  float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  if (n > 0) hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, s, n, w, g, m, v, lr, b1, b2, eps, c1, c2);
+}
+void launch_gather_rows(hipStream_t s, int nrows_out, int F, const int32_t* graphs, int nsub, const float* src,
+                        float* dst) {
+  int64_t n = (int64_t)nrows_out * F;
+  if (n > 0) hipLaunchKernelGGL(k_gather_rows, dim3(nblk(n, 256)), dim3(256), 0, s, nrows_out, F, graphs, nsub, src, dst);
+}
+void launch_scale_f(hipStream_t s, int64_t n, float* x, float f) {
+  if (n > 0) hipLaunchKernelGGL(k_scale_f, dim3(nblk(n, 256)), dim3(256), 0, s, n, x, f);
+}
+void launch_nonfinite(hipStream_t s, int64_t n, const float* x, int32_t* flag) {
+  if (n > 0) hipLaunchKernelGGL(k_nonfinite, dim3(nblk(n, 256)), dim3(256), 0, s, n, x, flag);
+}
+
+}  // namespace mx

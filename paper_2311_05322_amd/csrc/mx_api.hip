@@ -2,6 +2,8 @@
 // operator assembly, ORAS set-up, and the pseudo-block flexible GMRES driver.
 #include <algorithm>
 #include <chrono>
+#include <functional>
+#include <random>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -103,6 +105,33 @@ __global__ void k_extract_local(int n, int N, const C* A, double2* out) {
   if (idx >= (int64_t)n * n) return;
   int64_t i = idx / n, j = idx % n;
   out[idx] = to_c128(A[i * N + j]);
+}
+
+__global__ void k_scale_d(int n, double* x, double f) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= f;
+}
+__global__ void k_axpy_err(int64_t n, const double2* xs, const double2* x, const double2* mr, double2* t) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) t[i] = make_double2(xs[i].x - x[i].x - mr[i].x, xs[i].y - x[i].y - mr[i].y);
+}
+
+__global__ void k_sub(int64_t n, const double2* a, const double2* b, double2* o) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) o[i] = make_double2(a[i].x - b[i].x, a[i].y - b[i].y);
+}
+// theta_j = (Aq_j^H t_j) / ||Aq_j||^2; z += theta q, w += theta Aq
+__global__ void k_theta_axpy(int64_t n, int nrhs, const double2* dot, const double* nrm, const double2* q,
+                             const double2* aq, double2* z, double2* w) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int j = (int)(i % nrhs);
+  double d = nrm[j] * nrm[j];
+  double2 th = d > 0 ? make_double2(dot[j].x / d, dot[j].y / d) : make_double2(0, 0);
+  if (!(isfinite(th.x) && isfinite(th.y))) th = make_double2(0, 0);
+  double2 a = q[i], b = aq[i];
+  z[i] = make_double2(z[i].x + th.x * a.x - th.y * a.y, z[i].y + th.x * a.y + th.y * a.x);
+  w[i] = make_double2(w[i].x + th.x * b.x - th.y * b.y, w[i].y + th.x * b.y + th.y * b.x);
 }
 
 struct SourceSet {
@@ -222,6 +251,23 @@ struct mx_ctx {
   DBuf<int32_t> a_edge, a_col, t2e, v2t;
   DBuf<int64_t> v2t_ptr;
   DBuf<double2> a_val, U_fwd, gt, rt, gradv, keps;
+  // learned coarse correction
+  bool coarse_geom = false;      // lattices, P and G built for the current decomposition
+  bool coarse_weights = false;   // network weights present
+  bool coarse_use = false;       // opts.coarse of the last set-up
+  bool coarse_off_now = false;   // disabled for the rest of the current solve (fallback)
+  int coarse_fallbacks = 0;
+  double sx = 1.0, sy = 1.0;     // input / output scales of the network
+  DBuf<double2> qv, aq, thdot;
+  DBuf<double> thnrm, thtn;
+  DBuf<char> xloc2;
+  DBuf<float> cP, theta, gtheta, adam_m, adam_v, nbuf, gwork, dsX, dsY;
+  DBuf<double> cbox, cG, cscale, cpdp, msepart;
+  DBuf<int32_t> row_sub, edges_dev, cnbrs, bgraph, cflag;
+  DBuf<int64_t> cnbr_ptr;
+  int64_t nbuf_rows = 0;
+  int64_t ds_graphs = 0, ds_cap = 0;
+  int adam_t = 0;
   // workspace
   int ws_nrhs = 0, ws_m = 0;
   DBuf<double2> V, Z, x, b, r, H, sn, g, y, h1, h2, dotpart, S;
@@ -316,8 +362,157 @@ int ensure_workspace(mx_ctx* c, int nrhs, int m) {
 }
 
 // z = M^{-1} v (one ORAS application), v and z device blocks [ne][nrhs]
+
+// ---------------------------------------------------------------------------
+// learned coarse correction
+// ---------------------------------------------------------------------------
+constexpr int NCO = 192, NIN = 384, NW = 256;
+// parameter layout (floats): W1 b1 W2 b2 W3 b3 W4 b4 Ws1 Wn1 b5 Ws2 Wn2 b6
+struct NetLayout {
+  int64_t W[4], b[4], Ws1, Wn1, b5, Ws2, Wn2, b6, total;
+  NetLayout() {
+    int64_t o = 0;
+    for (int l = 0; l < 4; ++l) {
+      W[l] = o;
+      o += (int64_t)NW * (l == 0 ? NIN : NW);
+      b[l] = o;
+      o += NW;
+    }
+    Ws1 = o; o += (int64_t)NW * NW;
+    Wn1 = o; o += (int64_t)NW * NW;
+    b5 = o; o += NW;
+    Ws2 = o; o += (int64_t)NIN * NW;
+    Wn2 = o; o += (int64_t)NIN * NW;
+    b6 = o; o += NIN;
+    total = o;
+  }
+};
+const NetLayout NL;
+
+// activation buffers inside c->nbuf for `rows` rows
+struct NetBufs {
+  float *X, *Z[4], *H[4], *M4, *Z5, *H5, *M5, *OUT, *dOUT, *dH, *dZ, *dM, *T;
+};
+int net_bufs(mx_ctx* c, int64_t rows, NetBufs& B) {
+  const int64_t per = rows * NW, pin = rows * NIN;
+  const int64_t need = 2 * pin + 8 * per + 3 * per + 2 * pin + 4 * per;
+  if (c->nbuf_rows < rows) {
+    CK(c->nbuf.alloc((size_t)need));
+    c->nbuf_rows = rows;
+  }
+  float* p = c->nbuf.p;
+  B.X = p; p += pin;
+  for (int l = 0; l < 4; ++l) { B.Z[l] = p; p += per; B.H[l] = p; p += per; }
+  B.M4 = p; p += per; B.Z5 = p; p += per; B.H5 = p; p += per;
+  B.M5 = p; p += per;
+  B.OUT = p; p += pin; B.dOUT = p; p += pin;
+  B.dH = p; p += per; B.dZ = p; p += per; B.dM = p; p += per; B.T = p; p += per;
+  CK(c->gwork.alloc((size_t)16 * NIN * NIN));
+  return MX_OK;
+}
+
+// network outputs B.OUT for inputs B.X (rows = ngraph * nsub)
+void net_forward(mx_ctx* c, int ngraph, NetBufs& B) {
+  const int nsub = c->dec.nsub;
+  const int rows = ngraph * nsub;
+  const float* th = c->theta.p;
+  hipStream_t s = c->stream;
+  const float* in = B.X;
+  int K = NIN;
+  for (int l = 0; l < 4; ++l) {
+    launch_gemm(s, false, true, rows, NW, K, in, K, th + NL.W[l], K, B.H[l], NW, 0, th + NL.b[l], 1, B.Z[l], 1, 1,
+                nullptr);
+    in = B.H[l];
+    K = NW;
+  }
+  launch_nbr_mean(s, ngraph, nsub, NW, c->cnbr_ptr.p, c->cnbrs.p, B.H[3], B.M4);
+  launch_gemm(s, false, true, rows, NW, NW, B.H[3], NW, th + NL.Ws1, NW, B.H5, NW, 0, nullptr, 0, nullptr, 1, 1,
+              nullptr);
+  launch_gemm(s, false, true, rows, NW, NW, B.M4, NW, th + NL.Wn1, NW, B.H5, NW, 1, th + NL.b5, 1, B.Z5, 1, 1,
+              nullptr);
+  launch_nbr_mean(s, ngraph, nsub, NW, c->cnbr_ptr.p, c->cnbrs.p, B.H5, B.M5);
+  launch_gemm(s, false, true, rows, NIN, NW, B.H5, NW, th + NL.Ws2, NW, B.OUT, NIN, 0, nullptr, 0, nullptr, 1, 1,
+              nullptr);
+  launch_gemm(s, false, true, rows, NIN, NW, B.M5, NW, th + NL.Wn2, NW, B.OUT, NIN, 1, th + NL.b6, 0, nullptr, 1, 1,
+              nullptr);
+}
+
+// parameter gradient into c->gtheta from dOUT (after net_forward on the same rows)
+void net_backward(mx_ctx* c, int ngraph, NetBufs& B) {
+  const int nsub = c->dec.nsub;
+  const int rows = ngraph * nsub;
+  const float* th = c->theta.p;
+  float* g = c->gtheta.p;
+  hipStream_t s = c->stream;
+  const int ns = 16;
+  float* wk = c->gwork.p;
+  // output layer
+  launch_colsum(s, rows, NIN, B.dOUT, g + NL.b6);
+  launch_gemm(s, true, false, NIN, NW, rows, B.dOUT, NIN, B.H5, NW, g + NL.Ws2, NW, 0, nullptr, 0, nullptr, 1, ns, wk);
+  launch_gemm(s, true, false, NIN, NW, rows, B.dOUT, NIN, B.M5, NW, g + NL.Wn2, NW, 0, nullptr, 0, nullptr, 1, ns, wk);
+  launch_gemm(s, false, false, rows, NW, NIN, B.dOUT, NIN, th + NL.Ws2, NW, B.dH, NW, 0, nullptr, 0, nullptr, 1, 1,
+              nullptr);
+  launch_gemm(s, false, false, rows, NW, NIN, B.dOUT, NIN, th + NL.Wn2, NW, B.dM, NW, 0, nullptr, 0, nullptr, 1, 1,
+              nullptr);
+  launch_nbr_mean_T(s, ngraph, nsub, NW, c->cnbr_ptr.p, c->cnbrs.p, B.dM, B.dH, 1);
+  // message pass 1
+  launch_gelu_back(s, (int64_t)rows * NW, B.dH, B.Z5, B.dZ);
+  launch_colsum(s, rows, NW, B.dZ, g + NL.b5);
+  launch_gemm(s, true, false, NW, NW, rows, B.dZ, NW, B.H[3], NW, g + NL.Ws1, NW, 0, nullptr, 0, nullptr, 1, ns, wk);
+  launch_gemm(s, true, false, NW, NW, rows, B.dZ, NW, B.M4, NW, g + NL.Wn1, NW, 0, nullptr, 0, nullptr, 1, ns, wk);
+  launch_gemm(s, false, false, rows, NW, NW, B.dZ, NW, th + NL.Ws1, NW, B.dH, NW, 0, nullptr, 0, nullptr, 1, 1,
+              nullptr);
+  launch_gemm(s, false, false, rows, NW, NW, B.dZ, NW, th + NL.Wn1, NW, B.dM, NW, 0, nullptr, 0, nullptr, 1, 1,
+              nullptr);
+  launch_nbr_mean_T(s, ngraph, nsub, NW, c->cnbr_ptr.p, c->cnbrs.p, B.dM, B.dH, 1);
+  // MLP layers
+  for (int l = 3; l >= 0; --l) {
+    const int K = l == 0 ? NIN : NW;
+    const float* a = l == 0 ? B.X : B.H[l - 1];
+    launch_gelu_back(s, (int64_t)rows * NW, B.dH, B.Z[l], B.dZ);
+    launch_colsum(s, rows, NW, B.dZ, g + NL.b[l]);
+    launch_gemm(s, true, false, NW, K, rows, B.dZ, NW, a, K, g + NL.W[l], K, 0, nullptr, 0, nullptr, 1, ns, wk);
+    if (l > 0)
+      launch_gemm(s, false, false, rows, NW, NW, B.dZ, NW, th + NL.W[l], NW, B.dH, NW, 0, nullptr, 0, nullptr, 1, 1,
+                  nullptr);
+  }
+}
+
+void launch_sub(hipStream_t s, int64_t n, const double2* a, const double2* b, double2* o) {
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, b, o);
+}
+void launch_theta_axpy(hipStream_t s, int64_t n, int nrhs, const double2* dot, const double* nrm, const double2* q,
+                       const double2* aq, double2* z, double2* w) {
+  hipLaunchKernelGGL(k_theta_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nrhs, dot, nrm, q, aq, z, w);
+}
+
+void launch_scale_rhs_norm(mx_ctx* c, int nrhs) {
+  hipLaunchKernelGGL(k_scale_d, dim3((unsigned)((nrhs + 255) / 256)), dim3(256), 0, c->stream, nrhs, c->cscale.p,
+                     1.0 / std::sqrt((double)c->topo.ne));
+}
+
+// network correction of one preconditioner application (after the local solves)
+template <typename C>
+void coarse_correct(mx_ctx* c, const double2* v, C* xl, int nrhs) {
+  const Decomposition& D = c->dec;
+  hipStream_t s = c->stream;
+  NetBufs B;
+  if (net_bufs(c, (int64_t)nrhs * D.nsub, B) != MX_OK) return;
+  // s_j = ||v_j|| / sqrt(ne)
+  launch_norm(s, c->topo.ne, nrhs, v, c->normpart.p, c->cscale.p);
+  launch_scale_rhs_norm(c, nrhs);
+  launch_pool(s, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, nullptr, v, nrhs, c->cscale.p, B.X);
+  launch_scale_f(s, (int64_t)nrhs * D.nsub * NIN, B.X, (float)(1.0 / c->sx));
+  net_forward(c, nrhs, B);
+  launch_nonfinite(s, (int64_t)nrhs * D.nsub * NIN, B.OUT, c->cflag.p);
+  launch_coarse_apply<C>(s, D.dof_ptr[D.nsub], c->row_sub.p, c->dof_ptr.p, c->vec_off.p, c->cP.p, B.OUT, D.nsub,
+                         nrhs, c->cscale.p, (float)c->sy, xl);
+}
+
+// z = M^{-1} v; with the learned term active it is added to z, or, when q is
+// given, returned separately in q (z then holds plain ORAS)
 template <typename R>
-void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs) {
+void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr) {
   typedef C_t<R> C;
   const Decomposition& D = c->dec;
   const int64_t nrows = D.vec_off[D.nsub];
@@ -327,20 +522,36 @@ void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs) {
   c->prof.end(K_RESTRICT);
   launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, xl, D.nsub, nrhs,
                  &c->prof);
+  const bool coarse = c->coarse_use && !c->coarse_off_now && c->coarse_geom && c->coarse_weights;
+  C* xq = nullptr;
+  if (coarse) {
+    c->prof.begin(K_COARSE);
+    if (q) {
+      // learned term in its own local buffer, prolonged separately into q
+      xq = (C*)c->xloc2.p;
+      launch_fill_zero<C>(c->stream, nrows * nrhs, xq);
+      coarse_correct<C>(c, v, xq, nrhs);
+    } else {
+      coarse_correct<C>(c, v, xl, nrhs);
+    }
+    c->prof.end(K_COARSE);
+  }
   c->prof.begin(K_PROLONG);
   launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, z);
+  if (xq) launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, q);
   for (int col = 0; col < D.ncolour; ++col) {
     int64_t a = D.pcol_ptr[col], b = D.pcol_ptr[col + 1];
     launch_prolong<C>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xl, z, nrhs);
+    if (xq) launch_prolong<C>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xq, q, nrhs);
   }
   c->prof.end(K_PROLONG);
 }
 
-int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs) {
+int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr) {
   if (c->precision == MX_PREC_C64)
-    apply_precond_t<float>(c, v, z, nrhs);
+    apply_precond_t<float>(c, v, z, nrhs, q);
   else
-    apply_precond_t<double>(c, v, z, nrhs);
+    apply_precond_t<double>(c, v, z, nrhs, q);
   MX_HIP_CHECK(hipGetLastError());
   return MX_OK;
 }
@@ -354,7 +565,9 @@ int spmm(mx_ctx* c, const double2* X, double2* Y, int nrhs) {
 }
 
 // Right-preconditioned pseudo-block FGMRES on b (device) -> x (device, ctx->x).
-int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info) {
+// on_cycle (optional) runs at the start of every restart cycle with the
+// current iterate in c->x and its true residual in c->r.
+int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::function<int()>* on_cycle = nullptr) {
   const int m = c->ws_m;
   const int64_t ne = c->topo.ne;
   const int64_t blk = ne * (int64_t)nrhs;
@@ -380,7 +593,25 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info) {
     return MX_OK;
   };
   CK(true_residual());
+  c->coarse_off_now = false;
+  const bool coarse_on = c->coarse_use && c->coarse_geom && c->coarse_weights;
+  if (coarse_on) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, 1, c->cflag.p);
+    CK(c->qv.alloc(blk));
+    CK(c->aq.alloc(blk));
+    CK(c->thdot.alloc(nrhs));
+    CK(c->thnrm.alloc(nrhs));
+    CK(c->xloc2.alloc((size_t)c->dec.vec_off[c->dec.nsub] * nrhs * elem_bytes(c->precision)));
+  }
+  int fallback = 0;
+  int judge_steps = 0;
+  double judge_sum = 0;
+  std::vector<double2> hj_dot(nrhs);
+  std::vector<double> hj_aq(nrhs), hj_t(nrhs);
+  if (coarse_on) CK(c->thtn.alloc(nrhs));
   for (;;) {
+    if (on_cycle) CK((*on_cycle)());
+    std::vector<double> rr_start(rr);
     bool all = true;
     for (int j = 0; j < nrhs; ++j) {
       if (rr[j] <= rtol) done[j] = 1;
@@ -402,8 +633,23 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info) {
       double2* vk = c->V.p + k * blk;
       double2* zk = c->Z.p + k * blk;
       double2* w = c->V.p + (k + 1) * blk;
-      CK(apply_precond(c, vk, zk, nrhs));
-      CK(spmm(c, zk, w, nrhs));
+      bool judged = false;
+      if (coarse_on && !c->coarse_off_now) {
+        // plain ORAS judges the learned term: z = M^{-1} v + theta q with the
+        // per-transmitter theta minimising ||v - A z||
+        CK(apply_precond(c, vk, zk, nrhs, c->qv.p));
+        CK(spmm(c, zk, w, nrhs));
+        CK(spmm(c, c->qv.p, c->aq.p, nrhs));
+        launch_sub(s, blk, vk, w, c->r.p);
+        launch_dot(s, ne, nrhs, c->aq.p, blk, 1, c->r.p, c->dotpart.p, c->thdot.p);
+        launch_norm(s, ne, nrhs, c->aq.p, c->normpart.p, c->thnrm.p);
+        launch_norm(s, ne, nrhs, c->r.p, c->normpart.p, c->thtn.p);
+        launch_theta_axpy(s, blk, nrhs, c->thdot.p, c->thnrm.p, c->qv.p, c->aq.p, zk, w);
+        judged = true;
+      } else {
+        CK(apply_precond(c, vk, zk, nrhs));
+        CK(spmm(c, zk, w, nrhs));
+      }
       c->prof.begin(K_CGS);
       launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h1.p);
       launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w);
@@ -415,12 +661,50 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info) {
                     c->conv.p, c->kdone.p, c->res.p);
       c->prof.end(K_CGS);
       MX_HIP_CHECK(hipMemcpyAsync(c->h_conv, c->conv.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      if (coarse_on && !c->coarse_off_now)
+        MX_HIP_CHECK(hipMemcpyAsync(c->h_kd, c->cflag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      if (judged) {
+        MX_HIP_CHECK(hipMemcpyAsync(hj_dot.data(), c->thdot.p, nrhs * sizeof(double2), hipMemcpyDeviceToHost, s));
+        MX_HIP_CHECK(hipMemcpyAsync(hj_aq.data(), c->thnrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        MX_HIP_CHECK(hipMemcpyAsync(hj_t.data(), c->thtn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      }
       CK(sync(c));
+      if (judged) {
+        // squared reduction of the local preconditioned residual the learned
+        // term brings: ||v - A(z1 + theta q)||^2 / ||v - A z1||^2
+        double red = 0;
+        int cnt = 0;
+        for (int j = 0; j < nrhs; ++j) {
+          const double d = hj_aq[j] * hj_t[j];
+          if (d > 0) {
+            const double a = std::hypot(hj_dot[j].x, hj_dot[j].y) / d;
+            red += 1.0 - a * a;
+            ++cnt;
+          }
+        }
+        judge_sum += cnt ? red / cnt : 1.0;
+        if (++judge_steps == 4 && judge_sum / judge_steps > 0.95 * 0.95) {
+          // the learned term removes less than 5% of what plain ORAS leaves: drop it
+          c->coarse_off_now = true;
+          fallback = 3;
+        }
+      }
+      if (coarse_on && !c->coarse_off_now && c->h_kd[0] != 0) {
+        // non-finite network output: drop this cycle, continue with plain ORAS
+        c->coarse_off_now = true;
+        fallback = 1;
+        ksteps = -1;
+        break;
+      }
       ksteps = k + 1;
       ++total;
       int nconv = 0;
       for (int j = 0; j < nrhs; ++j) nconv += c->h_conv[j] != 0 || done[j];
       if (nconv == nrhs || total >= c->maxit) break;
+    }
+    if (ksteps < 0) {
+      CK(true_residual());
+      continue;
     }
     launch_lsq(s, ksteps, m, nrhs, c->H.p, c->g.p, c->conv.p, c->kdone.p, c->y.p);
     launch_xupdate(s, ne, nrhs, c->Z.p, blk, c->y.p, c->kdone.p, c->x.p);
@@ -431,7 +715,19 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info) {
     for (int j = 0; j < nrhs; ++j)
       if (!done[j]) iters[j] += c->h_kd[j];
     ++cycles;
+    if (coarse_on && !c->coarse_off_now) {
+      // plain one-level Schwarz judges the learned term: a full cycle that does
+      // not reduce the worst residual by 10% switches it off for this solve
+      double worst = 0;
+      for (int j = 0; j < nrhs; ++j)
+        if (!done[j] && rr_start[j] > 0) worst = std::max(worst, rr[j] / rr_start[j]);
+      if (worst > 0.9) {
+        c->coarse_off_now = true;
+        fallback = 2;
+      }
+    }
   }
+  if (fallback) c->coarse_fallbacks++;
   auto t1 = std::chrono::steady_clock::now();
   if (info) {
     int mx_ = 0;
@@ -442,9 +738,99 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info) {
     }
     info->iters_max = mx_;
     info->cycles = cycles;
+    info->fallback = fallback;
     info->t_iter = std::chrono::duration<double>(t1 - t0).count();
   }
   return rc;
+}
+
+
+// host Cholesky inverse of an SPD n x n matrix (row-major, in place)
+bool spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> L(A.size(), 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0)) return false;
+    d = std::sqrt(d);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = v / d;
+    }
+  }
+  // inverse = L^{-T} L^{-1}: solve column by column
+  std::vector<double> X((size_t)n * n, 0.0), y(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double v = i == c ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * y[k];
+      y[i] = v / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < n; ++k) v -= L[(size_t)k * n + i] * X[(size_t)k * n + c];
+      X[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+    }
+  }
+  A.swap(X);
+  return true;
+}
+
+// lattices, prolongations and least-squares operators of the current decomposition
+int coarse_prepare(mx_ctx* c) {
+  const Topology& T = c->topo;
+  const Decomposition& D = c->dec;
+  const int nsub = D.nsub;
+  const int64_t nrows = D.dof_ptr[nsub];
+  std::vector<int32_t> rs(nrows);
+  for (int i = 0; i < nsub; ++i)
+    for (int64_t k = D.dof_ptr[i]; k < D.dof_ptr[i + 1]; ++k) rs[k] = i;
+  std::vector<double> box(6 * (size_t)nsub);
+  for (int i = 0; i < nsub; ++i) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = D.tet_ptr[i]; k < D.tet_ptr[i + 1]; ++k)
+      for (int q = 0; q < 4; ++q) {
+        const double* x = &T.xyz[3 * (size_t)T.ts[4 * (size_t)D.tets[k] + q]];
+        for (int d = 0; d < 3; ++d) { lo[d] = std::min(lo[d], x[d]); hi[d] = std::max(hi[d], x[d]); }
+      }
+    for (int d = 0; d < 3; ++d) { box[6 * i + d] = lo[d]; box[6 * i + 3 + d] = hi[d]; }
+  }
+  CK(c->row_sub.upload(rs, c->stream));
+  CK(c->cbox.upload(box, c->stream));
+  CK(c->edges_dev.upload(T.edges, c->stream));
+  CK(c->cnbr_ptr.upload(D.nbr_ptr, c->stream));
+  CK(c->cnbrs.upload(D.nbrs.empty() ? std::vector<int32_t>(1, 0) : D.nbrs, c->stream));
+  CK(c->cP.alloc((size_t)nrows * NCO));
+  launch_coarse_P(c->stream, nrows, c->row_sub.p, c->dofs.p, c->edges_dev.p, c->xyz.p, c->cbox.p, c->cP.p);
+  CK(c->cpdp.alloc((size_t)nsub * NCO * NCO));
+  CK(c->p_w.n ? MX_OK : MX_OK);
+  DBuf<double> Dw;
+  CK(Dw.upload(D.D, c->stream));
+  launch_pdp(c->stream, nsub, c->dof_ptr.p, c->cP.p, Dw.p, c->cpdp.p);
+  MX_HIP_CHECK(hipGetLastError());
+  std::vector<double> G((size_t)nsub * NCO * NCO);
+  MX_HIP_CHECK(hipMemcpyAsync(G.data(), c->cpdp.p, G.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  CK(sync(c));
+  bool ok = true;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < nsub; ++i) {
+    std::vector<double> A(G.begin() + (size_t)i * NCO * NCO, G.begin() + (size_t)(i + 1) * NCO * NCO);
+    double tr = 0;
+    for (int k = 0; k < NCO; ++k) tr += A[(size_t)k * NCO + k];
+    const double lam = 1e-6 * tr / NCO;
+    for (int k = 0; k < NCO; ++k) A[(size_t)k * NCO + k] += lam;
+    if (!spd_inverse(A, NCO)) ok = false;
+    std::copy(A.begin(), A.end(), G.begin() + (size_t)i * NCO * NCO);
+  }
+  if (!ok) return set_err(MX_EINVAL, "coarse least-squares matrix is not positive definite");
+  CK(c->cG.upload(G, c->stream));
+  CK(c->cscale.alloc(256));
+  CK(c->cflag.alloc(4));
+  CK(sync(c));
+  c->coarse_geom = true;
+  return MX_OK;
 }
 
 int fill_pool(mx_ctx* c) {
@@ -626,7 +1012,7 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
 int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_opts* opts) {
   if (!c) return set_err(MX_EINVAL, "NULL context");
   if (!c->assembled) return set_err(MX_ESTATE, "mx_assemble must come first");
-  mx_schwarz_opts o = {MX_PREC_C128, 30, 2000, 1};
+  mx_schwarz_opts o = {MX_PREC_C128, 30, 2000, 1, 0};
   if (opts) o = *opts;
   if (o.precision != MX_PREC_C128 && o.precision != MX_PREC_C64) return set_err(MX_EINVAL, "bad precision");
   CK(use_device(c));
@@ -667,6 +1053,8 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     CK(c->pswap.alloc((size_t)nsub * (2 * lu_max_swap_rows() + 1)));
     c->have_dec = true;
     c->ws_nrhs = 0;
+    c->coarse_geom = false;
+    c->ds_graphs = 0;
   }
   const Decomposition& D = c->dec;
   c->local_ready = c->factored = false;
@@ -715,6 +1103,8 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
                                       std::to_string(st[i] - 1));
     c->factored = true;
   }
+  c->coarse_use = o.coarse != 0;
+  if (c->coarse_use && !c->coarse_geom) CK(coarse_prepare(c));
   CK(sync(c));
   return MX_OK;
 }
@@ -971,6 +1361,257 @@ int mx_get_local_matrix(mx_ctx* c, int32_t i, mx_c128* B) {
                        (const double2*)c->factors.p + D.mat_off[i], tmp.p);
   MX_HIP_CHECK(hipGetLastError());
   MX_HIP_CHECK(hipMemcpyAsync(B, tmp.p, (size_t)n * n * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+
+int mx_coarse_init(mx_ctx* c, uint64_t seed) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  CK(use_device(c));
+  std::vector<float> th(NL.total, 0.f);
+  std::mt19937_64 rng(seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  auto fill = [&](int64_t off, int rows, int cols, double scale) {
+    for (int64_t k = 0; k < (int64_t)rows * cols; ++k) th[off + k] = (float)(scale * nd(rng) / std::sqrt((double)cols));
+  };
+  for (int l = 0; l < 4; ++l) fill(NL.W[l], NW, l == 0 ? NIN : NW, 1.0);
+  fill(NL.Ws1, NW, NW, 1.0);
+  fill(NL.Wn1, NW, NW, 1.0);
+  fill(NL.Ws2, NIN, NW, 0.1);
+  fill(NL.Wn2, NIN, NW, 0.1);
+  CK(c->theta.upload(th, c->stream));
+  CK(c->gtheta.alloc(NL.total));
+  CK(c->adam_m.alloc(NL.total));
+  CK(c->adam_v.alloc(NL.total));
+  std::vector<float> z(NL.total, 0.f);
+  MX_HIP_CHECK(hipMemcpyAsync(c->adam_m.p, z.data(), z.size() * 4, hipMemcpyHostToDevice, c->stream));
+  MX_HIP_CHECK(hipMemcpyAsync(c->adam_v.p, z.data(), z.size() * 4, hipMemcpyHostToDevice, c->stream));
+  c->adam_t = 0;
+  c->sx = c->sy = 1.0;
+  c->coarse_weights = true;
+  return sync(c);
+}
+
+int64_t mx_coarse_num_params(void) { return NL.total; }
+
+int mx_coarse_set_weights(mx_ctx* c, const float* theta, int64_t n, double in_scale, double out_scale) {
+  if (!c || !theta) return set_err(MX_EINVAL, "NULL argument");
+  if (n != NL.total) return set_err(MX_EINVAL, "expected " + std::to_string(NL.total) + " parameters");
+  if (!(in_scale > 0) || !(out_scale > 0)) return set_err(MX_EINVAL, "scales must be positive");
+  CK(use_device(c));
+  if (!c->coarse_weights) CK(mx_coarse_init(c, 0));
+  MX_HIP_CHECK(hipMemcpyAsync(c->theta.p, theta, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  c->sx = in_scale;
+  c->sy = out_scale;
+  return sync(c);
+}
+
+int mx_coarse_get_weights(mx_ctx* c, float* theta, int64_t n, double* in_scale, double* out_scale) {
+  if (!c || !theta) return set_err(MX_EINVAL, "NULL argument");
+  if (!c->coarse_weights) return set_err(MX_ESTATE, "no network weights");
+  if (n != NL.total) return set_err(MX_EINVAL, "expected " + std::to_string(NL.total) + " parameters");
+  CK(use_device(c));
+  MX_HIP_CHECK(hipMemcpyAsync(theta, c->theta.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  if (in_scale) *in_scale = c->sx;
+  if (out_scale) *out_scale = c->sy;
+  return sync(c);
+}
+
+int mx_coarse_features(mx_ctx* c, const mx_c128* v, int32_t nrhs, float* X) {
+  if (!c || !v || !X || nrhs <= 0 || nrhs > 256) return set_err(MX_EINVAL, "bad arguments");
+  if (!c->coarse_geom) return set_err(MX_ESTATE, "needs mx_setup_schwarz with opts.coarse = 1");
+  CK(use_device(c));
+  const Decomposition& D = c->dec;
+  DBuf<double2> vin;
+  DBuf<float> Xd;
+  CK(vin.alloc((size_t)c->topo.ne * nrhs));
+  CK(Xd.alloc((size_t)nrhs * D.nsub * NIN));
+  CK(copy_in(c, vin.p, v, (size_t)c->topo.ne * nrhs * sizeof(double2)));
+  CK(c->normpart.alloc((size_t)dot_blocks(c->topo.ne) * nrhs));
+  launch_norm(c->stream, c->topo.ne, nrhs, vin.p, c->normpart.p, c->cscale.p);
+  launch_scale_rhs_norm(c, nrhs);
+  launch_pool(c->stream, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, nullptr, vin.p, nrhs, c->cscale.p, Xd.p);
+  MX_HIP_CHECK(hipGetLastError());
+  MX_HIP_CHECK(hipMemcpyAsync(X, Xd.p, (size_t)nrhs * D.nsub * NIN * 4, hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+int mx_coarse_forward(mx_ctx* c, const float* X, int32_t ngraph, float* out) {
+  if (!c || !X || !out || ngraph <= 0) return set_err(MX_EINVAL, "bad arguments");
+  if (!c->have_dec || !c->coarse_geom || !c->coarse_weights) return set_err(MX_ESTATE, "needs coarse set-up and weights");
+  CK(use_device(c));
+  const int64_t rows = (int64_t)ngraph * c->dec.nsub;
+  NetBufs B;
+  CK(net_bufs(c, rows, B));
+  MX_HIP_CHECK(hipMemcpyAsync(B.X, X, rows * NIN * 4, hipMemcpyHostToDevice, c->stream));
+  net_forward(c, ngraph, B);
+  MX_HIP_CHECK(hipGetLastError());
+  MX_HIP_CHECK(hipMemcpyAsync(out, B.OUT, rows * NIN * 4, hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+double mse_loss(mx_ctx* c, int64_t n, NetBufs& B, const float* Ydev) {
+  (void)c->msepart.alloc(mse_blocks());
+  launch_mse(c->stream, n, B.OUT, Ydev, B.dOUT, c->msepart.p);
+  std::vector<double> part(mse_blocks());
+  (void)hipMemcpyAsync(part.data(), c->msepart.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  double sum = 0;
+  for (double v : part) sum += v;
+  return sum / (double)n;
+}
+
+int mx_coarse_loss_grad(mx_ctx* c, const float* X, const float* Y, int32_t ngraph, double* loss, float* grad) {
+  if (!c || !X || !Y || !loss || !grad || ngraph <= 0) return set_err(MX_EINVAL, "bad arguments");
+  if (!c->have_dec || !c->coarse_geom || !c->coarse_weights) return set_err(MX_ESTATE, "needs coarse set-up and weights");
+  CK(use_device(c));
+  const int64_t rows = (int64_t)ngraph * c->dec.nsub;
+  NetBufs B;
+  CK(net_bufs(c, rows, B));
+  MX_HIP_CHECK(hipMemcpyAsync(B.X, X, rows * NIN * 4, hipMemcpyHostToDevice, c->stream));
+  MX_HIP_CHECK(hipMemcpyAsync(B.dOUT, Y, rows * NIN * 4, hipMemcpyHostToDevice, c->stream));
+  net_forward(c, ngraph, B);
+  *loss = mse_loss(c, rows * NIN, B, B.dOUT);
+  net_backward(c, ngraph, B);
+  MX_HIP_CHECK(hipGetLastError());
+  MX_HIP_CHECK(hipMemcpyAsync(grad, c->gtheta.p, NL.total * 4, hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+int mx_coarse_clear(mx_ctx* c) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  c->ds_graphs = 0;
+  return MX_OK;
+}
+
+int mx_coarse_collect(mx_ctx* c, const mx_sources* tx, int32_t snap_every, int32_t max_snapshots, double rtol_exact,
+                      int32_t* nsnap) {
+  if (!c || !tx || snap_every < 1 || max_snapshots < 1 || !(rtol_exact > 0)) return set_err(MX_EINVAL, "bad arguments");
+  if (!c->factored) return set_err(MX_ESTATE, "mx_setup_schwarz (with factor=1) must come first");
+  CK(use_device(c));
+  if (!c->coarse_geom) CK(coarse_prepare(c));
+  const Decomposition& D = c->dec;
+  const int ntx = tx->n;
+  if (ntx > 256) return set_err(MX_EINVAL, "at most 256 transmitters");
+  CK(build_sources(c, tx, c->tx));
+  {
+    std::vector<int32_t> colv(c->tx.edge.size());
+    for (int j = 0; j < ntx; ++j)
+      for (int64_t k = c->tx.ptr[j]; k < c->tx.ptr[j + 1]; ++k) colv[k] = j;
+    CK(c->s_edge.upload(c->tx.edge, c->stream));
+    CK(c->s_col.upload(colv, c->stream));
+    CK(c->s_val.upload(c->tx.val, c->stream));
+  }
+  const bool use_save = c->coarse_use;
+  c->coarse_use = false;
+  CK(ensure_workspace(c, ntx, c->restart));
+  const int64_t blk = c->topo.ne * (int64_t)ntx;
+  launch_fill_zero<double2>(c->stream, blk, c->b.p);
+  launch_scatter_rhs(c->stream, (int64_t)c->tx.edge.size(), c->s_edge.p, c->s_col.p, c->s_val.p,
+                     make_double2(0.0, -c->omega_mu0), ntx, c->b.p);
+  int rc = fgmres(c, ntx, rtol_exact, nullptr);
+  if (rc != MX_OK) { c->coarse_use = use_save; return rc; }
+  DBuf<double2> xs;
+  CK(xs.alloc(blk));
+  MX_HIP_CHECK(hipMemcpyAsync(xs.p, c->x.p, blk * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+  // grow the data set
+  const int64_t per_graph = (int64_t)D.nsub * NIN;
+  const int64_t need = c->ds_graphs + (int64_t)max_snapshots * ntx;
+  if (need > c->ds_cap) {
+    DBuf<float> nx, ny;
+    CK(nx.alloc((size_t)need * per_graph));
+    CK(ny.alloc((size_t)need * per_graph));
+    if (c->ds_graphs) {
+      MX_HIP_CHECK(hipMemcpyAsync(nx.p, c->dsX.p, c->ds_graphs * per_graph * 4, hipMemcpyDeviceToDevice, c->stream));
+      MX_HIP_CHECK(hipMemcpyAsync(ny.p, c->dsY.p, c->ds_graphs * per_graph * 4, hipMemcpyDeviceToDevice, c->stream));
+    }
+    CK(sync(c));
+    std::swap(c->dsX.p, nx.p); std::swap(c->dsX.n, nx.n);
+    std::swap(c->dsY.p, ny.p); std::swap(c->dsY.n, ny.n);
+    c->ds_cap = need;
+  }
+  NetBufs B;
+  CK(net_bufs(c, (int64_t)ntx * D.nsub, B));
+  CK(ensure_workspace(c, ntx, snap_every));
+  DBuf<double> Dw;
+  CK(Dw.upload(D.D, c->stream));
+  int count = 0;
+  std::function<int()> cb = [&]() -> int {
+    if (count >= max_snapshots) return MX_OK;
+    hipStream_t s = c->stream;
+    float* Xo = c->dsX.p + c->ds_graphs * per_graph;
+    float* Yo = c->dsY.p + c->ds_graphs * per_graph;
+    launch_norm(s, c->topo.ne, ntx, c->r.p, c->normpart.p, c->cscale.p);
+    launch_scale_rhs_norm(c, ntx);
+    launch_pool(s, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, nullptr, c->r.p, ntx, c->cscale.p, Xo);
+    double2* mr = c->Z.p;
+    double2* t = c->V.p + blk;
+    CK(apply_precond(c, c->r.p, mr, ntx));
+    hipLaunchKernelGGL(k_axpy_err, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, blk, xs.p, c->x.p, mr, t);
+    launch_pool(s, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, Dw.p, t, ntx, c->cscale.p, B.X);
+    launch_gapply(s, D.nsub, ntx, c->cG.p, B.X, Yo);
+    MX_HIP_CHECK(hipGetLastError());
+    c->ds_graphs += ntx;
+    ++count;
+    return MX_OK;
+  };
+  rc = fgmres(c, ntx, rtol_exact, nullptr, &cb);
+  c->coarse_use = use_save;
+  CK(ensure_workspace(c, ntx, c->restart));
+  if (nsnap) *nsnap = count;
+  CK(sync(c));
+  return rc == MX_ENOTCONV ? MX_OK : rc;
+}
+
+int mx_coarse_train(mx_ctx* c, int32_t epochs, int32_t batch_graphs, double lr, uint64_t seed, double* loss_hist) {
+  if (!c || epochs < 1 || batch_graphs < 1 || !(lr > 0)) return set_err(MX_EINVAL, "bad arguments");
+  if (!c->coarse_weights) return set_err(MX_ESTATE, "call mx_coarse_init first");
+  if (c->ds_graphs < 1) return set_err(MX_ESTATE, "no training data (mx_coarse_collect)");
+  CK(use_device(c));
+  const Decomposition& D = c->dec;
+  const int64_t per_graph = (int64_t)D.nsub * NIN;
+  // input / output scales from (up to) the first 64 graphs
+  {
+    const int64_t ng = std::min<int64_t>(64, c->ds_graphs);
+    std::vector<float> hx(ng * per_graph), hy(ng * per_graph);
+    MX_HIP_CHECK(hipMemcpyAsync(hx.data(), c->dsX.p, hx.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    MX_HIP_CHECK(hipMemcpyAsync(hy.data(), c->dsY.p, hy.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    CK(sync(c));
+    double a = 0, b = 0;
+    for (size_t k = 0; k < hx.size(); ++k) { a += (double)hx[k] * hx[k]; b += (double)hy[k] * hy[k]; }
+    c->sx = std::sqrt(a / hx.size());
+    c->sy = std::sqrt(b / hy.size());
+    if (!(c->sx > 0)) c->sx = 1;
+    if (!(c->sy > 0)) c->sy = 1;
+  }
+  const int bg = (int)std::min<int64_t>(batch_graphs, c->ds_graphs);
+  NetBufs B;
+  CK(net_bufs(c, (int64_t)bg * D.nsub, B));
+  CK(c->bgraph.alloc(bg));
+  std::mt19937_64 rng(seed);
+  std::vector<int32_t> perm(c->ds_graphs);
+  for (int64_t g = 0; g < c->ds_graphs; ++g) perm[g] = (int32_t)g;
+  for (int ep = 0; ep < epochs; ++ep) {
+    std::shuffle(perm.begin(), perm.end(), rng);
+    double lsum = 0;
+    int nb = 0;
+    for (int64_t b0 = 0; b0 + bg <= c->ds_graphs; b0 += bg) {
+      MX_HIP_CHECK(hipMemcpyAsync(c->bgraph.p, perm.data() + b0, bg * 4, hipMemcpyHostToDevice, c->stream));
+      const int rows = bg * D.nsub;
+      launch_gather_rows(c->stream, rows, NIN, c->bgraph.p, D.nsub, c->dsX.p, B.X);
+      launch_gather_rows(c->stream, rows, NIN, c->bgraph.p, D.nsub, c->dsY.p, B.dOUT);
+      launch_scale_f(c->stream, (int64_t)rows * NIN, B.X, (float)(1.0 / c->sx));
+      launch_scale_f(c->stream, (int64_t)rows * NIN, B.dOUT, (float)(1.0 / c->sy));
+      net_forward(c, bg, B);
+      lsum += mse_loss(c, (int64_t)rows * NIN, B, B.dOUT);
+      net_backward(c, bg, B);
+      launch_adam(c->stream, NL.total, c->theta.p, c->gtheta.p, c->adam_m.p, c->adam_v.p, (float)lr, 0.9f, 0.999f,
+                  1e-8f, ++c->adam_t);
+      MX_HIP_CHECK(hipGetLastError());
+      ++nb;
+    }
+    if (loss_hist) loss_hist[ep] = nb ? lsum / nb : 0.0;
+  }
   return sync(c);
 }
 

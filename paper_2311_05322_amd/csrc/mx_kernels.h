@@ -12,7 +12,8 @@ template <typename R> using C_t = typename cplx_t<R>::type;
 // Kernel classes (same numbering as the MX_K_* enum of mx.h).
 enum KClass {
   K_LU_PANEL = 0, K_LU_ROWPANEL = 1, K_LU_UPDATE = 2, K_LU_INV = 3, K_TRSM_LOWER = 4, K_TRSM_UPPER = 5,
-  K_SPMM = 6, K_RESTRICT = 7, K_PROLONG = 8, K_CGS = 9, K_ASSEMBLE = 10, K_LOCAL = 11, K_NCLASS = 16
+  K_SPMM = 6, K_RESTRICT = 7, K_PROLONG = 8, K_CGS = 9, K_ASSEMBLE = 10, K_LOCAL = 11, K_COARSE = 12,
+  K_NCLASS = 16
 };
 
 // Optional launch bracketing used for per-kernel-class device timing.
@@ -44,6 +45,35 @@ void launch_grad_tet(hipStream_t s, int32_t nt, const int32_t* ts, const double*
                      double2* rt);
 void launch_grad_vertex(hipStream_t s, int32_t nv, const int64_t* v2t_ptr, const int32_t* v2t, const int32_t* ts,
                         const double2* gt, const double2* rt, double reg, double2* grad, double2* keps);
+
+// learned coarse correction
+void launch_coarse_P(hipStream_t s, int64_t nrows, const int32_t* row_sub, const int32_t* dofs, const int32_t* edges,
+                     const double* xyz, const double* box, float* P);
+void launch_pool(hipStream_t s, int nsub, const int64_t* dof_ptr, const int32_t* dofs, const float* P,
+                 const double* wts, const double2* v, int nrhs, const double* scale, float* X);
+template <typename C>
+void launch_coarse_apply(hipStream_t s, int64_t nrows, const int32_t* row_sub, const int64_t* dof_ptr,
+                         const int64_t* vec_off, const float* P, const float* Cn, int nsub, int nrhs,
+                         const double* scale, float alpha, C* xloc);
+void launch_gapply(hipStream_t s, int nsub, int nrhs, const double* G, const float* in, float* out);
+void launch_pdp(hipStream_t s, int nsub, const int64_t* dof_ptr, const float* P, const double* D, double* out);
+void launch_gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B,
+                 int ldb, float* C, int ldc, int beta, const float* bias, int act, float* Z, int rnd, int nsplit,
+                 float* work);
+void launch_nbr_mean(hipStream_t s, int ngraph, int nsub, int F, const int64_t* nptr, const int32_t* nbrs,
+                     const float* in, float* out);
+void launch_nbr_mean_T(hipStream_t s, int ngraph, int nsub, int F, const int64_t* nptr, const int32_t* nbrs,
+                       const float* in, float* out, int accumulate);
+void launch_gelu_back(hipStream_t s, int64_t n, const float* dh, const float* z, float* dz);
+int mse_blocks();
+void launch_mse(hipStream_t s, int64_t n, const float* out, const float* y, float* d, double* part);
+void launch_colsum(hipStream_t s, int rows, int F, const float* in, float* out);
+void launch_adam(hipStream_t s, int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2,
+                 float eps, int t);
+void launch_gather_rows(hipStream_t s, int nrows_out, int F, const int32_t* graphs, int nsub, const float* src,
+                        float* dst);
+void launch_scale_f(hipStream_t s, int64_t n, float* x, float f);
+void launch_nonfinite(hipStream_t s, int64_t n, const float* x, int32_t* flag);
 
 // operator application and Schwarz transfer
 void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t* col, const double2* val,

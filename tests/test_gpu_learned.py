@@ -1,0 +1,102 @@
+"""Learned coarse correction on the GPU (through the C ABI) against the
+oracle: lattice pooling, the bf16 network forward pass and its parameter
+gradient (oracle in FP64 with bf16 rounding emulated at the same points),
+training from the plain solver's residual/error pairs, and solves with the
+learned term that still meet the residual tolerance and the direct solution."""
+import numpy as np
+import pytest
+
+import workload
+from oracle import fem, learned, schwarz
+
+mx = pytest.importorskip("paper_2311_05322_amd")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    print("[case] chamber c=20mm nsub=16 overlap=1", flush=True)
+    p = workload.chamber_problem(c=0.02, nsub=16, overlap=1, nsrc=8)
+    t = fem.Topology(p.xyz, p.tet)
+    dec = schwarz.Decomposition(t, 16, 1)
+    ctx = mx.Context(0)
+    ctx.assemble(p.xyz, p.tet, p.eps, p.eps_kind, p.freq, p.eps_b)
+    ctx.setup_schwarz(16, 1, precision=mx.MX_PREC_C64, coarse=True)
+    ctx.coarse_init(seed=4)
+    yield p, t, dec, ctx
+    ctx.close()
+
+
+def test_pooled_features(setup):
+    p, t, dec, ctx = setup
+    co = learned.Coarse(dec)
+    v = workload.seeded_complex((t.ne, 5), 3)
+    X = ctx.coarse_features(v)
+    ref = co.pool(v)
+    assert np.abs(X - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def test_network_forward_and_gradient(setup):
+    """Tolerances: both sides round the same operands to bf16, but the GPU
+    rounds an FP32-accumulated value and the oracle an FP64 one, so an operand
+    lying at a rounding boundary can differ by one bf16 ulp (2^-8 relative);
+    the message-passing layers spread such a flip over its whole graph. A few
+    flips perturb the outputs by ~1e-3 of their norm, far below any modelling
+    error (a wrong weight, sign or index gives O(1))."""
+    p, t, dec, ctx = setup
+    nb = [dec.neighbours(i) for i in range(dec.nsub)]
+    theta, _, _ = ctx.coarse_weights()
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((3, dec.nsub, 384)).astype(np.float32)
+    Y = rng.standard_normal((3, dec.nsub, 384)).astype(np.float32)
+    out = ctx.coarse_forward(X)
+    ref, _ = learned.forward(theta.astype(np.float64), X.astype(np.float64), nb, use_bf16=True)
+    assert np.linalg.norm(out - ref) <= 5e-3 * np.linalg.norm(ref)
+    loss, g = ctx.coarse_loss_grad(X, Y)
+    lref, gref = learned.loss_and_grad(theta.astype(np.float64), X.astype(np.float64), Y.astype(np.float64), nb,
+                                       use_bf16=True)
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    assert np.linalg.norm(g - gref) <= 1e-2 * np.linalg.norm(gref)
+    cos = g @ gref / (np.linalg.norm(g) * np.linalg.norm(gref))
+    assert cos > 0.9999
+    # without rounding both sides are plain FP32 / FP64 arithmetic of the same network
+    ref32, _ = learned.forward(theta.astype(np.float64), X.astype(np.float64), nb, use_bf16=False)
+    assert np.linalg.norm(out - ref32) <= 0.05 * np.linalg.norm(ref32)
+
+
+def test_train_and_solve(setup):
+    p, t, dec, ctx = setup
+    q = workload.chamber_problem(c=0.02, nsub=16, overlap=1, nsrc=8, tear_seed=1001)
+    ctx.assemble(None, None, q.eps, q.eps_kind, q.freq, q.eps_b, reuse_mesh=True)
+    ctx.setup_schwarz(16, 1, precision=mx.MX_PREC_C64, coarse=True)
+    ctx.coarse_clear()
+    n = ctx.coarse_collect(q.src_pos, q.src_mom, snap_every=2, max_snapshots=12)
+    assert n >= 2
+    hist = ctx.coarse_train(epochs=30, batch_graphs=8, lr=1e-3, seed=1)
+    print("loss", hist[0], "->", hist[-1])
+    assert np.all(np.isfinite(hist)) and hist[-1] < hist[0]
+    # held-out phantom: the learned term may help or not, the answer is fixed by rtol
+    ctx.assemble(None, None, p.eps, p.eps_kind, p.freq, p.eps_b, reuse_mesh=True)
+    ctx.setup_schwarz(16, 1, precision=mx.MX_PREC_C64, coarse=False)
+    _, _, plain = ctx.solve(p.src_pos, p.src_mom, rtol=1e-10, want_E=False)
+    ctx.setup_schwarz(16, 1, precision=mx.MX_PREC_C64, coarse=True)
+    E, S, info = ctx.solve(p.src_pos, p.src_mom, rtol=1e-10)
+    print("iterations plain", plain["iters_max"], "learned", info["iters_max"], "fallback", info["fallback"])
+    assert info["converged"]
+    A = fem.assemble(t, p.eps, p.eps_kind, p.freq, p.eps_b)
+    U = fem.solve_direct(A, fem.dipole_rhs(t, p.src_pos, p.src_mom, p.freq))
+    err = np.linalg.norm(E - U, axis=0) / np.linalg.norm(U, axis=0)
+    assert err.max() <= 1e-5
+
+
+def test_nonfinite_weights_fall_back(setup):
+    """NaN weights: the solver drops the learned term and still converges."""
+    p, t, dec, ctx = setup
+    theta, sx, sy = ctx.coarse_weights()
+    bad = theta.copy()
+    bad[:100] = np.nan
+    ctx.coarse_set_weights(bad, sx, sy)
+    ctx.setup_schwarz(16, 1, precision=mx.MX_PREC_C64, coarse=True)
+    _, _, info = ctx.solve(p.src_pos, p.src_mom, rtol=1e-8, want_E=False)
+    assert info["converged"] and info["fallback"] == 1
+    ctx.coarse_set_weights(theta, sx, sy)
