@@ -331,8 +331,12 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
 }
 
 // --------------------------------------------------------------------------
-// trailing update A22 -= L21 U12 on 64x64 tiles
+// trailing update A22 -= L21 U12 on 64x64 tiles; the 64-deep panels are
+// staged in two 32-deep chunks (small LDS footprint: 4 workgroups per CU for
+// complex64, 2 for complex128); the C tile is loaded before the staging.
 // --------------------------------------------------------------------------
+constexpr int KCH = 32;
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                    const int32_t* __restrict__ Npad,
@@ -345,14 +349,9 @@ __global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, co
   const int j0 = k0 + NB + blockIdx.x * NB;
   if (i0 >= N || j0 >= N) return;
   C* A = pool + mat_off[s];
-  __shared__ C As[NB][NB + 1];
-  __shared__ C Bs[NB][NB + 1];
+  __shared__ C As[NB][KCH + 1];
+  __shared__ C Bs[KCH][NB + 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) {
-    int r = e / NB, c = e % NB;
-    As[r][c] = A[(int64_t)(i0 + r) * N + k0 + c];
-    Bs[r][c] = A[(int64_t)(k0 + r) * N + j0 + c];
-  }
   const int lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   Acc cre[2][2], cim[2][2];
@@ -366,21 +365,31 @@ __global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, co
         cre[it][jt][r] = v.x;
         cim[it][jt][r] = v.y;
       }
-  __syncthreads();
-  for (int kk = 0; kk < NB; kk += 4) {
-    C av[2], bv[2];
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      C t = As[wr + 16 * it + (lane & 15)][kk + (lane >> 4)];
-      av[it].x = -t.x;
-      av[it].y = -t.y;
+  for (int kc = 0; kc < NB; kc += KCH) {
+    if (kc) __syncthreads();
+    for (int e = tid; e < NB * KCH; e += 256) {
+      int r = e / KCH, c = e % KCH;
+      As[r][c] = A[(int64_t)(i0 + r) * N + k0 + kc + c];
+      int r2 = e / NB, c2 = e % NB;
+      Bs[r2][c2] = A[(int64_t)(k0 + kc + r2) * N + j0 + c2];
     }
+    __syncthreads();
 #pragma unroll
-    for (int jt = 0; jt < 2; ++jt) bv[jt] = Bs[kk + (lane >> 4)][wc + 16 * jt + (lane & 15)];
+    for (int kk = 0; kk < KCH; kk += 4) {
+      C av[2], bv[2];
 #pragma unroll
-    for (int it = 0; it < 2; ++it)
+      for (int it = 0; it < 2; ++it) {
+        C t = As[wr + 16 * it + (lane & 15)][kk + (lane >> 4)];
+        av[it].x = -t.x;
+        av[it].y = -t.y;
+      }
 #pragma unroll
-      for (int jt = 0; jt < 2; ++jt) cmfma<R>(av[it], bv[jt], cre[it][jt], cim[it][jt]);
+      for (int jt = 0; jt < 2; ++jt) bv[jt] = Bs[kk + (lane >> 4)][wc + 16 * jt + (lane & 15)];
+#pragma unroll
+      for (int it = 0; it < 2; ++it)
+#pragma unroll
+        for (int jt = 0; jt < 2; ++jt) cmfma<R>(av[it], bv[jt], cre[it][jt], cim[it][jt]);
+    }
   }
 #pragma unroll
   for (int it = 0; it < 2; ++it)
@@ -517,15 +526,27 @@ __global__ void __launch_bounds__(256) k_trsm(const C_t<R>* __restrict__ pool, c
       }
       __syncthreads();
       if (w < nd) {
-        for (int kk = 0; kk < KC; kk += 4) {
-          C bv[2];
-#pragma unroll
-          for (int ct = 0; ct < 2; ++ct) bv[ct] = Yb[kk + (lane >> 4)][16 * ct + (lane & 15)];
+        // Each lane loads 4 consecutive complex values of its row (one full
+        // cache line per 4 lanes); MFMA step s then uses k = kq + 4*(lane/16) + s,
+        // and the B operand is read with the same permuted k.
+#pragma unroll 2
+        for (int kq = 0; kq < KC; kq += 16) {
+          C av[4][4];
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt) {
-            C av = A[(int64_t)(b0 + 64 * w + 16 * rt + (lane & 15)) * N + kc + kk + (lane >> 4)];
+            const C* ap = A + (int64_t)(b0 + 64 * w + 16 * rt + (lane & 15)) * N + kc + kq + 4 * (lane >> 4);
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct) cmfma<R>(av, bv[ct], cre[rt][ct], cim[rt][ct]);
+            for (int s4 = 0; s4 < 4; ++s4) av[rt][s4] = ap[s4];
+          }
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            C bv[2];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) bv[ct] = Yb[kq + 4 * (lane >> 4) + s4][16 * ct + (lane & 15)];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+              for (int ct = 0; ct < 2; ++ct) cmfma<R>(av[rt][s4], bv[ct], cre[rt][ct], cim[rt][ct]);
           }
         }
       }
