@@ -472,10 +472,20 @@ __global__ void __launch_bounds__(64) k_perm(int32_t nsub, const int32_t* __rest
 // --------------------------------------------------------------------------
 // triangular solves: X <- U^{-1} L^{-1} X on [N][nrhs] blocks, 32 right-hand
 // sides per workgroup, 256-row super-blocks, 64-row diagonal blocks applied
-// through their stored inverses
+// through their stored inverses.
+//
+// Off-diagonal part of a super-block: wave w owns rows 64w..64w+63 and
+// accumulates A[rows, K] X[K] on its own, with no workgroup barrier: it
+// streams its factor rows and the matching right-hand-side rows straight
+// into MFMA operand registers, one 16-column chunk ahead of the chunk being
+// multiplied (the right-hand-side rows are shared by the four waves and
+// come from L1/L2). The diagonal part then runs on the super-block's
+// residual held in LDS: each 64-row diagonal block is multiplied by its
+// stored inverse and the remaining rows of the super-block are updated,
+// spread over all four waves in 16-row tiles.
 // --------------------------------------------------------------------------
 constexpr int SB = 256;
-constexpr int KC = 32;
+constexpr int KC = 16;
 constexpr int RC = 32;
 
 template <typename R, bool LOWER>
@@ -490,76 +500,139 @@ __device__ inline C_t<R> diag_inv_elem(const C_t<R>* A, int N, int b0, int i, in
   }
 }
 
+// One K chunk of operands for this lane. MFMA step s4 uses
+// k = kc + 4*(lane/16) + s4: the factor row 16*rt + lane%16 is read as 4
+// consecutive complex values per lane, and the right-hand-side rows with the
+// same permuted k, columns 16*ct + lane%16.
+template <typename R>
+struct trsm_ops {
+  C_t<R> a[4][4];
+  C_t<R> b[4][2];
+};
+
+template <typename R>
+__device__ __forceinline__ void trsm_load(trsm_ops<R>& o, const C_t<R>* __restrict__ Arow, int N,
+                                          const C_t<R>* __restrict__ X, int nrhs, int j0, int nc, int kc, int lane) {
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) {
+    const C_t<R>* ap = Arow + (int64_t)(16 * rt + (lane & 15)) * N + kc + 4 * (lane >> 4);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) o.a[rt][s4] = ap[s4];
+  }
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int col = 16 * ct + (lane & 15);
+      o.b[s4][ct] = col < nc ? X[(int64_t)(kc + 4 * (lane >> 4) + s4) * nrhs + j0 + col] : czero<C_t<R>>();
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void trsm_mul(const trsm_ops<R>& o, Acc_t<R> (&cre)[4][2], Acc_t<R> (&cim)[4][2]) {
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    C_t<R> bn[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) bn[ct].y = -o.b[s4][ct].y;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) cmfma_nb<R>(o.a[rt][s4], o.b[s4][ct], bn[ct], cre[rt][ct], cim[rt][ct]);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void trsm_mul3(const trsm_ops<R>& o, Acc_t<R> (&t1)[4][2], Acc_t<R> (&t2)[4][2],
+                                          Acc_t<R> (&t3)[4][2]) {
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    R bs[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) bs[ct] = o.b[s4][ct].x + o.b[s4][ct].y;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const R as = o.a[rt][s4].x + o.a[rt][s4].y;
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        t1[rt][ct] = mfma(o.a[rt][s4].x, o.b[s4][ct].x, t1[rt][ct]);
+        t2[rt][ct] = mfma(o.a[rt][s4].y, o.b[s4][ct].y, t2[rt][ct]);
+        t3[rt][ct] = mfma(as, bs[ct], t3[rt][ct]);
+      }
+    }
+  }
+}
+
 template <typename R, bool LOWER>
-__global__ void __launch_bounds__(256) k_trsm(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
-                                              const int32_t* __restrict__ Npad, const int64_t* __restrict__ vec_off,
-                                              C_t<R>* __restrict__ xloc, int nrhs) {
+__global__ void __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1)
+    k_trsm(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off, const int32_t* __restrict__ Npad,
+           const int64_t* __restrict__ vec_off, const int32_t* __restrict__ order, C_t<R>* __restrict__ xloc,
+           int nrhs) {
   typedef C_t<R> C;
   typedef Acc_t<R> Acc;
-  const int s = blockIdx.x;
+  const int s = order[blockIdx.x];
   const int N = Npad[s];
   const C* A = pool + mat_off[s];
   C* X = xloc + vec_off[s] * (int64_t)nrhs;
   const int j0 = blockIdx.y * RC;
   const int nc = min(RC, nrhs - j0);
-  __shared__ C Yb[KC][RC + 1];
   __shared__ C Tb[SB][RC + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nsb = (N + SB - 1) / SB;
   for (int q = 0; q < nsb; ++q) {
     const int sbi = LOWER ? q : nsb - 1 - q;
     const int b0 = sbi * SB;
-    const int sbn = min(SB, N - b0);
-    const int nd = sbn / NB;
-    // off-diagonal part: acc = A[rows, K] X[K]
-    const int kbeg = LOWER ? 0 : b0 + sbn;
-    const int kend = LOWER ? b0 : N;
-    Acc cre[4][2], cim[4][2];
+    const int nd = min(SB, N - b0) / NB;
+    if (w < nd) {
+      const C* Arow = A + (int64_t)(b0 + NB * w) * N;
+      Acc cre[4][2], cim[4][2];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) { cre[rt][ct] = zacc<R>(); cim[rt][ct] = zacc<R>(); }
-    for (int kc = kbeg; kc < kend; kc += KC) {
-      for (int e = tid; e < KC * RC; e += 256) {
-        int r = e / RC, c = e % RC;
-        Yb[r][c] = c < nc ? X[(int64_t)(kc + r) * nrhs + j0 + c] : czero<C>();
-      }
-      __syncthreads();
-      if (w < nd) {
-        // Each lane loads 4 consecutive complex values of its row (one full
-        // cache line per 4 lanes); MFMA step s then uses k = kq + 4*(lane/16) + s,
-        // and the B operand is read with the same permuted k.
-#pragma unroll 2
-        for (int kq = 0; kq < KC; kq += 16) {
-          C av[4][4];
+        for (int ct = 0; ct < 2; ++ct) { cre[rt][ct] = zacc<R>(); cim[rt][ct] = zacc<R>(); }
+      // off-diagonal part over K = [kbeg, kbeg + KC * nch)
+      const int kbeg = LOWER ? 0 : b0 + nd * NB;
+      const int nch = ((LOWER ? b0 : N) - kbeg) / KC;
+      if (nch > 0) {
+        Acc t3[4][2];
 #pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            const C* ap = A + (int64_t)(b0 + 64 * w + 16 * rt + (lane & 15)) * N + kc + kq + 4 * (lane >> 4);
+        for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) av[rt][s4] = ap[s4];
+          for (int ct = 0; ct < 2; ++ct) t3[rt][ct] = zacc<R>();
+        if constexpr (sizeof(R) == 4) {
+          // complex64: two chunks of loads in flight before their products
+          trsm_ops<R> o0, o1;
+          for (int c = 0; c < nch; c += 2) {
+            trsm_load<R>(o0, Arow, N, X, nrhs, j0, nc, kbeg + c * KC, lane);
+            if (c + 1 < nch) trsm_load<R>(o1, Arow, N, X, nrhs, j0, nc, kbeg + (c + 1) * KC, lane);
+            trsm_mul3<R>(o0, cre, cim, t3);
+            if (c + 1 < nch) trsm_mul3<R>(o1, cre, cim, t3);
           }
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) {
-            C bv[2];
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) bv[ct] = Yb[kq + 4 * (lane >> 4) + s4][16 * ct + (lane & 15)];
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-              for (int ct = 0; ct < 2; ++ct) cmfma<R>(av[rt][s4], bv[ct], cre[rt][ct], cim[rt][ct]);
+        } else {
+          // complex128: the three accumulator sets take 192 registers
+          trsm_ops<R> o0;
+          for (int c = 0; c < nch; ++c) {
+            trsm_load<R>(o0, Arow, N, X, nrhs, j0, nc, kbeg + c * KC, lane);
+            trsm_mul3<R>(o0, cre, cim, t3);
           }
         }
+        // cre = sum a.re b.re, cim = sum a.im b.im, t3 = sum (a.re + a.im)(b.re + b.im)
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const Acc t1 = cre[rt][ct], t2 = cim[rt][ct];
+            cre[rt][ct] = t1 - t2;
+            cim[rt][ct] = t3[rt][ct] - t1 - t2;
+          }
       }
-      __syncthreads();
-    }
-    if (w < nd) {
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = 64 * w + 16 * rt + acc_row<R>(lane, r);
+            const int row = NB * w + 16 * rt + acc_row<R>(lane, r);
             const int col = 16 * ct + (lane & 15);
             C x = col < nc ? X[(int64_t)(b0 + row) * nrhs + j0 + col] : czero<C>();
             x.x -= cre[rt][ct][r];
@@ -571,18 +644,20 @@ __global__ void __launch_bounds__(256) k_trsm(const C_t<R>* __restrict__ pool, c
     // diagonal part
     for (int dq = 0; dq < nd; ++dq) {
       const int d = LOWER ? dq : nd - 1 - dq;
-      const int db = b0 + 64 * d;
+      const int db = b0 + NB * d;
+      C dv[NB / 4];
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk) dv[kk] = diag_inv_elem<R, LOWER>(A, N, db, 16 * w + (lane & 15), 4 * kk + (lane >> 4));
       Acc yre[2], yim[2];
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) { yre[ct] = zacc<R>(); yim[ct] = zacc<R>(); }
-      for (int kk = 0; kk < NB; kk += 4) {
-        C av = diag_inv_elem<R, LOWER>(A, N, db, 16 * w + (lane & 15), kk + (lane >> 4));
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-          C bv = Tb[64 * d + kk + (lane >> 4)][16 * ct + (lane & 15)];
-          cmfma<R>(av, bv, yre[ct], yim[ct]);
+          C bv = Tb[NB * d + 4 * kk + (lane >> 4)][16 * ct + (lane & 15)];
+          cmfma<R>(dv[kk], bv, yre[ct], yim[ct]);
         }
-      }
       __syncthreads();
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct)
@@ -593,31 +668,34 @@ __global__ void __launch_bounds__(256) k_trsm(const C_t<R>* __restrict__ pool, c
           C v;
           v.x = yre[ct][r];
           v.y = yim[ct][r];
-          Tb[64 * d + row][col] = v;
+          Tb[NB * d + row][col] = v;
           if (col < nc) X[(int64_t)(db + row) * nrhs + j0 + col] = v;
         }
       __syncthreads();
-      // update the remaining diagonal blocks of this super-block
+      // update the remaining diagonal blocks of this super-block, 16-row tiles
       const int nrem = LOWER ? (nd - 1 - d) : d;
       for (int t = w; t < 4 * nrem; t += 4) {
         const int dd = LOWER ? d + 1 + t / 4 : t / 4;
         const int rt = t % 4;
+        C av[NB / 4];
+#pragma unroll
+        for (int kk = 0; kk < NB / 4; ++kk)
+          av[kk] = A[(int64_t)(b0 + NB * dd + 16 * rt + (lane & 15)) * N + db + 4 * kk + (lane >> 4)];
         Acc ure[2], uim[2];
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) { ure[ct] = zacc<R>(); uim[ct] = zacc<R>(); }
-        for (int kk = 0; kk < NB; kk += 4) {
-          C av = A[(int64_t)(b0 + 64 * dd + 16 * rt + (lane & 15)) * N + db + kk + (lane >> 4)];
+#pragma unroll
+        for (int kk = 0; kk < NB / 4; ++kk)
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct) {
-            C bv = Tb[64 * d + kk + (lane >> 4)][16 * ct + (lane & 15)];
-            cmfma<R>(av, bv, ure[ct], uim[ct]);
+            C bv = Tb[NB * d + 4 * kk + (lane >> 4)][16 * ct + (lane & 15)];
+            cmfma<R>(av[kk], bv, ure[ct], uim[ct]);
           }
-        }
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = 64 * dd + 16 * rt + acc_row<R>(lane, r);
+            const int row = NB * dd + 16 * rt + acc_row<R>(lane, r);
             const int col = 16 * ct + (lane & 15);
             Tb[row][col].x -= ure[ct][r];
             Tb[row][col].y -= uim[ct][r];
@@ -691,20 +769,20 @@ void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_
 
 template <typename R>
 void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
-                 const int64_t* vec_off, C_t<R>* xloc, int nsub, int nrhs, KTimer* tm) {
+                 const int64_t* vec_off, const int32_t* order, C_t<R>* xloc, int nsub, int nrhs, KTimer* tm) {
   if (nsub <= 0 || nrhs <= 0) return;
   dim3 grid(nsub, ceil_div(nrhs, RC));
   MX_TB(K_TRSM_LOWER);
-  hipLaunchKernelGGL((k_trsm<R, true>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, xloc, nrhs);
+  hipLaunchKernelGGL((k_trsm<R, true>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs);
   MX_TE(K_TRSM_LOWER);
   MX_TB(K_TRSM_UPPER);
-  hipLaunchKernelGGL((k_trsm<R, false>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, xloc, nrhs);
+  hipLaunchKernelGGL((k_trsm<R, false>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs);
   MX_TE(K_TRSM_UPPER);
 }
-template void launch_trsm<float>(hipStream_t, const float2*, const int64_t*, const int32_t*, const int64_t*, float2*,
-                                 int, int, KTimer*);
+template void launch_trsm<float>(hipStream_t, const float2*, const int64_t*, const int32_t*, const int64_t*,
+                                 const int32_t*, float2*, int, int, KTimer*);
 template void launch_trsm<double>(hipStream_t, const double2*, const int64_t*, const int32_t*, const int64_t*,
-                                  double2*, int, int, KTimer*);
+                                  const int32_t*, double2*, int, int, KTimer*);
 
 int lu_max_swap_rows() { return MAXSW; }
 

@@ -234,19 +234,38 @@ __global__ void k_pad_identity(int32_t nsub, const int64_t* __restrict__ dof_ptr
 }
 
 // Y = A X, X and Y DOF-major [n][nrhs]; TPR threads per row, each handling
-// right-hand sides j = lane, lane + TPR, ...
+// right-hand sides j = lane, lane + TPR, ...  Workgroups are dealt to the 8
+// XCDs round-robin; the grid is a multiple of 8 and workgroup b takes row
+// block (b % 8) * (grid / 8) + b / 8, so each XCD sweeps one contiguous band
+// of rows and the X rows its band gathers stay in that XCD's own L2.
 template <int TPR>
 __global__ void __launch_bounds__(256) k_spmm(int64_t nrows, const int64_t* __restrict__ rp,
                                               const int32_t* __restrict__ col, const double2* __restrict__ val,
                                               const double2* __restrict__ X, double2* __restrict__ Y, int nrhs) {
   const int RPB = 256 / TPR;
-  int64_t row = blockIdx.x * (int64_t)RPB + threadIdx.x / TPR;
+  const int64_t per = gridDim.x / 8;
+  const int64_t blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  int64_t row = blk * RPB + threadIdx.x / TPR;
   int lane = threadIdx.x % TPR;
   if (row >= nrows) return;
-  int64_t k0 = rp[row], k1 = rp[row + 1];
+  const int64_t k0 = rp[row], k1 = rp[row + 1];
   for (int j = lane; j < nrhs; j += TPR) {
     double re = 0, im = 0;
-    for (int64_t k = k0; k < k1; ++k) {
+    int64_t k = k0;
+    // four non-zeros per iteration: all loads issued before the arithmetic
+    for (; k + 4 <= k1; k += 4) {
+      double2 a[4], x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = val[k + q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = X[(int64_t)col[k + q] * nrhs + j];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        re += a[q].x * x[q].x - a[q].y * x[q].y;
+        im += a[q].x * x[q].y + a[q].y * x[q].x;
+      }
+    }
+    for (; k < k1; ++k) {
       double2 a = val[k];
       double2 x = X[(int64_t)col[k] * nrhs + j];
       re += a.x * x.x - a.y * x.y;
@@ -422,17 +441,20 @@ void launch_pad_identity(hipStream_t s, int32_t nsub, const int64_t* dof_ptr, co
 template void launch_pad_identity<float2>(hipStream_t, int32_t, const int64_t*, const int32_t*, const int64_t*, float2*);
 template void launch_pad_identity<double2>(hipStream_t, int32_t, const int64_t*, const int32_t*, const int64_t*, double2*);
 
+// workgroup count rounded up to a multiple of the XCD count
+static inline unsigned nblk8(int64_t n, int64_t per) { return (unsigned)((nblk(n, per) + 7) / 8 * 8); }
+
 void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t* col, const double2* val,
                  const double2* X, double2* Y, int nrhs) {
   if (nrows <= 0) return;
   if (nrhs <= 8)
-    hipLaunchKernelGGL(k_spmm<8>, dim3(nblk(nrows, 32)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+    hipLaunchKernelGGL(k_spmm<8>, dim3(nblk8(nrows, 32)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
   else if (nrhs <= 16)
-    hipLaunchKernelGGL(k_spmm<16>, dim3(nblk(nrows, 16)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+    hipLaunchKernelGGL(k_spmm<16>, dim3(nblk8(nrows, 16)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
   else if (nrhs <= 32)
-    hipLaunchKernelGGL(k_spmm<32>, dim3(nblk(nrows, 8)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+    hipLaunchKernelGGL(k_spmm<32>, dim3(nblk8(nrows, 8)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
   else
-    hipLaunchKernelGGL(k_spmm<64>, dim3(nblk(nrows, 4)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+    hipLaunchKernelGGL(k_spmm<64>, dim3(nblk8(nrows, 4)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
 }
 
 template <typename C>

@@ -231,7 +231,7 @@ struct mx_ctx {
   // decomposition
   Decomposition dec;
   bool have_dec = false;
-  DBuf<int32_t> dofs, Npad, order, if_tet, if_lf, lsrc, p_edge, piv, status, pswap, perm, rowsrc;
+  DBuf<int32_t> dofs, Npad, order, trsm_order, if_tet, if_lf, lsrc, p_edge, piv, status, pswap, perm, rowsrc;
   DBuf<int64_t> dof_ptr, mat_off, vec_off, ldest, lptr, p_row;
   DBuf<double> p_w;
   std::vector<int32_t> Nsorted;
@@ -520,8 +520,8 @@ void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2*
   c->prof.begin(K_RESTRICT);
   launch_restrict<C>(c->stream, nrows, c->rowsrc.p, v, xl, nrhs);
   c->prof.end(K_RESTRICT);
-  launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, xl, D.nsub, nrhs,
-                 &c->prof);
+  launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, c->trsm_order.p, xl,
+                 D.nsub, nrhs, &c->prof);
   const bool coarse = c->coarse_use && !c->coarse_off_now && c->coarse_geom && c->coarse_weights;
   C* xq = nullptr;
   if (coarse) {
@@ -879,6 +879,20 @@ int build_sources(mx_ctx* c, const mx_sources* src, SourceSet& out) {
 
 }  // namespace
 
+// Workgroup order of the triangular solves: one workgroup per subdomain and
+// 32 right-hand sides, all resident at once when there are at most two per
+// compute unit. Workgroups b and b + nsub/2 are then dealt to the same compute
+// unit, so the b-th largest subdomain is paired with the b-th smallest and the
+// per-unit work is even; beyond that the largest subdomains go first.
+static std::vector<int32_t> trsm_dispatch_order(const std::vector<int32_t>& by_size_desc) {
+  const int n = (int)by_size_desc.size();
+  if (n > 512) return by_size_desc;
+  std::vector<int32_t> o(n);
+  const int half = (n + 1) / 2;
+  for (int b = 0; b < n; ++b) o[b] = b < half ? by_size_desc[b] : by_size_desc[n - 1 - (b - half)];
+  return o;
+}
+
 extern "C" {
 
 const char* mx_last_error(void) { return g_err.c_str(); }
@@ -1046,6 +1060,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     c->Nsorted.resize(nsub);
     for (int i = 0; i < nsub; ++i) c->Nsorted[i] = d.Npad[ord[i]];
     CK(c->order.upload(ord, c->stream));
+    CK(c->trsm_order.upload(trsm_dispatch_order(ord), c->stream));
     CK(c->piv.alloc(d.vec_off[nsub]));
     CK(c->perm.alloc(d.vec_off[nsub]));
     CK(c->rowsrc.alloc(d.vec_off[nsub]));

@@ -85,6 +85,16 @@ __device__ inline void cmfma(C_t<R> a, C_t<R> b, Acc_t<R>& cre, Acc_t<R>& cim) {
   cim = mfma(a.y, b.x, cim);
 }
 
+// Same product with the sign carried by B's imaginary part: for a B value
+// shared by several A tiles the negation is done once per B value.
+template <typename R>
+__device__ inline void cmfma_nb(C_t<R> a, C_t<R> b, C_t<R> bneg_im, Acc_t<R>& cre, Acc_t<R>& cim) {
+  cre = mfma(a.x, b.x, cre);
+  cre = mfma(a.y, bneg_im.y, cre);
+  cim = mfma(a.x, b.y, cim);
+  cim = mfma(a.y, b.x, cim);
+}
+
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 
 }  // namespace mx

@@ -93,7 +93,7 @@ void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_
                  const int32_t* dofs, const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc);
 template <typename R>
 void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
-                 const int64_t* vec_off, C_t<R>* xloc, int nsub, int nrhs, KTimer* tm);
+                 const int64_t* vec_off, const int32_t* order, C_t<R>* xloc, int nsub, int nrhs, KTimer* tm);
 int lu_max_swap_rows();
 
 // Krylov
