@@ -331,9 +331,10 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
 }
 
 // --------------------------------------------------------------------------
-// trailing update A22 -= L21 U12 on 64x64 tiles; the 64-deep panels are
-// staged in two 32-deep chunks (small LDS footprint: 4 workgroups per CU for
-// complex64, 2 for complex128); the C tile is loaded before the staging.
+// trailing update A22 -= L21 U12 on 64x64 tiles, complex products in the
+// 3-multiplication form (three real MFMA products instead of four); the
+// 64-deep panels are staged in two 32-deep chunks (33.5 KB of LDS for
+// complex64, 67 KB for complex128); the C tile is loaded before the staging.
 // --------------------------------------------------------------------------
 constexpr int KCH = 32;
 
@@ -354,17 +355,21 @@ __global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, co
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  Acc cre[2][2], cim[2][2];
+  // C tile in registers; products accumulated in the 3-multiplication form
+  // t1 = sum l.re u.re, t2 = sum l.im u.im, t3 = sum (l.re + l.im)(u.re + u.im)
+  C cv[2][2][4];
 #pragma unroll
   for (int it = 0; it < 2; ++it)
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        C v = A[(int64_t)(i0 + wr + 16 * it + acc_row<R>(lane, r)) * N + j0 + wc + 16 * jt + (lane & 15)];
-        cre[it][jt][r] = v.x;
-        cim[it][jt][r] = v.y;
-      }
+      for (int r = 0; r < 4; ++r)
+        cv[it][jt][r] = A[(int64_t)(i0 + wr + 16 * it + acc_row<R>(lane, r)) * N + j0 + wc + 16 * jt + (lane & 15)];
+  Acc t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) { t1[it][jt] = zacc<R>(); t2[it][jt] = zacc<R>(); t3[it][jt] = zacc<R>(); }
   for (int kc = 0; kc < NB; kc += KCH) {
     if (kc) __syncthreads();
     for (int e = tid; e < NB * KCH; e += 256) {
@@ -377,18 +382,25 @@ __global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, co
 #pragma unroll
     for (int kk = 0; kk < KCH; kk += 4) {
       C av[2], bv[2];
+      R as[2], bs[2];
 #pragma unroll
       for (int it = 0; it < 2; ++it) {
-        C t = As[wr + 16 * it + (lane & 15)][kk + (lane >> 4)];
-        av[it].x = -t.x;
-        av[it].y = -t.y;
+        av[it] = As[wr + 16 * it + (lane & 15)][kk + (lane >> 4)];
+        as[it] = av[it].x + av[it].y;
       }
 #pragma unroll
-      for (int jt = 0; jt < 2; ++jt) bv[jt] = Bs[kk + (lane >> 4)][wc + 16 * jt + (lane & 15)];
+      for (int jt = 0; jt < 2; ++jt) {
+        bv[jt] = Bs[kk + (lane >> 4)][wc + 16 * jt + (lane & 15)];
+        bs[jt] = bv[jt].x + bv[jt].y;
+      }
 #pragma unroll
       for (int it = 0; it < 2; ++it)
 #pragma unroll
-        for (int jt = 0; jt < 2; ++jt) cmfma<R>(av[it], bv[jt], cre[it][jt], cim[it][jt]);
+        for (int jt = 0; jt < 2; ++jt) {
+          t1[it][jt] = mfma(av[it].x, bv[jt].x, t1[it][jt]);
+          t2[it][jt] = mfma(av[it].y, bv[jt].y, t2[it][jt]);
+          t3[it][jt] = mfma(as[it], bs[jt], t3[it][jt]);
+        }
     }
   }
 #pragma unroll
@@ -397,9 +409,9 @@ __global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, co
     for (int jt = 0; jt < 2; ++jt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        C v;
-        v.x = cre[it][jt][r];
-        v.y = cim[it][jt][r];
+        C v = cv[it][jt][r];
+        v.x -= t1[it][jt][r] - t2[it][jt][r];
+        v.y -= t3[it][jt][r] - t1[it][jt][r] - t2[it][jt][r];
         A[(int64_t)(i0 + wr + 16 * it + acc_row<R>(lane, r)) * N + j0 + wc + 16 * jt + (lane & 15)] = v;
       }
 }
