@@ -165,6 +165,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="headline without the learned coarse term")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy kernel (read MIB MiB, write MIB MiB) three times, as the "
+                         "reference for HBM byte counters, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the solver runs on a single MI355X; --gpus {args.gpus} "
@@ -172,6 +175,17 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                          "dispatches": 3}))
+        return
     import paper_2311_05322_amd as mx
 
     p = make_problem(args.workload)

@@ -265,30 +265,35 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
 }
 
 // --------------------------------------------------------------------------
-// row permutation outside the panel and U12 = L11^{-1} A12
+// row permutation outside the panel and U12 = L11^{-1} A12.
+// mode 0: both; mode 1: the permutation only (all rows written back);
+// mode 2: U12 only, from the rows k0..k0+63 as they stand (the permutation
+// already applied and any deferred update of those rows already done).
 // --------------------------------------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                      const int32_t* __restrict__ Npad,
                                                      const int32_t* __restrict__ order,
-                                                     const int32_t* __restrict__ pswap, int k0) {
+                                                     const int32_t* __restrict__ pswap, int k0, int mode) {
   typedef C_t<R> C;
   typedef Acc_t<R> Acc;
   const int s = order[blockIdx.y];
   const int N = Npad[s];
   const int cb = blockIdx.x * NB;
   if (cb >= N || cb == k0 || k0 >= N) return;
+  if (mode == 2 && cb < k0) return;
   C* A = pool + mat_off[s];
   const int32_t* ps = pswap + (int64_t)s * (2 * MAXSW + 1);
-  const int n = ps[0];
+  const int n = mode == 2 ? NB : ps[0];
   __shared__ C X[MAXSW][NB + 1];
   const int tid = threadIdx.x;
   for (int e = tid; e < n * NB; e += 256) {
     int q = e / NB, j = e % NB;
-    X[q][j] = A[(int64_t)ps[1 + MAXSW + q] * N + cb + j];
+    const int src = mode == 2 ? k0 + q : ps[1 + MAXSW + q];
+    X[q][j] = A[(int64_t)src * N + cb + j];
   }
   __syncthreads();
-  if (cb < k0) {
+  if (cb < k0 || mode == 1) {
     for (int e = tid; e < n * NB; e += 256) {
       int q = e / NB, j = e % NB;
       A[(int64_t)ps[1 + q] * N + cb + j] = X[q][j];
@@ -296,7 +301,7 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
     return;
   }
   // rows below the panel that received another row's content
-  for (int e = tid; e < (n - NB) * NB; e += 256) {
+  for (int e = tid; mode == 0 && e < (n - NB) * NB; e += 256) {
     int q = NB + e / NB, j = e % NB;
     A[(int64_t)ps[1 + q] * N + cb + j] = X[q][j];
   }
@@ -331,23 +336,26 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
 }
 
 // --------------------------------------------------------------------------
-// trailing update A22 -= L21 U12 on 64x64 tiles, complex products in the
+// trailing update A[r0.., c0..] -= A[r0.., kl..kl+kd) A[kl..kl+kd), c0..] on
+// 64x64 tiles (kd = 64: one panel; kd = 128: two panels at once, which halves
+// the passes over the trailing matrix), complex products in the
 // 3-multiplication form (three real MFMA products instead of four); the
-// 64-deep panels are staged in two 32-deep chunks (33.5 KB of LDS for
-// complex64, 67 KB for complex128); the C tile is loaded before the staging.
+// panels are staged in 32-deep chunks (33.5 KB of LDS for complex64, 67 KB
+// for complex128); the C tile is loaded before the staging.
 // --------------------------------------------------------------------------
 constexpr int KCH = 32;
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                    const int32_t* __restrict__ Npad,
-                                                   const int32_t* __restrict__ order, int k0) {
+                                                   const int32_t* __restrict__ order, int kl, int kd, int r0,
+                                                   int c0) {
   typedef C_t<R> C;
   typedef Acc_t<R> Acc;
   const int s = order[blockIdx.z];
   const int N = Npad[s];
-  const int i0 = k0 + NB + blockIdx.y * NB;
-  const int j0 = k0 + NB + blockIdx.x * NB;
+  const int i0 = r0 + blockIdx.y * NB;
+  const int j0 = c0 + blockIdx.x * NB;
   if (i0 >= N || j0 >= N) return;
   C* A = pool + mat_off[s];
   __shared__ C As[NB][KCH + 1];
@@ -370,13 +378,13 @@ __global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, co
   for (int it = 0; it < 2; ++it)
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) { t1[it][jt] = zacc<R>(); t2[it][jt] = zacc<R>(); t3[it][jt] = zacc<R>(); }
-  for (int kc = 0; kc < NB; kc += KCH) {
+  for (int kc = 0; kc < kd; kc += KCH) {
     if (kc) __syncthreads();
     for (int e = tid; e < NB * KCH; e += 256) {
       int r = e / KCH, c = e % KCH;
-      As[r][c] = A[(int64_t)(i0 + r) * N + k0 + kc + c];
+      As[r][c] = A[(int64_t)(i0 + r) * N + kl + kc + c];
       int r2 = e / NB, c2 = e % NB;
-      Bs[r2][c2] = A[(int64_t)(k0 + kc + r2) * N + j0 + c2];
+      Bs[r2][c2] = A[(int64_t)(kl + kc + r2) * N + j0 + c2];
     }
     __syncthreads();
 #pragma unroll
@@ -728,39 +736,84 @@ inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) /
   if (tm) tm->end(cls)
 
 template <typename R>
+static void launch_panel(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
+                         const int32_t* order, int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
+                         int Nmax, int nact, int k0) {
+  const int m = Nmax - k0;
+  if (m <= PT * 1)
+    hipLaunchKernelGGL((k_lu_panel<R, 1>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
+                       status, pswap, k0);
+  else if (m <= PT * 2)
+    hipLaunchKernelGGL((k_lu_panel<R, 2>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
+                       status, pswap, k0);
+  else if (m <= PT * 4)
+    hipLaunchKernelGGL((k_lu_panel<R, 4>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
+                       status, pswap, k0);
+  else
+    hipLaunchKernelGGL((k_lu_panel<R, 8>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
+                       status, pswap, k0);
+}
+
+// Panels are taken in pairs (k0, k0 + 64). After the first panel only the
+// second panel's columns are updated; after the second, the two panels'
+// update of the rest of the matrix is applied in one 128-deep pass. The rows
+// of the second panel receive the first panel's update between the row
+// permutation and U12 = L11^{-1} A12 of the second panel.
+template <typename R>
 void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
                int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
                const std::vector<int32_t>& Nsorted, KTimer* tm) {
   if (Nsorted.empty()) return;
   const int Nmax = Nsorted[0];
-  for (int k0 = 0; k0 < Nmax; k0 += NB) {
-    int nact = 0;
-    while (nact < (int)Nsorted.size() && Nsorted[nact] > k0) ++nact;
-    const int m = Nmax - k0;
+  const int nsub = (int)Nsorted.size();
+  auto active = [&](int k) {  // subdomains with N > k (Nsorted is descending)
+    int a = 0;
+    while (a < nsub && Nsorted[a] > k) ++a;
+    return a;
+  };
+  const unsigned ctiles = ceil_div(Nmax, NB);
+  for (int k0 = 0; k0 < Nmax; k0 += 2 * NB) {
+    const int k1 = k0 + NB;
+    const int nact0 = active(k0);
     MX_TB(K_LU_PANEL);
-    if (m <= PT * 1)
-      hipLaunchKernelGGL((k_lu_panel<R, 1>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
-                         status, pswap, k0);
-    else if (m <= PT * 2)
-      hipLaunchKernelGGL((k_lu_panel<R, 2>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
-                         status, pswap, k0);
-    else if (m <= PT * 4)
-      hipLaunchKernelGGL((k_lu_panel<R, 4>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
-                         status, pswap, k0);
-    else
-      hipLaunchKernelGGL((k_lu_panel<R, 8>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
-                         status, pswap, k0);
+    launch_panel<R>(st, pool, mat_off, Npad, order, piv, vec_off, status, pswap, Nmax, nact0, k0);
     MX_TE(K_LU_PANEL);
     MX_TB(K_LU_ROWPANEL);
-    hipLaunchKernelGGL((k_lu_rowpanel<R>), dim3(ceil_div(Nmax, NB), nact), dim3(256), 0, st, pool, mat_off, Npad,
-                       order, pswap, k0);
+    hipLaunchKernelGGL((k_lu_rowpanel<R>), dim3(ctiles, nact0), dim3(256), 0, st, pool, mat_off, Npad, order, pswap,
+                       k0, 0);
     MX_TE(K_LU_ROWPANEL);
-    const int nt = (Nmax - k0 - NB) / NB;
-    if (nt > 0) {
-      MX_TB(K_LU_UPDATE);
-      hipLaunchKernelGGL((k_lu_update<R>), dim3(nt, nt, nact), dim3(256), 0, st, pool, mat_off, Npad, order, k0);
-      MX_TE(K_LU_UPDATE);
-    }
+    if (k1 >= Nmax) break;
+    const int nrow1 = (Nmax - k1) / NB;
+    // the second panel's columns only
+    MX_TB(K_LU_UPDATE);
+    hipLaunchKernelGGL((k_lu_update<R>), dim3(1, nrow1, nact0), dim3(256), 0, st, pool, mat_off, Npad, order, k0, NB,
+                       k1, k1);
+    MX_TE(K_LU_UPDATE);
+    const int nact1 = active(k1);
+    MX_TB(K_LU_PANEL);
+    launch_panel<R>(st, pool, mat_off, Npad, order, piv, vec_off, status, pswap, Nmax, nact1, k1);
+    MX_TE(K_LU_PANEL);
+    MX_TB(K_LU_ROWPANEL);
+    hipLaunchKernelGGL((k_lu_rowpanel<R>), dim3(ctiles, nact1), dim3(256), 0, st, pool, mat_off, Npad, order, pswap,
+                       k1, 1);
+    MX_TE(K_LU_ROWPANEL);
+    const int k2 = k1 + NB;
+    if (k2 >= Nmax) break;
+    const int nt = (Nmax - k2) / NB;
+    // first panel's update of the second panel's rows, then U12 of the second panel
+    MX_TB(K_LU_UPDATE);
+    hipLaunchKernelGGL((k_lu_update<R>), dim3(nt, 1, nact1), dim3(256), 0, st, pool, mat_off, Npad, order, k0, NB, k1,
+                       k2);
+    MX_TE(K_LU_UPDATE);
+    MX_TB(K_LU_ROWPANEL);
+    hipLaunchKernelGGL((k_lu_rowpanel<R>), dim3(ctiles, nact1), dim3(256), 0, st, pool, mat_off, Npad, order, pswap,
+                       k1, 2);
+    MX_TE(K_LU_ROWPANEL);
+    // both panels' update of the trailing matrix
+    MX_TB(K_LU_UPDATE);
+    hipLaunchKernelGGL((k_lu_update<R>), dim3(nt, nt, active(k2)), dim3(256), 0, st, pool, mat_off, Npad, order, k0,
+                       2 * NB, k2, k2);
+    MX_TE(K_LU_UPDATE);
   }
   MX_TB(K_LU_INV);
   hipLaunchKernelGGL((k_inv_upper<R>), dim3(ceil_div(Nmax, NB), (unsigned)Nsorted.size()), dim3(64), 0, st, pool,
