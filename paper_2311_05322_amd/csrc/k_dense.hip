@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
 constexpr int KCH = 32;
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_lu_update(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+__global__ void __launch_bounds__(256, 2) k_lu_update(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                    const int32_t* __restrict__ Npad,
                                                    const int32_t* __restrict__ order, int kl, int kd, int r0,
                                                    int c0) {
