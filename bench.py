@@ -71,6 +71,26 @@ def algorithmic_work(kind, n_i, nnz, ne, nrhs, elem_bytes, kt):
     return None, None
 
 
+def measured_traffic(kernel, workload_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel on this workload, or None when there is none or the kernel's
+    source changed after the counters were taken."""
+    from paper_2311_05322_amd.pmc_summary import SOURCES, source_hash
+    name = "k_" + kernel.split("_lower")[0].split("_upper")[0]
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload_name}_hbm_traffic.md")
+    if name not in SOURCES or not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":")[0] in ("bytes_per_launch", "source_sha256"):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    if vals.get("source_sha256") != source_hash(name) or "bytes_per_launch" not in vals:
+        return None
+    return float(vals["bytes_per_launch"])
+
+
 def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=True, coarse=False):
     import torch
     import paper_2311_05322_amd as mx
@@ -85,9 +105,8 @@ def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=Tr
     for w in range(warmup):
         info = step()
         log(f"  warmup {w}: iters {info['iters_max']} converged {info['converged']}")
+    # timed steps: no per-kernel events, plain Arnoldi steps replayed from HIP graphs
     torch.cuda.synchronize()
-    if profile:
-        ctx.set_profiling(True)
     t0 = time.perf_counter()
     infos = []
     for k in range(steps):
@@ -96,9 +115,16 @@ def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=Tr
             f"fallback {infos[-1]['fallback']}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kt = ctx.kernel_times() if profile else None
+    kt = None
     if profile:
+        # one more step, outside the timed region, with HIP events around every
+        # kernel class (eager launches) for the per-kernel split and rooflines
+        ctx.set_profiling(True)
+        info = step()
+        torch.cuda.synchronize()
+        kt = ctx.kernel_times()
         ctx.set_profiling(False)
+        log(f"  profiled step: iters {info['iters_max']}")
     return (t1 - t0) / steps, infos, kt, S
 
 
@@ -220,7 +246,8 @@ def main():
         log(f"variant {name}")
         ms, infos, kt, S = run_variant(ctx, p, eps_dev, E_dev, prec, args.steps, args.warmup, args.restart,
                                        coarse=co)
-        variants[name] = {"ms": ms, "infos": infos, "kt": kt, "S": S}
+        variants[name] = {"ms": ms, "infos": infos, "kt": kt, "S": S, "tuning": ctx.tuning()}
+        log(f"  autotuner: {variants[name]['tuning']}")
     ctx.close()
     head = "c64_learned" if learned else "c64_plain"
     ms_mix, infos_mix, kt_mix, S_mix = (variants[head][k] for k in ("ms", "infos", "kt", "S"))
@@ -229,10 +256,11 @@ def main():
         v = variants["c128_plain"]
         ref = {"solves_per_s": 1.0 / v["ms"], "ms_per_step": v["ms"] * 1e3,
                "iters": int(v["infos"][-1]["iters_max"]),
-               "kernel_ms_per_step": {k: x[0] / args.steps for k, x in v["kt"].items() if x[1]},
+               "kernel_ms_per_step": {k: x[0] for k, x in v["kt"].items() if x[1]},
                "S_rel_diff_vs_headline": float(np.abs(S_mix - v["S"]).max() / np.abs(v["S"]).max())}
     others = {k: {"solves_per_s": 1.0 / v["ms"], "iters": int(v["infos"][-1]["iters_max"]),
-                  "fallback": int(v["infos"][-1]["fallback"])} for k, v in variants.items()}
+                  "fallback": int(v["infos"][-1]["fallback"]), "autotune": v["tuning"]}
+              for k, v in variants.items()}
 
     # dominant kernel of the headline variant and its roofline
     kt = kt_mix
@@ -246,7 +274,7 @@ def main():
         roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": MFMA_PEAK_TFLOPS["fp32"],
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom, args.workload)
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_s * 1e3
     # the same figures for every kernel class that has an algorithmic count
@@ -283,7 +311,7 @@ def main():
         "iters": iters,
         "speedup_vs_fp64_gpu": (value / ref["solves_per_s"]) if ref else None,
         "fp64_reference": ref,
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt_mix.items() if v[1]},
+        "kernel_ms_per_step": {k: v[0] for k, v in kt_mix.items() if v[1]},
         "roofline": roof,
         "roofline_by_kernel": roof_all,
         "cpu_baseline": cpu,

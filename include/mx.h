@@ -142,6 +142,33 @@ int mx_destroy(mx_ctx* ctx);
  * The caller keeps the stream alive while the context uses it. */
 int mx_set_stream(mx_ctx* ctx, void* hip_stream);
 
+/* Autotuner (on by default): at the first solve of a problem shape (edges,
+ * non-zeros, subdomains, factor entries, precision, number of right-hand
+ * sides) the candidate variants below are timed on the problem's own data
+ * with HIP events and the fastest is used from then on:
+ *   SpMM: 0 = one lane per right-hand side, non-zeros read by every lane;
+ *         1 = 32 lanes per row, each non-zero read once and broadcast
+ *             (nrhs <= 32 only);
+ *   triangular-solve workgroup order: 1 = b-th largest subdomain paired with
+ *         the b-th smallest, 0 = largest first.
+ * enable = 0 switches it off and restores variant 0 / paired order. */
+typedef struct {
+  int32_t spmm_variant;
+  int32_t trsm_paired;
+  double spmm_ms[2];   /* average time of one SpMM per variant (0 if not run) */
+  double trsm_ms[2];   /* one lower + upper solve: [largest first, paired]     */
+} mx_tuning;
+int mx_set_autotune(mx_ctx* ctx, int enable);
+int mx_get_tuning(mx_ctx* ctx, mx_tuning* out);
+
+/* enable != 0 (the default): Arnoldi steps that use the one-level
+ * preconditioner are captured as HIP graphs and replayed. A step runs eagerly
+ * the first time it is reached with the current buffers, sizes and
+ * tolerance; from the second time on it is one graph launch. Steps with the
+ * learned term, and all steps while profiling is on, run eagerly.
+ * enable = 0 drops the captured graphs. Results are bitwise identical. */
+int mx_set_graphs(mx_ctx* ctx, int enable);
+
 /* enable != 0: bracket every launch of the classes above with HIP events on
  * the context's stream (small overhead) and reset the totals; 0: stop. */
 int mx_set_profiling(mx_ctx* ctx, int enable);

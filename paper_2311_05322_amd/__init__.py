@@ -22,7 +22,7 @@ MX_PREC_C128, MX_PREC_C64 = 0, 1
 EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_solve", "mx_solve_rhs",
            "mx_apply_operator", "mx_apply_preconditioner", "mx_get_sizes", "mx_get_topology",
            "mx_get_matrix_values", "mx_get_partition", "mx_get_local_matrix", "mx_point_functionals",
-           "mx_set_stream", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_coarse_num_params", "mx_coarse_init",
+           "mx_set_stream", "mx_set_autotune", "mx_get_tuning", "mx_set_graphs", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_coarse_num_params", "mx_coarse_init",
            "mx_coarse_set_weights", "mx_coarse_get_weights", "mx_coarse_features", "mx_coarse_forward",
            "mx_coarse_loss_grad", "mx_coarse_collect", "mx_coarse_clear", "mx_coarse_train", "mx_last_error"]
 
@@ -64,6 +64,11 @@ class Sizes(ct.Structure):
                 ("sum_ni", ct.c_int64), ("sum_Ni2", ct.c_int64), ("nb", ct.c_int32)]
 
 
+class Tuning(ct.Structure):
+    _fields_ = [("spmm_variant", ct.c_int32), ("trsm_paired", ct.c_int32), ("spmm_ms", ct.c_double * 2),
+                ("trsm_ms", ct.c_double * 2)]
+
+
 class KernelTimes(ct.Structure):
     _fields_ = [("ms", ct.c_double * 16), ("launches", ct.c_int64 * 16)]
 
@@ -96,6 +101,9 @@ def lib():
             "mx_point_functionals": [vp, ct.POINTER(Sources), vp],
             "mx_set_stream": [vp, vp],
             "mx_set_profiling": [vp, ct.c_int],
+            "mx_set_graphs": [vp, ct.c_int],
+            "mx_set_autotune": [vp, ct.c_int],
+            "mx_get_tuning": [vp, vp],
             "mx_get_kernel_times": [vp, ct.POINTER(KernelTimes)],
             "mx_gradient": [vp, vp, vp, dbl, vp, ct.POINTER(dbl), ct.POINTER(SolveInfo)],
             "mx_coarse_init": [vp, ct.c_uint64],
@@ -183,6 +191,20 @@ class Context:
 
     def set_profiling(self, enable=True):
         _check(lib().mx_set_profiling(self._h, 1 if enable else 0))
+
+    def set_autotune(self, enable=True):
+        _check(lib().mx_set_autotune(self._h, 1 if enable else 0))
+
+    def tuning(self):
+        """Variants picked by the autotuner and their measured times (ms)."""
+        t = Tuning()
+        _check(lib().mx_get_tuning(self._h, ct.byref(t)))
+        return {"spmm_variant": t.spmm_variant, "trsm_paired": t.trsm_paired,
+                "spmm_ms": list(t.spmm_ms), "trsm_ms_largest_first_paired": list(t.trsm_ms)}
+
+    def set_graphs(self, enable=True):
+        """Replay captured HIP graphs for plain Arnoldi steps (default on)."""
+        _check(lib().mx_set_graphs(self._h, 1 if enable else 0))
 
     def kernel_times(self):
         """{class: (milliseconds, launches)} since profiling was enabled."""

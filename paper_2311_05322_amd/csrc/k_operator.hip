@@ -275,6 +275,53 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t nrows, const int64_t* __re
   }
 }
 
+// Y = A X for nrhs <= 32, 32 lanes per row (lane j: right-hand side j). The
+// row's column indices and values are loaded once, one entry per lane, and
+// handed to all 32 lanes with cross-lane shuffles, so that each lane issues
+// only the X loads (four in flight). Same XCD row-band mapping as k_spmm.
+__global__ void __launch_bounds__(256) k_spmm_bcast(int64_t nrows, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col,
+                                                    const double2* __restrict__ val,
+                                                    const double2* __restrict__ X, double2* __restrict__ Y,
+                                                    int nrhs) {
+  const int64_t per = gridDim.x / 8;
+  const int64_t blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t row = blk * 8 + threadIdx.x / 32;
+  const int lane = threadIdx.x % 32;
+  const int half = threadIdx.x & 32;  // first lane of this row's group within the wave
+  if (row >= nrows) return;
+  const int64_t k0 = rp[row], k1 = rp[row + 1];
+  double re = 0, im = 0;
+  for (int64_t kb = k0; kb < k1; kb += 32) {
+    const int cnt = (int)min((int64_t)32, k1 - kb);
+    int c = 0;
+    double2 a = make_double2(0.0, 0.0);
+    if (lane < cnt) {
+      c = col[kb + lane];
+      a = val[kb + lane];
+    }
+    for (int q = 0; q < cnt; q += 4) {
+      double2 x[4], aa[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int src = half + q + u;
+        const int cc = __shfl(c, src, 64);
+        aa[u].x = __shfl(a.x, src, 64);
+        aa[u].y = __shfl(a.y, src, 64);
+        x[u] = (q + u < cnt && lane < nrhs) ? X[(int64_t)cc * nrhs + lane] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (q + u < cnt) {
+          re += aa[u].x * x[u].x - aa[u].y * x[u].y;
+          im += aa[u].x * x[u].y + aa[u].y * x[u].x;
+        }
+      }
+    }
+  }
+  if (lane < nrhs) Y[row * nrhs + lane] = make_double2(re, im);
+}
+
 // xloc[R][j] = v[rowsrc[R]][j] (0 for padded rows), cast to C
 template <typename C>
 __global__ void k_restrict(int64_t nrows, const int32_t* __restrict__ rowsrc, const double2* __restrict__ v,
@@ -445,9 +492,11 @@ template void launch_pad_identity<double2>(hipStream_t, int32_t, const int64_t*,
 static inline unsigned nblk8(int64_t n, int64_t per) { return (unsigned)((nblk(n, per) + 7) / 8 * 8); }
 
 void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t* col, const double2* val,
-                 const double2* X, double2* Y, int nrhs) {
+                 const double2* X, double2* Y, int nrhs, int variant) {
   if (nrows <= 0) return;
-  if (nrhs <= 8)
+  if (variant == 1 && nrhs <= 32)
+    hipLaunchKernelGGL(k_spmm_bcast, dim3(nblk8(nrows, 8)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+  else if (nrhs <= 8)
     hipLaunchKernelGGL(k_spmm<8>, dim3(nblk8(nrows, 32)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
   else if (nrhs <= 16)
     hipLaunchKernelGGL(k_spmm<16>, dim3(nblk8(nrows, 16)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);

@@ -278,6 +278,25 @@ struct mx_ctx {
   double* h_vec = nullptr;
   int32_t* h_kd = nullptr;
   int h_cap = 0;
+  // Arnoldi steps captured as HIP graphs, one per step index k; valid while
+  // the buffers, sizes and tolerance they were captured with are unchanged
+  // autotuner: kernel variants picked by timing them on this problem
+  bool autotune_on = true;
+  uint64_t tune_key = 0;
+  int tune_spmm = 0;           // 0: lanes per right-hand side, 1: broadcast entries
+  int tune_trsm_paired = 1;    // 1: size-paired workgroup order, 0: largest first
+  double tune_spmm_ms[2] = {0, 0}, tune_trsm_ms[2] = {0, 0};
+  bool graphs_on = true;
+  uint64_t g_sig = 0;         // signature of the buffers, sizes and tolerance captured
+  std::vector<hipGraphExec_t> gexec;
+  std::vector<char> gseen;
+  void drop_graphs() {
+    for (auto& e : gexec)
+      if (e) (void)hipGraphExecDestroy(e);
+    gexec.clear();
+    gseen.clear();
+    g_sig = 0;
+  }
 };
 
 namespace {
@@ -520,8 +539,8 @@ void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2*
   c->prof.begin(K_RESTRICT);
   launch_restrict<C>(c->stream, nrows, c->rowsrc.p, v, xl, nrhs);
   c->prof.end(K_RESTRICT);
-  launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, c->trsm_order.p, xl,
-                 D.nsub, nrhs, &c->prof);
+  launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p,
+                 c->tune_trsm_paired ? c->trsm_order.p : c->order.p, xl, D.nsub, nrhs, &c->prof);
   const bool coarse = c->coarse_use && !c->coarse_off_now && c->coarse_geom && c->coarse_weights;
   C* xq = nullptr;
   if (coarse) {
@@ -558,7 +577,7 @@ int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q 
 
 int spmm(mx_ctx* c, const double2* X, double2* Y, int nrhs) {
   c->prof.begin(K_SPMM);
-  launch_spmm(c->stream, c->topo.ne, c->row_ptr.p, c->col.p, c->val.p, X, Y, nrhs);
+  launch_spmm(c->stream, c->topo.ne, c->row_ptr.p, c->col.p, c->val.p, X, Y, nrhs, c->tune_spmm);
   c->prof.end(K_SPMM);
   MX_HIP_CHECK(hipGetLastError());
   return MX_OK;
@@ -567,12 +586,108 @@ int spmm(mx_ctx* c, const double2* X, double2* Y, int nrhs) {
 // Right-preconditioned pseudo-block FGMRES on b (device) -> x (device, ctx->x).
 // on_cycle (optional) runs at the start of every restart cycle with the
 // current iterate in c->x and its true residual in c->r.
+// Autotuner: at the first solve of a problem shape (edges, non-zeros,
+// subdomains, factor entries, precision, right-hand sides) every candidate
+// variant of the SpMM and of the triangular-solve workgroup order is run on
+// this problem's own data (X = b; the restricted b) and timed with HIP
+// events; the fastest is kept for the following solves.
+template <typename R>
+int autotune_trsm(mx_ctx* c, int nrhs, hipEvent_t e0, hipEvent_t e1) {
+  typedef C_t<R> C;
+  const Decomposition& D = c->dec;
+  C* xl = (C*)c->xloc.p;
+  launch_restrict<C>(c->stream, D.vec_off[D.nsub], c->rowsrc.p, c->b.p, xl, nrhs);
+  for (int v = 0; v < 2; ++v) {
+    const int32_t* ord = v ? c->trsm_order.p : c->order.p;
+    launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, ord, xl, D.nsub, nrhs,
+                   nullptr);
+    MX_HIP_CHECK(hipEventRecord(e0, c->stream));
+    launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, ord, xl, D.nsub, nrhs,
+                   nullptr);
+    MX_HIP_CHECK(hipEventRecord(e1, c->stream));
+    MX_HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    MX_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    c->tune_trsm_ms[v] = ms;
+  }
+  c->tune_trsm_paired = c->tune_trsm_ms[1] <= c->tune_trsm_ms[0] ? 1 : 0;
+  return MX_OK;
+}
+
+int autotune(mx_ctx* c, int nrhs) {
+  if (!c->autotune_on) return MX_OK;
+  uint64_t key = 1469598103934665603ull;
+  auto mixv = [&](int64_t v) { key = (key ^ (uint64_t)v) * 1099511628211ull; };
+  mixv(c->topo.ne);
+  mixv((int64_t)c->col.n);
+  mixv(c->dec.nsub);
+  mixv(c->dec.mat_off.empty() ? 0 : c->dec.mat_off.back());
+  mixv(c->precision);
+  mixv(nrhs);
+  if (key == c->tune_key) return MX_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MX_HIP_CHECK(hipEventCreate(&e0));
+  MX_HIP_CHECK(hipEventCreate(&e1));
+  const int64_t ne = c->topo.ne;
+  int rc = MX_OK;
+  for (int v = 0; v < 2 && rc == MX_OK; ++v) {
+    if (v == 1 && nrhs > 32) {
+      c->tune_spmm_ms[v] = 1e30;
+      continue;
+    }
+    launch_spmm(c->stream, ne, c->row_ptr.p, c->col.p, c->val.p, c->b.p, c->r.p, nrhs, v);
+    hipError_t e = hipEventRecord(e0, c->stream);
+    for (int it = 0; it < 3; ++it) launch_spmm(c->stream, ne, c->row_ptr.p, c->col.p, c->val.p, c->b.p, c->r.p, nrhs, v);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) rc = hip_fail(e, "autotune spmm", __FILE__, __LINE__);
+    c->tune_spmm_ms[v] = ms / 3;
+  }
+  if (rc == MX_OK) c->tune_spmm = c->tune_spmm_ms[1] < c->tune_spmm_ms[0] ? 1 : 0;
+  if (rc == MX_OK && c->factored)
+    rc = c->precision == MX_PREC_C64 ? autotune_trsm<float>(c, nrhs, e0, e1) : autotune_trsm<double>(c, nrhs, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == MX_OK) c->tune_key = key;
+  return rc;
+}
+
+// FNV-1a over every pointer, size and scalar a captured Arnoldi step bakes in
+uint64_t step_signature(const mx_ctx* c, int nrhs, int m, double rtol) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  auto val = [&](auto v) { mix(&v, sizeof(v)); };
+  const void* ptrs[] = {c->V.p, c->Z.p, c->xloc.p, c->factors.p, c->val.p, c->row_ptr.p, c->col.p,
+                        c->rowsrc.p, c->trsm_order.p, c->mat_off.p, c->Npad.p, c->vec_off.p, c->p_edge.p,
+                        c->p_row.p, c->p_w.p, c->dotpart.p, c->normpart.p, c->h1.p, c->h2.p, c->hn.p, c->H.p,
+                        c->cs.p, c->sn.p, c->g.p, c->bnorm.p, c->conv.p, c->kdone.p, c->res.p};
+  mix(ptrs, sizeof(ptrs));
+  val(c->topo.ne);
+  val(c->dec.nsub);
+  val(c->dec.ncolour);
+  val(c->precision);
+  val(c->tune_spmm);
+  val(c->tune_trsm_paired);
+  val(nrhs);
+  val(m);
+  val(rtol);
+  if (!c->dec.vec_off.empty()) val(c->dec.vec_off.back());
+  mix(c->dec.pcol_ptr.data(), c->dec.pcol_ptr.size() * sizeof(int64_t));
+  return h;
+}
+
 int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::function<int()>* on_cycle = nullptr) {
   const int m = c->ws_m;
   const int64_t ne = c->topo.ne;
   const int64_t blk = ne * (int64_t)nrhs;
   hipStream_t s = c->stream;
   auto t0 = std::chrono::steady_clock::now();
+  CK(autotune(c, nrhs));
   launch_norm(s, ne, nrhs, c->b.p, c->normpart.p, c->bnorm.p);
   launch_fill_zero<double2>(s, blk, c->x.p);
   MX_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, blk * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -609,6 +724,68 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
   std::vector<double2> hj_dot(nrhs);
   std::vector<double> hj_aq(nrhs), hj_t(nrhs);
   if (coarse_on) CK(c->thtn.alloc(nrhs));
+  // Gram-Schmidt (twice), normalisation and the Givens update of step k
+  auto arnoldi_tail = [&](int k) -> int {
+    double2* w = c->V.p + (k + 1) * blk;
+    launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h1.p);
+    launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w);
+    launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h2.p);
+    launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h2.p, w);
+    launch_norm(s, ne, nrhs, w, c->normpart.p, c->hn.p);
+    launch_scale(s, ne, nrhs, w, c->hn.p, w);
+    launch_givens(s, k, m, nrhs, c->h1.p, c->h2.p, c->hn.p, c->H.p, c->cs.p, c->sn.p, c->g.p, c->bnorm.p, rtol,
+                  c->conv.p, c->kdone.p, c->res.p);
+    MX_HIP_CHECK(hipGetLastError());
+    return MX_OK;
+  };
+  // one whole step with the one-level preconditioner: kernel launches only
+  auto plain_step = [&](int k) -> int {
+    CK(apply_precond(c, c->V.p + k * blk, c->Z.p + k * blk, nrhs));
+    CK(spmm(c, c->Z.p + k * blk, c->V.p + (k + 1) * blk, nrhs));
+    c->prof.begin(K_CGS);
+    CK(arnoldi_tail(k));
+    c->prof.end(K_CGS);
+    return MX_OK;
+  };
+  // Graphs are used without profiling; a step runs eagerly the first time
+  // it is reached under the current buffers/sizes/tolerance and is captured
+  // and replayed from the second time on.
+  const bool use_graphs = c->graphs_on && !c->prof.on;
+  if (use_graphs) {
+    const uint64_t sig = step_signature(c, nrhs, m, rtol);
+    if (sig != c->g_sig || (int)c->gexec.size() != m) {
+      c->drop_graphs();
+      c->g_sig = sig;
+      c->gexec.assign(m, nullptr);
+      c->gseen.assign(m, 0);
+    }
+  }
+  auto graph_step = [&](int k) -> int {
+    if (!c->graphs_on) return plain_step(k);
+    if (!c->gexec[k]) {
+      if (!c->gseen[k]) {
+        c->gseen[k] = 1;
+        return plain_step(k);
+      }
+      hipGraph_t g = nullptr;
+      MX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const int rc_step = plain_step(k);
+      const hipError_t e_end = hipStreamEndCapture(s, &g);
+      hipError_t e_inst = hipErrorUnknown;
+      if (rc_step == MX_OK && e_end == hipSuccess && g)
+        e_inst = hipGraphInstantiate(&c->gexec[k], g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (rc_step != MX_OK || e_end != hipSuccess || e_inst != hipSuccess) {
+        // capture not possible here: run eagerly from now on
+        (void)hipGetLastError();
+        c->gexec[k] = nullptr;
+        c->graphs_on = false;
+        return plain_step(k);
+      }
+    }
+    MX_HIP_CHECK(hipGraphLaunch(c->gexec[k], s));
+    return MX_OK;
+  };
   for (;;) {
     if (on_cycle) CK((*on_cycle)());
     std::vector<double> rr_start(rr);
@@ -646,20 +823,14 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
         launch_norm(s, ne, nrhs, c->r.p, c->normpart.p, c->thtn.p);
         launch_theta_axpy(s, blk, nrhs, c->thdot.p, c->thnrm.p, c->qv.p, c->aq.p, zk, w);
         judged = true;
+        c->prof.begin(K_CGS);
+        CK(arnoldi_tail(k));
+        c->prof.end(K_CGS);
+      } else if (use_graphs) {
+        CK(graph_step(k));
       } else {
-        CK(apply_precond(c, vk, zk, nrhs));
-        CK(spmm(c, zk, w, nrhs));
+        CK(plain_step(k));
       }
-      c->prof.begin(K_CGS);
-      launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h1.p);
-      launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w);
-      launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h2.p);
-      launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h2.p, w);
-      launch_norm(s, ne, nrhs, w, c->normpart.p, c->hn.p);
-      launch_scale(s, ne, nrhs, w, c->hn.p, w);
-      launch_givens(s, k, m, nrhs, c->h1.p, c->h2.p, c->hn.p, c->H.p, c->cs.p, c->sn.p, c->g.p, c->bnorm.p, rtol,
-                    c->conv.p, c->kdone.p, c->res.p);
-      c->prof.end(K_CGS);
       MX_HIP_CHECK(hipMemcpyAsync(c->h_conv, c->conv.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       if (coarse_on && !c->coarse_off_now)
         MX_HIP_CHECK(hipMemcpyAsync(c->h_kd, c->cflag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -924,6 +1095,7 @@ int mx_destroy(mx_ctx* c) {
   if (c->h_conv) (void)hipHostFree(c->h_conv);
   if (c->h_vec) (void)hipHostFree(c->h_vec);
   if (c->h_kd) (void)hipHostFree(c->h_kd);
+  c->drop_graphs();
   c->prof.reset();
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
@@ -935,6 +1107,37 @@ int mx_set_stream(mx_ctx* c, void* hip_stream) {
   CK(use_device(c));
   CK(sync(c));
   c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
+  return MX_OK;
+}
+
+int mx_set_autotune(mx_ctx* c, int enable) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  c->autotune_on = enable != 0;
+  if (!c->autotune_on) {
+    c->tune_key = 0;
+    c->tune_spmm = 0;
+    c->tune_trsm_paired = 1;
+  }
+  return MX_OK;
+}
+
+int mx_get_tuning(mx_ctx* c, mx_tuning* out) {
+  if (!c || !out) return set_err(MX_EINVAL, "NULL argument");
+  out->spmm_variant = c->tune_spmm;
+  out->trsm_paired = c->tune_trsm_paired;
+  for (int i = 0; i < 2; ++i) {
+    out->spmm_ms[i] = c->tune_spmm_ms[i];
+    out->trsm_ms[i] = c->tune_trsm_ms[i];
+  }
+  return MX_OK;
+}
+
+int mx_set_graphs(mx_ctx* c, int enable) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  CK(use_device(c));
+  CK(sync(c));
+  c->drop_graphs();
+  c->graphs_on = enable != 0;
   return MX_OK;
 }
 

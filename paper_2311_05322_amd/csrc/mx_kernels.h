@@ -77,7 +77,7 @@ void launch_nonfinite(hipStream_t s, int64_t n, const float* x, int32_t* flag);
 
 // operator application and Schwarz transfer
 void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t* col, const double2* val,
-                 const double2* X, double2* Y, int nrhs);
+                 const double2* X, double2* Y, int nrhs, int variant = 0);
 template <typename C>
 void launch_restrict(hipStream_t s, int64_t nrows, const int32_t* rowsrc, const double2* v, C* xloc, int nrhs);
 template <typename C>

@@ -1,0 +1,96 @@
+"""Summarises rocprofv3 HBM byte counters of one kernel into a short text file.
+
+Input: four counter-collection CSV files written by `rocprofv3 --pmc ...
+--output-format csv`: FETCH_SIZE and WRITE_SIZE of a plain device copy of known
+size (`bench.py --copy-calibration MIB`), and FETCH_SIZE and WRITE_SIZE of the
+kernel. Each counter is scaled by (bytes the copy moved) / (what the counter
+read for it); the result is the kernel's HBM traffic per launch. The summary
+records the SHA-256 of the kernel's source files so that a reader can tell
+whether the kernel changed after the counters were taken.
+
+python -m paper_2311_05322_amd.pmc_summary --copy-mib 1024 \\
+    --copy-fetch C_F.csv --copy-write C_W.csv --fetch K_F.csv --write K_W.csv \\
+    --kernel k_lu_update --command "..." --out profiles/x.md
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = {"k_lu_update": ["csrc/k_dense.hip", "csrc/mx_device.h"],
+           "k_trsm": ["csrc/k_dense.hip", "csrc/mx_device.h"],
+           "k_spmm": ["csrc/k_operator.hip", "csrc/mx_device.h"]}
+
+
+def source_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for rel in SOURCES[kernel]:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _values(path, name_part):
+    out = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if name_part in r["Kernel_Name"]:
+                out.append(float(r["Counter_Value"]))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--copy-mib", type=int, required=True)
+    ap.add_argument("--copy-kernel", default="neg_kernel")
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--kernel", required=True, choices=sorted(SOURCES))
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    kib = a.copy_mib * 1024.0
+    cf, cw = _values(a.copy_fetch, a.copy_kernel), _values(a.copy_write, a.copy_kernel)
+    sf, sw = kib / (sum(cf) / len(cf)), kib / (sum(cw) / len(cw))
+    kf, kw = _values(a.fetch, a.kernel), _values(a.write, a.kernel)
+    if not kf or len(kf) != len(kw):
+        raise SystemExit("kernel dispatch counts differ or are empty")
+    n = len(kf)
+    fetch_b = sum(kf) / n * sf * 1024.0
+    write_b = sum(kw) / n * sw * 1024.0
+    lines = [
+        f"# HBM traffic of {a.kernel}, 1.02M-edge chamber (512 subdomains, 32 transmitters)",
+        "",
+        "Commands (repository root on the MI355X box, `cd /tmp && export TMPDIR=/tmp` first):",
+        "",
+        "```",
+        *a.command,
+        "```",
+        "",
+        f"Copy calibration ({a.copy_mib} MiB read and written per dispatch, {len(cf)} dispatches):",
+        f"FETCH_SIZE {sum(cf) / len(cf):.1f} KiB -> factor {sf:.4f}; WRITE_SIZE {sum(cw) / len(cw):.1f} KiB -> factor {sw:.4f}.",
+        "",
+        f"{a.kernel}: {n} dispatches (one factorisation).",
+        "",
+        "| per launch | counter (KiB) | scaled bytes |",
+        "|---|---:|---:|",
+        f"| read | {sum(kf) / n:.1f} | {fetch_b:.4e} |",
+        f"| written | {sum(kw) / n:.1f} | {write_b:.4e} |",
+        f"| total | | {fetch_b + write_b:.4e} |",
+        "",
+        f"bytes_per_launch: {fetch_b + write_b:.6e}",
+        f"source_sha256: {source_hash(a.kernel)}",
+        "",
+    ]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,11 @@ def jittered_cylinder(radius: float, height: float, c: float, seed: int,
     moved by a seeded uniform offset in [-jitter*c, jitter*c]^3 (small enough
     that no tetrahedron inverts); tetrahedra whose jittered centroid lies in
     the cylinder are kept (staircase boundary), unused vertices are dropped.
+
+    Numbering, as a mesher's locality reordering would leave it: vertices in
+    Morton (Z-curve) order of their lattice position, tetrahedra in Morton
+    order of their lattice cube (the six of one cube consecutive, in Kuhn path
+    order). Each tetrahedron keeps its vertices in Kuhn path order.
     """
     nxy = int(math.ceil(2.0 * radius / c))
     nz = int(math.ceil(height / c))
@@ -108,12 +113,29 @@ def jittered_cylinder(radius: float, height: float, c: float, seed: int,
     xyz = xyz + rng.uniform(-jitter * h, jitter * h, size=xyz.shape)
     cen = xyz[tet].mean(axis=1)
     keep = cen[:, 0] ** 2 + cen[:, 1] ** 2 < radius * radius
-    tet = tet[keep]
+    cube = np.nonzero(keep)[0] // 6
+    ci, cj, ck = cube % nxy, (cube // nxy) % nxy, cube // (nxy * nxy)
+    tet = tet[keep][np.argsort(morton3(ci, cj, ck), kind="stable")]
     used = np.zeros(xyz.shape[0], dtype=bool)
     used[tet.ravel()] = True
+    vid = np.nonzero(used)[0]
+    vi, vj, vk = vid % (nxy + 1), (vid // (nxy + 1)) % (nxy + 1), vid // ((nxy + 1) * (nxy + 1))
+    vid = vid[np.argsort(morton3(vi, vj, vk), kind="stable")]
     newid = np.full(xyz.shape[0], -1, dtype=np.int64)
-    newid[used] = np.arange(int(used.sum()))
-    return np.ascontiguousarray(xyz[used]), newid[tet].astype(np.int32)
+    newid[vid] = np.arange(vid.size)
+    return np.ascontiguousarray(xyz[vid]), newid[tet].astype(np.int32)
+
+
+def morton3(i, j, k):
+    """Z-curve code of non-negative lattice indices (< 2^20 each): bits of
+    i, j, k interleaved, i in the lowest position."""
+    code = np.zeros(np.shape(i), dtype=np.int64)
+    i, j, k = (np.asarray(a, dtype=np.int64) for a in (i, j, k))
+    for b in range(20):
+        code |= ((i >> b) & 1) << (3 * b)
+        code |= ((j >> b) & 1) << (3 * b + 1)
+        code |= ((k >> b) & 1) << (3 * b + 2)
+    return code
 
 
 # --------------------------------------------------------------------------
