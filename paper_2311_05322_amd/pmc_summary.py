@@ -75,7 +75,7 @@ def main():
         f"Copy calibration ({a.copy_mib} MiB read and written per dispatch, {len(cf)} dispatches):",
         f"FETCH_SIZE {sum(cf) / len(cf):.1f} KiB -> factor {sf:.4f}; WRITE_SIZE {sum(cw) / len(cw):.1f} KiB -> factor {sw:.4f}.",
         "",
-        f"{a.kernel}: {n} dispatches (one factorisation).",
+        f"{a.kernel}: {n} dispatches; figures are per-dispatch averages.",
         "",
         "| per launch | counter (KiB) | scaled bytes |",
         "|---|---:|---:|",
