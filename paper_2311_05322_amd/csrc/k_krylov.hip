@@ -85,6 +85,83 @@ __global__ void k_update(int64_t nrows, int nrhs, const double2* __restrict__ V,
   w[idx] = acc;
 }
 
+// Fused Gram-Schmidt passes. Both take w <- w - sum_{i < NV} V_i h[i] (the
+// same arithmetic and order as k_update) and then, on the updated rows,
+// MODE 0: part[b][i][j] = sum over this block's rows of conj(V_i[r][j]) w[r][j]
+//         (the next pass's coefficients, same row split and order as k_dot),
+// MODE 1: npart[b][j] = sum over this block's rows of |w[r][j]|^2 (as k_norm2).
+// The V_i values of a row stay in registers between the update and the dot,
+// so each basis vector is read once per pass instead of twice.
+template <int NV, int MODE>
+__global__ void __launch_bounds__(256) k_cgs_pass(int64_t nrows, int nrhs, const double2* __restrict__ V,
+                                                  int64_t vstride, const double2* __restrict__ h,
+                                                  double2* __restrict__ w, double2* __restrict__ part,
+                                                  double* __restrict__ npart) {
+  const int rpi = blockDim.x / nrhs;
+  const int t = threadIdx.x;
+  const int j = t % nrhs, rl = t / nrhs;
+  const int64_t chunk = (nrows + gridDim.x - 1) / gridDim.x;
+  const int64_t rb = blockIdx.x * chunk, re = min(nrows, rb + chunk);
+  __shared__ double2 hs[NV][32];
+  for (int e = t; e < NV * nrhs; e += blockDim.x) hs[e / nrhs][e % nrhs] = h[e];
+  __syncthreads();
+  double ar[MODE == 0 ? NV : 1], ai[MODE == 0 ? NV : 1];
+  double a2 = 0;
+#pragma unroll
+  for (int i = 0; i < (MODE == 0 ? NV : 1); ++i) { ar[i] = 0; ai[i] = 0; }
+  if (rl < rpi) {
+#pragma unroll 1
+    for (int64_t r = rb + rl; r < re; r += rpi) {
+      const int64_t o = r * nrhs + j;
+      double2 v[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = V[(int64_t)i * vstride + o];
+      double2 acc = w[o];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const double2 hh = hs[i][j];
+        acc.x -= v[i].x * hh.x - v[i].y * hh.y;
+        acc.y -= v[i].x * hh.y + v[i].y * hh.x;
+      }
+      w[o] = acc;
+      if (MODE == 0) {
+#pragma unroll
+        for (int i = 0; i < (MODE == 0 ? NV : 1); ++i) {
+          ar[i] += v[i].x * acc.x + v[i].y * acc.y;
+          ai[i] += v[i].x * acc.y - v[i].y * acc.x;
+        }
+      } else {
+        a2 += acc.x * acc.x + acc.y * acc.y;
+      }
+    }
+  }
+  if (MODE == 0) {
+    __shared__ double2 red[256];
+    for (int i = 0; i < NV; ++i) {
+      red[t] = make_double2(ar[i], ai[i]);
+      __syncthreads();
+      if (rl == 0 && t < nrhs) {
+        double sr = 0, si = 0;
+        for (int q = 0; q < rpi; ++q) {
+          sr += red[q * nrhs + j].x;
+          si += red[q * nrhs + j].y;
+        }
+        part[((int64_t)blockIdx.x * NV + i) * nrhs + j] = make_double2(sr, si);
+      }
+      __syncthreads();
+    }
+  } else {
+    __shared__ double redn[256];
+    redn[t] = a2;
+    __syncthreads();
+    if (rl == 0 && t < nrhs) {
+      double sum = 0;
+      for (int q = 0; q < rpi; ++q) sum += redn[q * nrhs + j];
+      npart[(int64_t)blockIdx.x * nrhs + j] = sum;
+    }
+  }
+}
+
 // part[b][j] = sum over this block's rows of |w[r][j]|^2
 __global__ void __launch_bounds__(256) k_norm2(int64_t nrows, int nrhs, const double2* __restrict__ w,
                                                double* __restrict__ part) {
@@ -275,6 +352,37 @@ void launch_dot(hipStream_t s, int64_t nrows, int nrhs, const double2* V, int64_
     }
     hipLaunchKernelGGL(k_dot_final, dim3(nblk(nv * nrhs, 256)), dim3(256), 0, s, nb, nv, nrhs, part, out, i0);
   }
+}
+
+int cgs_fused_max() { return 32; }
+
+int launch_cgs_pass(hipStream_t s, int64_t nrows, int nrhs, const double2* V, int64_t vstride, int nv,
+                    const double2* h, double2* w, double2* part, double* npart, double2* hout, double* nout) {
+  if (nv < 1 || nv > 32 || nrhs > 32 || nrhs < 1) return -1;
+  const int nb = dot_blocks(nrows);
+  const int rpi = 256 / nrhs;
+  const int threads = rpi * nrhs;
+  const bool dot = hout != nullptr;
+  switch (nv) {
+#define MXC(K)                                                                                                    \
+  case K:                                                                                                         \
+    if (dot)                                                                                                      \
+      hipLaunchKernelGGL((k_cgs_pass<K, 0>), dim3(nb), dim3(threads), 0, s, nrows, nrhs, V, vstride, h, w, part, \
+                         npart);                                                                                  \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_cgs_pass<K, 1>), dim3(nb), dim3(threads), 0, s, nrows, nrhs, V, vstride, h, w, part, \
+                         npart);                                                                                  \
+    break;
+    MXC(1) MXC(2) MXC(3) MXC(4) MXC(5) MXC(6) MXC(7) MXC(8) MXC(9) MXC(10) MXC(11) MXC(12) MXC(13) MXC(14)
+    MXC(15) MXC(16) MXC(17) MXC(18) MXC(19) MXC(20) MXC(21) MXC(22) MXC(23) MXC(24) MXC(25) MXC(26) MXC(27)
+    MXC(28) MXC(29) MXC(30) MXC(31) MXC(32)
+#undef MXC
+  }
+  if (dot)
+    hipLaunchKernelGGL(k_dot_final, dim3(nblk(nv * nrhs, 256)), dim3(256), 0, s, nb, nv, nrhs, part, hout, 0);
+  else
+    hipLaunchKernelGGL(k_norm_final, dim3(nblk(nrhs, 256)), dim3(256), 0, s, nb, nrhs, npart, nout);
+  return 0;
 }
 
 void launch_update(hipStream_t s, int64_t nrows, int nrhs, const double2* V, int64_t vstride, int nv,

@@ -363,7 +363,7 @@ int ensure_workspace(mx_ctx* c, int nrhs, int m) {
     CK(c->y.alloc((size_t)m * nrhs));
     CK(c->h1.alloc((size_t)(m + 1) * nrhs));
     CK(c->h2.alloc((size_t)(m + 1) * nrhs));
-    CK(c->dotpart.alloc((size_t)dot_blocks(ne) * 8 * nrhs));
+    CK(c->dotpart.alloc((size_t)dot_blocks(ne) * std::max(8, std::min(m + 1, cgs_fused_max())) * nrhs));
     CK(c->normpart.alloc((size_t)dot_blocks(ne) * nrhs));
     CK(c->bnorm.alloc(nrhs));
     CK(c->hn.alloc(nrhs));
@@ -728,10 +728,16 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
   auto arnoldi_tail = [&](int k) -> int {
     double2* w = c->V.p + (k + 1) * blk;
     launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h1.p);
-    launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w);
-    launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h2.p);
-    launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h2.p, w);
-    launch_norm(s, ne, nrhs, w, c->normpart.p, c->hn.p);
+    if (nrhs <= 32 && k + 1 <= cgs_fused_max()) {
+      // second pass fused: update with h1 and form h2; then update with h2 and ||w||
+      launch_cgs_pass(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w, c->dotpart.p, nullptr, c->h2.p, nullptr);
+      launch_cgs_pass(s, ne, nrhs, c->V.p, blk, k + 1, c->h2.p, w, nullptr, c->normpart.p, nullptr, c->hn.p);
+    } else {
+      launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w);
+      launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h2.p);
+      launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h2.p, w);
+      launch_norm(s, ne, nrhs, w, c->normpart.p, c->hn.p);
+    }
     launch_scale(s, ne, nrhs, w, c->hn.p, w);
     launch_givens(s, k, m, nrhs, c->h1.p, c->h2.p, c->hn.p, c->H.p, c->cs.p, c->sn.p, c->g.p, c->bnorm.p, rtol,
                   c->conv.p, c->kdone.p, c->res.p);
