@@ -32,6 +32,9 @@ WORKLOADS = {
     # 1.02M-edge cylindrical chamber, shoulder phantom, 32 z-dipoles on r=0.11 m,
     # 512 subdomains of about 5.2k unknowns (one vertex layer of overlap)
     "chamber1m": dict(kind="chamber", c=0.004, mesh_seed=0, tear_seed=0, nsub=512, overlap=1, nsrc=32),
+    # 2.08M-edge chamber (3.16 mm lattice), 2048 subdomains of about 3.2k unknowns
+    # (one vertex layer of overlap): complex64 factors 176 GB; complex128 would not fit
+    "chamber2m": dict(kind="chamber", c=0.00316, mesh_seed=0, tear_seed=0, nsub=2048, overlap=1, nsrc=32),
     # same chamber family at 8 mm lattice (about 0.13M edges), 64 subdomains
     "chamber130k": dict(kind="chamber", c=0.008, mesh_seed=0, tear_seed=0, nsub=64, overlap=1, nsrc=32),
     # 4,184-edge unit cube, 8 dipoles, 8 subdomains, one layer of overlap
@@ -222,7 +225,7 @@ def main():
     ctx.set_stream(stream.cuda_stream)
     t = time.perf_counter()
     ctx.assemble(p.xyz, p.tet, p.eps, p.eps_kind, p.freq, p.eps_b)
-    ctx.setup_schwarz(p.nsub, p.overlap, factor=False)
+    ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, factor=False)
     log(f"topology + partition: {time.perf_counter() - t:.1f} s")
     sz = ctx.sizes()
     part, dof_ptr, *_ = ctx.partition()
@@ -236,7 +239,7 @@ def main():
     learned = os.path.exists(wfile) and not args.no_learned
     if learned:
         from paper_2311_05322_amd.train_coarse import load_weights
-        ctx.setup_schwarz(p.nsub, p.overlap, factor=False, coarse=True)
+        ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, factor=False, coarse=True)
         load_weights(ctx, wfile)
     variants = {}
     order = ([("c64_learned", mx.MX_PREC_C64, True)] if learned else []) + [("c64_plain", mx.MX_PREC_C64, False)]

@@ -28,6 +28,7 @@ import paper_2311_05322_amd as mx  # noqa: E402
 SHAPES = {
     "chamber1m": dict(c=0.004, mesh_seed=0, nsub=512, overlap=1, nsrc=32),
     "chamber130k": dict(c=0.008, mesh_seed=0, nsub=64, overlap=1, nsrc=32),
+    "chamber2m": dict(c=0.00316, mesh_seed=0, nsub=2048, overlap=1, nsrc=32),
 }
 
 
@@ -45,10 +46,13 @@ def main():
     ap.add_argument("--snapshots", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--epochs-per-call", type=int, default=2, help="epochs per library call (progress lines)")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--out", default=os.path.join(HERE, "weights", "coarse_chamber1m.npz"))
+    ap.add_argument("--out", default=None, help="default: weights/coarse_<workload>.npz next to this file")
     a = ap.parse_args()
+    if a.out is None:
+        a.out = os.path.join(HERE, "weights", f"coarse_{a.workload}.npz")
     shp = SHAPES[a.workload]
     ctx = mx.Context(0)
     first = True
@@ -65,7 +69,12 @@ def main():
                                rtol_exact=1e-10)
         print(f"[collect] tear seed {ts}: {n} snapshots ({time.time() - t0:.1f} s)", flush=True)
     t1 = time.time()
-    hist = ctx.coarse_train(a.epochs, a.batch, a.lr, a.seed)
+    hist = []
+    for e0 in range(0, a.epochs, a.epochs_per_call):
+        ne = min(a.epochs_per_call, a.epochs - e0)
+        hist.extend(ctx.coarse_train(ne, a.batch, a.lr, a.seed + e0))
+        print(f"[train] epochs {e0 + ne}/{a.epochs}: loss {hist[-1]:.4f} ({time.time() - t1:.1f} s)", flush=True)
+    hist = np.asarray(hist)
     print(f"[train] {a.epochs} epochs in {time.time() - t1:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}", flush=True)
     theta, sx, sy = ctx.coarse_weights()
     os.makedirs(os.path.dirname(a.out), exist_ok=True)
