@@ -341,7 +341,9 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
 // the passes over the trailing matrix), complex products in the
 // 3-multiplication form (three real MFMA products instead of four); the
 // panels are staged in 32-deep chunks (33.5 KB of LDS for complex64, 67 KB
-// for complex128); the C tile is loaded before the staging.
+// for complex128), for complex64 with the next chunk already in registers
+// while the current one is multiplied; the C tile is loaded before the
+// staging.
 // --------------------------------------------------------------------------
 constexpr int KCH = 32;
 
@@ -378,37 +380,66 @@ __global__ void __launch_bounds__(256, 2) k_lu_update(C_t<R>* __restrict__ pool,
   for (int it = 0; it < 2; ++it)
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) { t1[it][jt] = zacc<R>(); t2[it][jt] = zacc<R>(); t3[it][jt] = zacc<R>(); }
-  for (int kc = 0; kc < kd; kc += KCH) {
-    if (kc) __syncthreads();
-    for (int e = tid; e < NB * KCH; e += 256) {
-      int r = e / KCH, c = e % KCH;
-      As[r][c] = A[(int64_t)(i0 + r) * N + kl + kc + c];
-      int r2 = e / NB, c2 = e % NB;
-      Bs[r2][c2] = A[(int64_t)(kl + kc + r2) * N + j0 + c2];
+  // one 4-deep step of the 3-multiplication product out of LDS
+  auto mma = [&](int kk) {
+    C av[2], bv[2];
+    R as[2], bs[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      av[it] = As[wr + 16 * it + (lane & 15)][kk + (lane >> 4)];
+      as[it] = av[it].x + av[it].y;
     }
-    __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < KCH; kk += 4) {
-      C av[2], bv[2];
-      R as[2], bs[2];
+    for (int jt = 0; jt < 2; ++jt) {
+      bv[jt] = Bs[kk + (lane >> 4)][wc + 16 * jt + (lane & 15)];
+      bs[jt] = bv[jt].x + bv[jt].y;
+    }
 #pragma unroll
-      for (int it = 0; it < 2; ++it) {
-        av[it] = As[wr + 16 * it + (lane & 15)][kk + (lane >> 4)];
-        as[it] = av[it].x + av[it].y;
-      }
+    for (int it = 0; it < 2; ++it)
 #pragma unroll
       for (int jt = 0; jt < 2; ++jt) {
-        bv[jt] = Bs[kk + (lane >> 4)][wc + 16 * jt + (lane & 15)];
-        bs[jt] = bv[jt].x + bv[jt].y;
+        t1[it][jt] = mfma(av[it].x, bv[jt].x, t1[it][jt]);
+        t2[it][jt] = mfma(av[it].y, bv[jt].y, t2[it][jt]);
+        t3[it][jt] = mfma(as[it], bs[jt], t3[it][jt]);
       }
+  };
+  if constexpr (sizeof(R) == 4) {
+    // complex64: the next chunk's operands are loaded into registers while
+    // the current chunk is multiplied out of LDS
+    C ra[NB * KCH / 256], rb[NB * KCH / 256];
+    auto gload = [&](int kc) {
 #pragma unroll
-      for (int it = 0; it < 2; ++it)
+      for (int q = 0; q < NB * KCH / 256; ++q) {
+        const int e = tid + 256 * q;
+        ra[q] = A[(int64_t)(i0 + e / KCH) * N + kl + kc + e % KCH];
+        rb[q] = A[(int64_t)(kl + kc + e / NB) * N + j0 + e % NB];
+      }
+    };
+    gload(0);
+    for (int kc = 0; kc < kd; kc += KCH) {
+      if (kc) __syncthreads();
 #pragma unroll
-        for (int jt = 0; jt < 2; ++jt) {
-          t1[it][jt] = mfma(av[it].x, bv[jt].x, t1[it][jt]);
-          t2[it][jt] = mfma(av[it].y, bv[jt].y, t2[it][jt]);
-          t3[it][jt] = mfma(as[it], bs[jt], t3[it][jt]);
-        }
+      for (int q = 0; q < NB * KCH / 256; ++q) {
+        const int e = tid + 256 * q;
+        As[e / KCH][e % KCH] = ra[q];
+        Bs[e / NB][e % NB] = rb[q];
+      }
+      __syncthreads();
+      if (kc + KCH < kd) gload(kc + KCH);
+#pragma unroll
+      for (int kk = 0; kk < KCH; kk += 4) mma(kk);
+    }
+  } else {
+    // complex128: staged directly (the register budget holds no second chunk)
+    for (int kc = 0; kc < kd; kc += KCH) {
+      if (kc) __syncthreads();
+      for (int e = tid; e < NB * KCH; e += 256) {
+        As[e / KCH][e % KCH] = A[(int64_t)(i0 + e / KCH) * N + kl + kc + e % KCH];
+        Bs[e / NB][e % NB] = A[(int64_t)(kl + kc + e / NB) * N + j0 + e % NB];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KCH; kk += 4) mma(kk);
     }
   }
 #pragma unroll
