@@ -41,6 +41,7 @@ template <typename R> __device__ inline Acc_t<R> zacc() {
   return z;
 }
 template <typename C> __device__ inline C czero() { C z; z.x = 0; z.y = 0; return z; }
+template <typename C, typename R> __device__ inline C make_c(R re, R im) { C z; z.x = re; z.y = im; return z; }
 template <typename C> __device__ inline C cone() { C z; z.x = 1; z.y = 0; return z; }
 template <typename C> __device__ inline C cmulT(C a, C b) {
   C z; z.x = a.x * b.x - a.y * b.y; z.y = a.x * b.y + a.y * b.x; return z;
@@ -83,15 +84,34 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
   C a[RPT][W];
   for (int s0 = 0; s0 < NB; s0 += W) {
     const int c0 = k0 + s0;
-    // (A) top rows of the sub-panel columns: U[k0:c0, c0:c0+W] = L11^{-1} A
-    if (tid < W) {
-      const int cc = c0 + tid;
-      for (int i = 0; i < s0; ++i) {
-        C x = A[(int64_t)(k0 + i) * N + cc];
-        for (int l = 0; l < i; ++l) x = csubT(x, cmulT(A[(int64_t)(k0 + i) * N + k0 + l], Utop[l][tid]));
-        Utop[i][tid] = x;
-        A[(int64_t)(k0 + i) * N + cc] = x;
+    // (A) top rows of the sub-panel columns: U[k0:c0, c0:c0+W] = L11^{-1} A by
+    // forward substitution, one wave per column, lane l holding the l-th
+    // term of each inner product. L11 rows are final once their pivots are
+    // taken, so the rows of the previous sub-panel are copied into Lt here.
+    if (s0 > 0)
+      for (int e = tid; e < W * s0; e += PT) {
+        const int i = s0 - W + e / s0, l = e % s0;
+        if (l < i) Lt[i][l] = A[(int64_t)(k0 + i) * N + k0 + l];
       }
+    __syncthreads();
+    if (wv < W && s0 > 0) {
+      const int cc = c0 + wv;
+      const C mine = lane < s0 ? A[(int64_t)(k0 + lane) * N + cc] : czero<C>();
+      for (int i = 0; i < s0; ++i) {
+        C part = lane < i ? cmulT(Lt[i][lane], Utop[lane][wv]) : czero<C>();
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          part.x += __shfl_xor(part.x, off);
+          part.y += __shfl_xor(part.y, off);
+        }
+        const C ai = make_c<C>(__shfl(mine.x, i), __shfl(mine.y, i));
+        const C x = csubT(ai, part);
+        // one wave: its LDS accesses are performed in order, so the next
+        // iteration's reads see this write
+        if (lane == 0) Utop[i][wv] = x;
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (lane < s0) A[(int64_t)(k0 + lane) * N + cc] = Utop[lane][wv];
     }
     __syncthreads();
     // (B) load sub-panel rows [c0, N) and subtract L[r, k0:c0] U[k0:c0, sub]
@@ -102,10 +122,15 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
         const C* row = A + (int64_t)r * N;
 #pragma unroll
         for (int j = 0; j < W; ++j) a[i][j] = row[c0 + j];
-        for (int l = 0; l < s0; ++l) {
-          C lv = row[k0 + l];
+        // W consecutive L entries per load (32 bytes: one sector per lane)
+        for (int l = 0; l < s0; l += W) {
+          C lv[W];
 #pragma unroll
-          for (int j = 0; j < W; ++j) a[i][j] = csubT(a[i][j], cmulT(lv, Utop[l][j]));
+          for (int q = 0; q < W; ++q) lv[q] = row[k0 + l + q];
+#pragma unroll
+          for (int q = 0; q < W; ++q)
+#pragma unroll
+            for (int j = 0; j < W; ++j) a[i][j] = csubT(a[i][j], cmulT(lv[q], Utop[l + q][j]));
         }
       }
     }
