@@ -264,7 +264,8 @@ __global__ void k_givens(int k, int m, int nrhs, const double2* __restrict__ h1,
   double2 gn = g[(k + 1) * nrhs + j];
   double rr = bnorm[j] > 0 ? hypot(gn.x, gn.y) / bnorm[j] : 0.0;
   res[j] = rr;
-  if (!conv[j] && rr <= rtol) { conv[j] = 1; kdone[j] = k + 1; }
+  // a zero right-hand side has the zero solution: no step contributes
+  if (!conv[j] && rr <= rtol) { conv[j] = 1; kdone[j] = bnorm[j] > 0 ? k + 1 : 0; }
 #undef HH
 }
 
@@ -284,7 +285,8 @@ __global__ void k_lsq(int ksteps, int m, int nrhs, const double2* __restrict__ H
       acc.y -= h.x * yy.y + h.y * yy.x;
     }
     double2 d = H[((int64_t)i * m + i) * nrhs + j];
-    y[i * nrhs + j] = cdiv(acc, d);
+    // an exactly singular rotated Hessenberg (breakdown) contributes nothing
+    y[i * nrhs + j] = (d.x != 0.0 || d.y != 0.0) ? cdiv(acc, d) : make_double2(0.0, 0.0);
   }
 }
 
