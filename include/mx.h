@@ -201,7 +201,9 @@ int mx_setup_schwarz(mx_ctx* ctx, int32_t nsub, int32_t overlap, const mx_schwar
  * S[i][j] = p_i . E_j(x_i) for the receivers rx (NULL: rx = tx).
  *   E  [ne][ntx] fields, host or device, may be NULL
  *   S  [nrx][ntx] host or device, may be NULL
- * Returns MX_ENOTCONV (outputs still written) when maxit is reached. */
+ * Returns MX_ENOTCONV (outputs still written) when maxit is reached;
+ * MX_EINVAL for an empty source set, more than 256 transmitters or a point
+ * outside the mesh. */
 int mx_solve(mx_ctx* ctx, const mx_sources* tx, const mx_sources* rx, double rtol,
              mx_c128* E, mx_c128* S, mx_solve_info* info);
 

@@ -1352,6 +1352,8 @@ int mx_solve_rhs(mx_ctx* c, const mx_c128* b, int32_t nrhs, double rtol, mx_c128
 int mx_solve(mx_ctx* c, const mx_sources* tx, const mx_sources* rx, double rtol, mx_c128* E, mx_c128* S,
              mx_solve_info* info) {
   if (!c || !tx) return set_err(MX_EINVAL, "bad arguments");
+  if (tx->n <= 0 || (rx && rx->n <= 0)) return set_err(MX_EINVAL, "empty source set");
+  if (tx->n > 256) return set_err(MX_EINVAL, "at most 256 transmitters per solve");
   if (!(rtol > 0)) return set_err(MX_EINVAL, "rtol must be positive");
   if (!c->factored) return set_err(MX_ESTATE, "mx_setup_schwarz (with factor=1) must come first");
   CK(use_device(c));

@@ -71,3 +71,27 @@ def test_autotune_off_same_answer(chamber):
     finally:
         ctx.set_autotune(True)
     assert np.linalg.norm(X1 - X2) <= 1e-8 * np.linalg.norm(X1)
+
+
+def test_limits_are_errors():
+    """Sizes beyond the documented limits are rejected before any launch:
+    a subdomain above 8192 unknowns, more than 256 right-hand sides, no
+    transmitters."""
+    xyz, tet = workload.kuhn_cube(14, 0.1)   # 18,389 edges in one subdomain
+    ctx = mx.Context(0)
+    try:
+        eps = np.full(len(tet), workload.eps_r(44.0, 0.6, 1e9))
+        ctx.assemble(xyz, tet, eps, 0, 1e9, eps[0])
+        with pytest.raises(mx.MxError) as e:
+            ctx.setup_schwarz(1, 1)
+        assert e.value.code == mx.MX_EINVAL
+        ctx.setup_schwarz(8, 1)
+        B = np.zeros((ctx.ne, 257), np.complex128)
+        with pytest.raises(mx.MxError) as e:
+            ctx.solve_rhs(B)
+        assert e.value.code == mx.MX_EINVAL
+        with pytest.raises(mx.MxError) as e:
+            ctx.solve(np.zeros((0, 3)), np.zeros((0, 3)), rtol=1e-8)
+        assert e.value.code == mx.MX_EINVAL
+    finally:
+        ctx.close()
