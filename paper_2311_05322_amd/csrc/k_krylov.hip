@@ -92,6 +92,8 @@ __global__ void k_update(int64_t nrows, int nrhs, const double2* __restrict__ V,
 // MODE 1: npart[b][j] = sum over this block's rows of |w[r][j]|^2 (as k_norm2).
 // The V_i values of a row stay in registers between the update and the dot,
 // so each basis vector is read once per pass instead of twice.
+// MODE 2: no update; the MODE 0 dots of w itself, all NV in one sweep (w read
+// once instead of once per 8 basis vectors as in k_dot).
 template <int NV, int MODE>
 __global__ void __launch_bounds__(256) k_cgs_pass(int64_t nrows, int nrhs, const double2* __restrict__ V,
                                                   int64_t vstride, const double2* __restrict__ h,
@@ -103,12 +105,13 @@ __global__ void __launch_bounds__(256) k_cgs_pass(int64_t nrows, int nrhs, const
   const int64_t chunk = (nrows + gridDim.x - 1) / gridDim.x;
   const int64_t rb = blockIdx.x * chunk, re = min(nrows, rb + chunk);
   __shared__ double2 hs[NV][32];
-  for (int e = t; e < NV * nrhs; e += blockDim.x) hs[e / nrhs][e % nrhs] = h[e];
+  if (MODE != 2)
+    for (int e = t; e < NV * nrhs; e += blockDim.x) hs[e / nrhs][e % nrhs] = h[e];
   __syncthreads();
-  double ar[MODE == 0 ? NV : 1], ai[MODE == 0 ? NV : 1];
+  double ar[MODE != 1 ? NV : 1], ai[MODE != 1 ? NV : 1];
   double a2 = 0;
 #pragma unroll
-  for (int i = 0; i < (MODE == 0 ? NV : 1); ++i) { ar[i] = 0; ai[i] = 0; }
+  for (int i = 0; i < (MODE != 1 ? NV : 1); ++i) { ar[i] = 0; ai[i] = 0; }
   if (rl < rpi) {
 #pragma unroll 1
     for (int64_t r = rb + rl; r < re; r += rpi) {
@@ -117,16 +120,18 @@ __global__ void __launch_bounds__(256) k_cgs_pass(int64_t nrows, int nrhs, const
 #pragma unroll
       for (int i = 0; i < NV; ++i) v[i] = V[(int64_t)i * vstride + o];
       double2 acc = w[o];
+      if (MODE != 2) {
 #pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        const double2 hh = hs[i][j];
-        acc.x -= v[i].x * hh.x - v[i].y * hh.y;
-        acc.y -= v[i].x * hh.y + v[i].y * hh.x;
+        for (int i = 0; i < NV; ++i) {
+          const double2 hh = hs[i][j];
+          acc.x -= v[i].x * hh.x - v[i].y * hh.y;
+          acc.y -= v[i].x * hh.y + v[i].y * hh.x;
+        }
+        w[o] = acc;
       }
-      w[o] = acc;
-      if (MODE == 0) {
+      if (MODE != 1) {
 #pragma unroll
-        for (int i = 0; i < (MODE == 0 ? NV : 1); ++i) {
+        for (int i = 0; i < (MODE != 1 ? NV : 1); ++i) {
           ar[i] += v[i].x * acc.x + v[i].y * acc.y;
           ai[i] += v[i].x * acc.y - v[i].y * acc.x;
         }
@@ -135,7 +140,7 @@ __global__ void __launch_bounds__(256) k_cgs_pass(int64_t nrows, int nrhs, const
       }
     }
   }
-  if (MODE == 0) {
+  if (MODE != 1) {
     __shared__ double2 red[256];
     for (int i = 0; i < NV; ++i) {
       red[t] = make_double2(ar[i], ai[i]);
@@ -365,10 +370,14 @@ int launch_cgs_pass(hipStream_t s, int64_t nrows, int nrhs, const double2* V, in
   const int rpi = 256 / nrhs;
   const int threads = rpi * nrhs;
   const bool dot = hout != nullptr;
+  const bool upd = h != nullptr;
   switch (nv) {
 #define MXC(K)                                                                                                    \
   case K:                                                                                                         \
-    if (dot)                                                                                                      \
+    if (dot && !upd)                                                                                              \
+      hipLaunchKernelGGL((k_cgs_pass<K, 2>), dim3(nb), dim3(threads), 0, s, nrows, nrhs, V, vstride, h, w, part, \
+                         npart);                                                                                  \
+    else if (dot)                                                                                                 \
       hipLaunchKernelGGL((k_cgs_pass<K, 0>), dim3(nb), dim3(threads), 0, s, nrows, nrhs, V, vstride, h, w, part, \
                          npart);                                                                                  \
     else                                                                                                          \

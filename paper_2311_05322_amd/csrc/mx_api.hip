@@ -727,12 +727,14 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
   // Gram-Schmidt (twice), normalisation and the Givens update of step k
   auto arnoldi_tail = [&](int k) -> int {
     double2* w = c->V.p + (k + 1) * blk;
-    launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h1.p);
     if (nrhs <= 32 && k + 1 <= cgs_fused_max()) {
-      // second pass fused: update with h1 and form h2; then update with h2 and ||w||
+      // first pass: all k+1 coefficients in one sweep; second pass fused:
+      // update with h1 and form h2, then update with h2 and ||w||
+      launch_cgs_pass(s, ne, nrhs, c->V.p, blk, k + 1, nullptr, w, c->dotpart.p, nullptr, c->h1.p, nullptr);
       launch_cgs_pass(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w, c->dotpart.p, nullptr, c->h2.p, nullptr);
       launch_cgs_pass(s, ne, nrhs, c->V.p, blk, k + 1, c->h2.p, w, nullptr, c->normpart.p, nullptr, c->hn.p);
     } else {
+      launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h1.p);
       launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h1.p, w);
       launch_dot(s, ne, nrhs, c->V.p, blk, k + 1, w, c->dotpart.p, c->h2.p);
       launch_update(s, ne, nrhs, c->V.p, blk, k + 1, c->h2.p, w);

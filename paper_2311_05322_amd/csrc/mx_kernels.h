@@ -100,8 +100,9 @@ int lu_max_swap_rows();
 int dot_blocks(int64_t nrows);
 void launch_dot(hipStream_t s, int64_t nrows, int nrhs, const double2* V, int64_t vstride, int nvec,
                 const double2* w, double2* part, double2* out);
-// w <- w - V h (nv basis vectors), then hout = V^H w (hout != NULL) or
-// nout = ||w|| per column (hout == NULL); nv, nrhs <= 32; returns -1 otherwise
+// w <- w - V h (nv basis vectors; skipped when h == NULL), then hout = V^H w
+// (hout != NULL) or nout = ||w|| per column (hout == NULL); nv, nrhs <= 32;
+// returns -1 otherwise
 int cgs_fused_max();
 int launch_cgs_pass(hipStream_t s, int64_t nrows, int nrhs, const double2* V, int64_t vstride, int nv,
                     const double2* h, double2* w, double2* part, double* npart, double2* hout, double* nout);
