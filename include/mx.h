@@ -91,6 +91,20 @@ typedef struct {
   const mx_c128* moment;
 } mx_sources;
 
+/* Waveguide port (Sec. III-B, eq. (1)): a planar rectangle on the mesh
+ * boundary with outward unit normal `normal`, broad-side direction `u`
+ * (orthogonalised against the normal), width a along u and height b along
+ * v = normal x u, centred at `centre`, filled with relative permittivity eps.
+ * Its TE10 profile is e(x) = sin(pi (s + a/2) / a) v, s = (x - centre).u,
+ * and beta = sqrt(k0^2 eps - (pi/a)^2) with Im beta <= 0. */
+typedef struct {
+  double centre[3];
+  double normal[3];
+  double u[3];
+  double a, b;
+  mx_c128 eps;
+} mx_port;
+
 /* Per-solve diagnostics (arrays are caller-owned, length nrhs, may be NULL). */
 typedef struct {
   int32_t* iters;      /* Krylov iterations per right-hand side */
@@ -160,6 +174,27 @@ typedef struct {
 } mx_tuning;
 int mx_set_autotune(mx_ctx* ctx, int enable);
 int mx_get_tuning(mx_ctx* ctx, mx_tuning* out);
+
+/* Port form of the boundary conditions of eq. (1) (Sec. III-B). A boundary
+ * face belongs to port p when its centroid lies in that port's plane and
+ * rectangle (relative tolerance 1e-6 of a + b); port faces carry
+ * j beta_p int (E x n).(v x n) in place of the impedance term. With pec != 0
+ * every other boundary face is a metallic wall (n x E = 0): its edges are
+ * eliminated symmetrically (row and column cleared, diagonal 1, zero
+ * right-hand side) in the operator and in the subdomain matrices; with
+ * pec == 0 they keep the impedance condition. Needs a mesh (mx_assemble);
+ * re-assembles the operator values; mx_setup_schwarz must follow.
+ * nports = 0 restores the impedance boundary everywhere. A new mesh clears
+ * the ports. Errors: MX_EINVAL (bad sizes or non-finite data), MX_ESTATE. */
+int mx_set_ports(mx_ctx* ctx, int32_t nports, const mx_port* ports, int32_t pec);
+
+/* All-port solve (eqs. (1), (3)): transmitter p is the TE10 incidence
+ * g = 2 j beta_p e_p on port p (b_e = int g.N_e over the port), all ports as
+ * one block right-hand side, FGMRES to relative true residual rtol;
+ * S[i][j] = int_{port i} E_j.e_i / int_{port i} e_i.e_i - delta_ij.
+ *   E [ne][nports] (host or device, may be NULL), S [nports][nports].
+ * Returns MX_ENOTCONV (outputs written) when maxit is reached. */
+int mx_solve_ports(mx_ctx* ctx, double rtol, mx_c128* E, mx_c128* S, mx_solve_info* info);
 
 /* enable != 0 (the default): Arnoldi steps that use the one-level
  * preconditioner are captured as HIP graphs and replayed. A step runs eagerly

@@ -24,7 +24,8 @@ EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_sol
            "mx_get_matrix_values", "mx_get_partition", "mx_get_local_matrix", "mx_point_functionals",
            "mx_set_stream", "mx_set_autotune", "mx_get_tuning", "mx_set_graphs", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_coarse_num_params", "mx_coarse_init",
            "mx_coarse_set_weights", "mx_coarse_get_weights", "mx_coarse_features", "mx_coarse_forward",
-           "mx_coarse_loss_grad", "mx_coarse_collect", "mx_coarse_clear", "mx_coarse_train", "mx_last_error"]
+           "mx_coarse_loss_grad", "mx_coarse_collect", "mx_coarse_clear", "mx_coarse_train", "mx_set_ports",
+           "mx_solve_ports", "mx_last_error"]
 
 KERNEL_CLASSES = ["lu_panel", "lu_rowpanel", "lu_update", "lu_inv", "trsm_lower", "trsm_upper", "spmm",
                   "restrict", "prolong", "cgs", "assemble", "local", "coarse"]
@@ -51,6 +52,13 @@ class SchwarzOpts(ct.Structure):
 
 class Sources(ct.Structure):
     _fields_ = [("n", ct.c_int32), ("pos", ct.c_void_p), ("moment", ct.c_void_p)]
+
+
+class Port(ct.Structure):
+    """Waveguide port: rectangle (centre, outward normal, broad side u, a x b)
+    filled with relative permittivity eps; TE10 incidence (Sec. III-B)."""
+    _fields_ = [("centre", ct.c_double * 3), ("normal", ct.c_double * 3), ("u", ct.c_double * 3),
+                ("a", ct.c_double), ("b", ct.c_double), ("eps", c128)]
 
 
 class SolveInfo(ct.Structure):
@@ -115,6 +123,8 @@ def lib():
             "mx_coarse_collect": [vp, ct.POINTER(Sources), i32, i32, dbl, ct.POINTER(i32)],
             "mx_coarse_clear": [vp],
             "mx_coarse_train": [vp, i32, i32, dbl, ct.c_uint64, vp],
+            "mx_set_ports": [vp, i32, ct.POINTER(Port), i32],
+            "mx_solve_ports": [vp, dbl, vp, vp, ct.POINTER(SolveInfo)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -165,6 +175,7 @@ class Context:
         h = ct.c_void_p()
         _check(lib().mx_create(ct.byref(h), device))
         self._h = h
+        self.nports = 0
         self.ne = 0
 
     def close(self):
@@ -228,6 +239,8 @@ class Context:
         eb = complex(eps_b)
         _check(lib().mx_assemble(self._h, mp, _ptr(eps), int(eps_kind), float(freq), c128(eb.real, eb.imag)))
         self.ne = self.sizes().ne
+        if not reuse_mesh:
+            self.nports = 0  # a new mesh clears the ports
         del keep
 
     def setup_schwarz(self, nsub, overlap, precision=MX_PREC_C128, restart=30, maxit=2000, factor=True,
@@ -255,6 +268,35 @@ class Context:
         info = SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
         rc = lib().mx_solve(self._h, ct.byref(tx), ct.byref(rxs) if rxs is not None else None, float(rtol),
                             _ptr(E), _ptr(S), ct.byref(info))
+        _check(rc, allow=(MX_ENOTCONV,))
+        return E, S, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
+                      "t_iter": info.t_iter, "converged": rc == MX_OK, "fallback": info.fallback}
+
+    def set_ports(self, ports, pec=True):
+        """Waveguide ports (objects with centre, normal, u, a, b, eps) and, with
+        pec, metallic walls on the rest of the boundary; [] restores the
+        impedance boundary. Re-assembles the operator: set up Schwarz after."""
+        arr = (Port * max(1, len(ports)))()
+        for i, p in enumerate(ports):
+            e = complex(p.eps)
+            arr[i] = Port((ct.c_double * 3)(*p.centre), (ct.c_double * 3)(*p.normal), (ct.c_double * 3)(*p.u),
+                          float(p.a), float(p.b), c128(e.real, e.imag))
+        _check(lib().mx_set_ports(self._h, len(ports), arr, 1 if pec else 0))
+        self.nports = len(ports)
+
+    def solve_ports(self, rtol=1e-8, E=None, S=None, want_E=True):
+        """All-port solve: TE10 incidence on every port; returns (E, S, info)
+        with S[i][j] the TE10 amplitude received on port i from port j minus
+        the incident unit wave."""
+        npt = self.nports
+        if E is None and want_E:
+            E = np.zeros((self.ne, npt), dtype=np.complex128)
+        if S is None:
+            S = np.zeros((npt, npt), dtype=np.complex128)
+        iters = np.zeros(npt, dtype=np.int32)
+        relres = np.zeros(npt, dtype=np.float64)
+        info = SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        rc = lib().mx_solve_ports(self._h, float(rtol), _ptr(E), _ptr(S), ct.byref(info))
         _check(rc, allow=(MX_ENOTCONV,))
         return E, S, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
                       "t_iter": info.t_iter, "converged": rc == MX_OK, "fallback": info.fallback}

@@ -120,7 +120,7 @@ __global__ void k_element(int32_t nt, const int32_t* __restrict__ ts, const doub
 __global__ void k_face(int32_t n, const int32_t* __restrict__ ftet, const int32_t* __restrict__ flf,
                        const int32_t* __restrict__ ts, const double* __restrict__ xyz,
                        const double2* __restrict__ eps, int eps_kind, int per_tet_k, double k0,
-                       double2 kconst, double2* __restrict__ out) {
+                       double2 kconst, const double2* __restrict__ kface, double2* __restrict__ out) {
   int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= n) return;
   int32_t t = ftet[f], lf = flf[f];
@@ -147,7 +147,7 @@ __global__ void k_face(int32_t n, const int32_t* __restrict__ ftet, const int32_
   double G[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) G[i][j] = dot3(gs[i], gs[j]);
-  double2 kk = kconst;
+  double2 kk = kface ? kface[f] : kconst;
   if (per_tet_k) {
     double2 e;
     if (eps_kind == 0) {
@@ -175,6 +175,45 @@ __global__ void k_face(int32_t n, const int32_t* __restrict__ ftet, const int32_
       o[3 * q + p] = val;
     }
   }
+}
+
+// Metallic edges eliminated symmetrically from the CSR operator: entries in a
+// metallic row or column become 0, the diagonal of a metallic row 1.
+__global__ void k_pec_csr(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          const int32_t* __restrict__ pec, double2* __restrict__ val) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const bool pr = pec[r] != 0;
+  for (int64_t k = rp[r]; k < rp[r + 1]; ++k)
+    if (pr || pec[col[k]] != 0) val[k] = make_double2(col[k] == r ? 1.0 : 0.0, 0.0);
+}
+
+// The same elimination in the dense subdomain matrices: for every metallic
+// local index q of subdomain s, row q and column q are cleared and A[q][q] = 1.
+template <typename C>
+__global__ void k_pec_local(int32_t nsub, const int32_t* __restrict__ Npad, const int64_t* __restrict__ mat_off,
+                            const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx, C* __restrict__ A) {
+  const int s = blockIdx.x;
+  if (s >= nsub) return;
+  const int64_t N = Npad[s];
+  C* M = A + mat_off[s];
+  for (int64_t k = ptr[s]; k < ptr[s + 1]; ++k) {
+    const int64_t q = idx[k];
+    for (int64_t j = threadIdx.x; j < N; j += blockDim.x) {
+      C v;
+      v.x = j == q ? 1 : 0;
+      v.y = 0;
+      M[q * N + j] = v;
+      M[j * N + q] = v;
+    }
+  }
+}
+
+// B[rows[k]][:] = 0
+__global__ void k_zero_rows(int64_t n, const int32_t* __restrict__ rows, int nrhs, double2* __restrict__ B) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  B[(int64_t)rows[i / nrhs] * nrhs + i % nrhs] = make_double2(0.0, 0.0);
 }
 
 // out[k] = sum of pool[src[j]] for j in [ptr[k], ptr[k+1]) (fixed order)
@@ -455,10 +494,27 @@ void launch_element(hipStream_t s, int32_t nt, const int32_t* ts, const double* 
 }
 void launch_face(hipStream_t s, int32_t n, const int32_t* ftet, const int32_t* flf, const int32_t* ts,
                  const double* xyz, const double2* eps, int eps_kind, int per_tet_k, double k0, double2 kconst,
-                 double2* out) {
+                 double2* out, const double2* kface) {
   if (n > 0)
     hipLaunchKernelGGL(k_face, dim3(nblk(n, 128)), dim3(128), 0, s, n, ftet, flf, ts, xyz, eps, eps_kind,
-                       per_tet_k, k0, kconst, out);
+                       per_tet_k, k0, kconst, kface, out);
+}
+void launch_pec_csr(hipStream_t s, int64_t n, const int64_t* rp, const int32_t* col, const int32_t* pec,
+                    double2* val) {
+  if (n > 0) hipLaunchKernelGGL(k_pec_csr, dim3(nblk(n, 256)), dim3(256), 0, s, n, rp, col, pec, val);
+}
+template <typename C>
+void launch_pec_local(hipStream_t s, int32_t nsub, const int32_t* Npad, const int64_t* mat_off, const int64_t* ptr,
+                      const int32_t* idx, C* A) {
+  if (nsub > 0) hipLaunchKernelGGL(k_pec_local<C>, dim3(nsub), dim3(256), 0, s, nsub, Npad, mat_off, ptr, idx, A);
+}
+template void launch_pec_local<float2>(hipStream_t, int32_t, const int32_t*, const int64_t*, const int64_t*,
+                                       const int32_t*, float2*);
+template void launch_pec_local<double2>(hipStream_t, int32_t, const int32_t*, const int64_t*, const int64_t*,
+                                        const int32_t*, double2*);
+void launch_zero_rows(hipStream_t s, int64_t n, const int32_t* rows, int nrhs, double2* B) {
+  if (n > 0 && nrhs > 0)
+    hipLaunchKernelGGL(k_zero_rows, dim3(nblk(n * nrhs, 256)), dim3(256), 0, s, n, rows, nrhs, B);
 }
 void launch_gather_csr(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* src, const double2* pool,
                        double2* out) {

@@ -278,6 +278,19 @@ struct mx_ctx {
   double* h_vec = nullptr;
   int32_t* h_kd = nullptr;
   int h_cap = 0;
+  // waveguide ports and metallic walls
+  std::vector<mx_port> ports;
+  bool pec_walls = false;
+  std::vector<int32_t> face_port;          // [nbf] port of each boundary face, -1: none
+  std::vector<int32_t> pec_list;           // metallic edges
+  std::vector<int64_t> pm_ptr;             // per port: moments int e_p.N_e over the port
+  std::vector<int32_t> pm_edge;
+  std::vector<double> pm_val, pm_norm;     // and int e_p.e_p
+  DBuf<int32_t> pec_flag, pec_rows, pl_idx, pt_edge, pt_col;
+  DBuf<int64_t> pl_ptr, pr_ptr;
+  DBuf<double2> face_k, pt_val, pr_val;
+  DBuf<int32_t> pr_edge;
+  bool pec_local_ready = false;            // pl_ptr / pl_idx match the decomposition
   // Arnoldi steps captured as HIP graphs, one per step index k; valid while
   // the buffers, sizes and tolerance they were captured with are unchanged
   // autotuner: kernel variants picked by timing them on this problem
@@ -1012,13 +1025,184 @@ int coarse_prepare(mx_ctx* c) {
   return MX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// waveguide ports (Sec. III-B, eq. (1))
+// ---------------------------------------------------------------------------
+double2 port_beta(double k0, const mx_port& p) {
+  const double2 z = make_double2(k0 * k0 * p.eps.re - (M_PI / p.a) * (M_PI / p.a), k0 * k0 * p.eps.im);
+  double2 b = csqrt_host(z);  // principal root; the decaying branch has Im <= 0
+  if (b.y > 0) b = make_double2(-b.x, -b.y);
+  return b;
+}
+
+struct PortFrame {
+  double c[3], n[3], u[3], v[3];
+};
+PortFrame port_frame(const mx_port& p) {
+  PortFrame f;
+  double nn = std::sqrt(p.normal[0] * p.normal[0] + p.normal[1] * p.normal[1] + p.normal[2] * p.normal[2]);
+  for (int k = 0; k < 3; ++k) { f.c[k] = p.centre[k]; f.n[k] = p.normal[k] / nn; }
+  const double un = p.u[0] * f.n[0] + p.u[1] * f.n[1] + p.u[2] * f.n[2];
+  for (int k = 0; k < 3; ++k) f.u[k] = p.u[k] - un * f.n[k];
+  const double uu = std::sqrt(f.u[0] * f.u[0] + f.u[1] * f.u[1] + f.u[2] * f.u[2]);
+  for (int k = 0; k < 3; ++k) f.u[k] /= uu;
+  f.v[0] = f.n[1] * f.u[2] - f.n[2] * f.u[1];
+  f.v[1] = f.n[2] * f.u[0] - f.n[0] * f.u[2];
+  f.v[2] = f.n[0] * f.u[1] - f.n[1] * f.u[0];
+  return f;
+}
+
+// Face classification, metallic edges, and the port moments
+// m_p[e] = int_port e_p . N_e dS, |e_p|^2 = int_port e_p . e_p dS, with the
+// tangential edge functions of each face, N_ab = l_a grad l_b - l_b grad l_a,
+// grad l_0 = n x (x2 - x1) / (2|F|) and cyclically, and the 7-point
+// degree-5 triangle rule of Dunavant (1985).
+int build_ports(mx_ctx* c) {
+  const Topology& T = c->topo;
+  static const int LF[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+  static const int FE[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  auto local_edge = [](int a, int b) {  // (a < b) tetrahedron vertex pair -> local edge
+    static const int tab[4][4] = {{-1, 0, 1, 2}, {0, -1, 3, 4}, {1, 3, -1, 5}, {2, 4, 5, -1}};
+    return tab[a][b];
+  };
+  static const double QA = 0.0597158717897698, QB = 0.4701420641051151;
+  static const double QC = 0.7974269853530873, QD = 0.1012865073234563;
+  static const double QL[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {QA, QB, QB}, {QB, QA, QB}, {QB, QB, QA},
+                                  {QC, QD, QD}, {QD, QC, QD}, {QD, QD, QC}};
+  static const double QW[7] = {0.225, 0.1323941527885062, 0.1323941527885062, 0.1323941527885062,
+                               0.1259391805448271, 0.1259391805448271, 0.1259391805448271};
+  const int np = (int)c->ports.size();
+  std::vector<PortFrame> fr(np);
+  for (int p = 0; p < np; ++p) fr[p] = port_frame(c->ports[p]);
+  const int64_t nbf = T.nbf;
+  c->face_port.assign(nbf, -1);
+  std::vector<char> pec(T.ne, 0);
+  std::vector<std::vector<std::pair<int32_t, double>>> mom(np);
+  c->pm_norm.assign(np, 0.0);
+  for (int64_t f = 0; f < nbf; ++f) {
+    const int t = T.bf_tet[f], lf = T.bf_lf[f];
+    int vloc[3];
+    double P[3][3];
+    for (int k = 0; k < 3; ++k) {
+      vloc[k] = LF[lf][k];
+      const int vid = T.ts[4 * (size_t)t + vloc[k]];
+      for (int d = 0; d < 3; ++d) P[k][d] = T.xyz[3 * (size_t)vid + d];
+    }
+    double cen[3];
+    for (int d = 0; d < 3; ++d) cen[d] = (P[0][d] + P[1][d] + P[2][d]) / 3.0;
+    int port = -1;
+    for (int p = 0; p < np && port < 0; ++p) {
+      const mx_port& q = c->ports[p];
+      const double tol = 1e-6 * (q.a + q.b);
+      double dn = 0, du = 0, dv = 0;
+      for (int d = 0; d < 3; ++d) {
+        const double x = cen[d] - fr[p].c[d];
+        dn += x * fr[p].n[d];
+        du += x * fr[p].u[d];
+        dv += x * fr[p].v[d];
+      }
+      if (std::fabs(dn) <= tol && std::fabs(du) <= 0.5 * q.a + tol && std::fabs(dv) <= 0.5 * q.b + tol) port = p;
+    }
+    c->face_port[f] = port;
+    int32_t ge[3];
+    for (int k = 0; k < 3; ++k) ge[k] = T.t2e[6 * (size_t)t + local_edge(vloc[FE[k][0]], vloc[FE[k][1]])];
+    if (port < 0) {
+      if (c->pec_walls)
+        for (int k = 0; k < 3; ++k) pec[ge[k]] = 1;
+      continue;
+    }
+    // face geometry
+    double e01[3], e02[3], nrm[3];
+    for (int d = 0; d < 3; ++d) { e01[d] = P[1][d] - P[0][d]; e02[d] = P[2][d] - P[0][d]; }
+    nrm[0] = e01[1] * e02[2] - e01[2] * e02[1];
+    nrm[1] = e01[2] * e02[0] - e01[0] * e02[2];
+    nrm[2] = e01[0] * e02[1] - e01[1] * e02[0];
+    const double twoA = std::sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
+    for (int d = 0; d < 3; ++d) nrm[d] /= twoA;
+    double gl[3][3];
+    for (int k = 0; k < 3; ++k) {
+      const double* xa = P[(k + 1) % 3];
+      const double* xb = P[(k + 2) % 3];
+      const double w[3] = {xb[0] - xa[0], xb[1] - xa[1], xb[2] - xa[2]};
+      gl[k][0] = (nrm[1] * w[2] - nrm[2] * w[1]) / twoA;
+      gl[k][1] = (nrm[2] * w[0] - nrm[0] * w[2]) / twoA;
+      gl[k][2] = (nrm[0] * w[1] - nrm[1] * w[0]) / twoA;
+    }
+    const mx_port& q = c->ports[port];
+    double acc[3] = {0, 0, 0};
+    for (int iq = 0; iq < 7; ++iq) {
+      double x[3];
+      for (int d = 0; d < 3; ++d) x[d] = QL[iq][0] * P[0][d] + QL[iq][1] * P[1][d] + QL[iq][2] * P[2][d];
+      double su = 0;
+      for (int d = 0; d < 3; ++d) su += (x[d] - fr[port].c[d]) * fr[port].u[d];
+      const double amp = std::sin(M_PI * (su + 0.5 * q.a) / q.a);
+      const double wq = QW[iq] * 0.5 * twoA;
+      c->pm_norm[port] += wq * amp * amp;
+      for (int k = 0; k < 3; ++k) {
+        const int a = FE[k][0], b = FE[k][1];
+        double Nv = 0;  // e . N_k with e = amp v
+        for (int d = 0; d < 3; ++d) Nv += fr[port].v[d] * (QL[iq][a] * gl[b][d] - QL[iq][b] * gl[a][d]);
+        acc[k] += wq * amp * Nv;
+      }
+    }
+    for (int k = 0; k < 3; ++k) mom[port].push_back({ge[k], acc[k]});
+  }
+  c->pec_list.clear();
+  for (int64_t e = 0; e < T.ne; ++e)
+    if (pec[e]) c->pec_list.push_back((int32_t)e);
+  // sum the moments per (port, edge), metallic edges excluded
+  c->pm_ptr.assign(1, 0);
+  c->pm_edge.clear();
+  c->pm_val.clear();
+  for (int p = 0; p < np; ++p) {
+    if (c->pm_norm[p] <= 0) return set_err(MX_EINVAL, "port " + std::to_string(p) + " covers no boundary face");
+    auto& m = mom[p];
+    std::stable_sort(m.begin(), m.end(), [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+      return x.first < y.first;
+    });
+    for (size_t i = 0; i < m.size();) {
+      size_t j = i;
+      double sum = 0;
+      while (j < m.size() && m[j].first == m[i].first) sum += m[j++].second;
+      if (!pec[m[i].first]) {
+        c->pm_edge.push_back(m[i].first);
+        c->pm_val.push_back(sum);
+      }
+      i = j;
+    }
+    c->pm_ptr.push_back((int64_t)c->pm_edge.size());
+  }
+  std::vector<int32_t> flag(T.ne, 0);
+  for (int32_t e : c->pec_list) flag[e] = 1;
+  CK(c->pec_flag.upload(flag, c->stream));
+  CK(c->pec_rows.upload(c->pec_list, c->stream));
+  c->pec_local_ready = false;
+  return MX_OK;
+}
+
+bool pec_active(const mx_ctx* c) { return !c->ports.empty() && !c->pec_list.empty(); }
+
 int fill_pool(mx_ctx* c) {
   const Topology& T = c->topo;
   const size_t need = 36 * (size_t)T.nt + 9 * (size_t)T.nbf + (c->have_dec ? 9 * c->dec.if_tet.size() : 0);
   CK(c->pool.alloc(need));
   launch_element(c->stream, T.nt, c->ts.p, c->xyz.p, c->eps.p, c->eps_kind, c->k0 * c->k0, c->pool.p);
+  const double2* kface = nullptr;
+  if (!c->ports.empty()) {
+    // port faces j beta_p, metallic faces nothing (their edges are
+    // eliminated), other faces the impedance j k_b
+    std::vector<double2> kf(T.nbf);
+    std::vector<double2> beta(c->ports.size());
+    for (size_t p = 0; p < c->ports.size(); ++p) beta[p] = port_beta(c->k0, c->ports[p]);
+    for (int64_t f = 0; f < T.nbf; ++f) {
+      const int p = c->face_port[f];
+      kf[f] = p >= 0 ? beta[p] : (c->pec_walls ? make_double2(0.0, 0.0) : c->kb);
+    }
+    CK(c->face_k.upload(kf, c->stream));
+    kface = c->face_k.p;
+  }
   launch_face(c->stream, (int32_t)T.nbf, c->bf_tet.p, c->bf_lf.p, c->ts.p, c->xyz.p, c->eps.p, c->eps_kind, 0,
-              c->k0, c->kb, c->pool.p + 36 * (size_t)T.nt);
+              c->k0, c->kb, c->pool.p + 36 * (size_t)T.nt, kface);
   if (c->have_dec && !c->dec.if_tet.empty())
     launch_face(c->stream, (int32_t)c->dec.if_tet.size(), c->if_tet.p, c->if_lf.p, c->ts.p, c->xyz.p, c->eps.p,
                 c->eps_kind, 1, c->k0, c->kb, c->pool.p + 36 * (size_t)T.nt + 9 * (size_t)T.nbf);
@@ -1191,6 +1375,9 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
     c->tx = SourceSet();
     c->rx = SourceSet();
     c->ws_nrhs = 0;
+    c->ports.clear();
+    c->pec_list.clear();
+    c->face_port.clear();
     const Topology& t = c->topo;
     CK(c->xyz.upload(t.xyz, c->stream));
     CK(c->ts.upload(t.ts, c->stream));
@@ -1225,6 +1412,7 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
   c->prof.begin(K_ASSEMBLE);
   CK(fill_pool(c));
   launch_gather_csr(c->stream, T.nnz, c->cptr.p, c->csrc.p, c->pool.p, c->val.p);
+  if (pec_active(c)) launch_pec_csr(c->stream, T.ne, c->row_ptr.p, c->col.p, c->pec_flag.p, c->val.p);
   c->prof.end(K_ASSEMBLE);
   MX_HIP_CHECK(hipGetLastError());
   CK(sync(c));
@@ -1278,6 +1466,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     CK(c->status.alloc(nsub));
     CK(c->pswap.alloc((size_t)nsub * (2 * lu_max_swap_rows() + 1)));
     c->have_dec = true;
+    c->pec_local_ready = false;
     c->ws_nrhs = 0;
     c->coarse_geom = false;
     c->ds_graphs = 0;
@@ -1302,6 +1491,29 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     launch_fill_zero<double2>(c->stream, nent, F);
     launch_gather_dense<double2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
     launch_pad_identity<double2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
+  }
+  if (pec_active(c)) {
+    if (!c->pec_local_ready) {
+      // local indices of metallic edges per subdomain
+      std::vector<char> pec(c->topo.ne, 0);
+      for (int32_t e : c->pec_list) pec[e] = 1;
+      std::vector<int64_t> ptr(1, 0);
+      std::vector<int32_t> idx;
+      for (int sd = 0; sd < D.nsub; ++sd) {
+        for (int64_t r = D.dof_ptr[sd]; r < D.dof_ptr[sd + 1]; ++r)
+          if (pec[D.dofs[r]]) idx.push_back((int32_t)(r - D.dof_ptr[sd]));
+        ptr.push_back((int64_t)idx.size());
+      }
+      CK(c->pl_ptr.upload(ptr, c->stream));
+      CK(c->pl_idx.upload(idx.empty() ? std::vector<int32_t>(1, 0) : idx, c->stream));
+      c->pec_local_ready = true;
+    }
+    if (o.precision == MX_PREC_C64)
+      launch_pec_local<float2>(c->stream, D.nsub, c->Npad.p, c->mat_off.p, c->pl_ptr.p, c->pl_idx.p,
+                               (float2*)c->factors.p);
+    else
+      launch_pec_local<double2>(c->stream, D.nsub, c->Npad.p, c->mat_off.p, c->pl_ptr.p, c->pl_idx.p,
+                                (double2*)c->factors.p);
   }
   c->prof.end(K_LOCAL);
   MX_HIP_CHECK(hipGetLastError());
@@ -1381,6 +1593,7 @@ int mx_solve(mx_ctx* c, const mx_sources* tx, const mx_sources* rx, double rtol,
   launch_fill_zero<double2>(c->stream, blk, c->b.p);
   launch_scatter_rhs(c->stream, (int64_t)c->tx.edge.size(), c->s_edge.p, c->s_col.p, c->s_val.p,
                      make_double2(0.0, -c->omega_mu0), ntx, c->b.p);
+  if (pec_active(c)) launch_zero_rows(c->stream, (int64_t)c->pec_list.size(), c->pec_rows.p, ntx, c->b.p);
   MX_HIP_CHECK(hipGetLastError());
   int rc = fgmres(c, ntx, rtol, info);
   if (rc != MX_OK && rc != MX_ENOTCONV) return rc;
@@ -1396,6 +1609,104 @@ int mx_solve(mx_ctx* c, const mx_sources* tx, const mx_sources* rx, double rtol,
   c->last_nrx = nrx;
   c->last_rtol = rtol;
   if (rc == MX_ENOTCONV) g_err = "FGMRES reached maxit";
+  return rc;
+}
+
+int mx_set_ports(mx_ctx* c, int32_t nports, const mx_port* ports, int32_t pec) {
+  if (!c || nports < 0 || (nports > 0 && !ports)) return set_err(MX_EINVAL, "bad arguments");
+  if (nports > 256) return set_err(MX_EINVAL, "at most 256 ports");
+  if (!c->have_mesh) return set_err(MX_ESTATE, "mx_assemble (with a mesh) must come first");
+  for (int p = 0; p < nports; ++p) {
+    const mx_port& q = ports[p];
+    bool ok = q.a > 0 && q.b > 0 && std::isfinite(q.a) && std::isfinite(q.b) && std::isfinite(q.eps.re) &&
+              std::isfinite(q.eps.im);
+    double nn = 0, uu = 0, un = 0;
+    for (int d = 0; d < 3; ++d) {
+      ok = ok && std::isfinite(q.centre[d]) && std::isfinite(q.normal[d]) && std::isfinite(q.u[d]);
+      nn += q.normal[d] * q.normal[d];
+      uu += q.u[d] * q.u[d];
+      un += q.u[d] * q.normal[d];
+    }
+    if (!ok || !(nn > 0) || !(uu - un * un / nn > 1e-12 * uu))
+      return set_err(MX_EINVAL, "port " + std::to_string(p) + ": bad geometry or permittivity");
+  }
+  CK(use_device(c));
+  const std::vector<mx_port> old_ports = c->ports;
+  const bool old_pec = c->pec_walls;
+  c->ports.assign(ports, ports + nports);
+  c->pec_walls = nports > 0 && pec != 0;
+  c->pec_list.clear();
+  c->face_port.clear();
+  if (nports > 0) {
+    const int rc = build_ports(c);
+    if (rc != MX_OK) {  // keep the previous configuration, which the operator still holds
+      c->ports = old_ports;
+      c->pec_walls = old_pec;
+      c->pec_list.clear();
+      c->face_port.clear();
+      if (!c->ports.empty()) build_ports(c);
+      return rc;
+    }
+  }
+  c->local_ready = c->factored = false;
+  c->have_forward = false;
+  if (c->assembled) {
+    CK(fill_pool(c));
+    launch_gather_csr(c->stream, c->topo.nnz, c->cptr.p, c->csrc.p, c->pool.p, c->val.p);
+    if (pec_active(c)) launch_pec_csr(c->stream, c->topo.ne, c->row_ptr.p, c->col.p, c->pec_flag.p, c->val.p);
+    MX_HIP_CHECK(hipGetLastError());
+  }
+  return sync(c);
+}
+
+int mx_solve_ports(mx_ctx* c, double rtol, mx_c128* E, mx_c128* S, mx_solve_info* info) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  if (!(rtol > 0)) return set_err(MX_EINVAL, "rtol must be positive");
+  if (c->ports.empty()) return set_err(MX_ESTATE, "no ports (mx_set_ports)");
+  if (!c->factored) return set_err(MX_ESTATE, "mx_setup_schwarz (with factor=1) must come first");
+  CK(use_device(c));
+  const int np = (int)c->ports.size();
+  // transmitters: b[e][p] = 2 j beta_p m_p[e]; receivers: m_p[e] / |e_p|^2
+  std::vector<int32_t> col;
+  std::vector<double2> bval, rval;
+  for (int p = 0; p < np; ++p) {
+    const double2 bt = port_beta(c->k0, c->ports[p]);
+    const double2 g = make_double2(-2.0 * bt.y, 2.0 * bt.x);  // 2 j beta
+    for (int64_t k = c->pm_ptr[p]; k < c->pm_ptr[p + 1]; ++k) {
+      col.push_back(p);
+      bval.push_back(make_double2(g.x * c->pm_val[k], g.y * c->pm_val[k]));
+      rval.push_back(make_double2(c->pm_val[k] / c->pm_norm[p], 0.0));
+    }
+  }
+  CK(c->pt_edge.upload(c->pm_edge, c->stream));
+  CK(c->pt_col.upload(col, c->stream));
+  CK(c->pt_val.upload(bval, c->stream));
+  CK(c->pr_ptr.upload(c->pm_ptr, c->stream));
+  CK(c->pr_edge.upload(c->pm_edge, c->stream));
+  CK(c->pr_val.upload(rval, c->stream));
+  CK(ensure_workspace(c, np, c->restart));
+  const int64_t blk = c->topo.ne * (int64_t)np;
+  launch_fill_zero<double2>(c->stream, blk, c->b.p);
+  launch_scatter_rhs(c->stream, (int64_t)c->pm_edge.size(), c->pt_edge.p, c->pt_col.p, c->pt_val.p,
+                     make_double2(1.0, 0.0), np, c->b.p);
+  MX_HIP_CHECK(hipGetLastError());
+  int rc = fgmres(c, np, rtol, info);
+  if (rc != MX_OK && rc != MX_ENOTCONV) return rc;
+  CK(c->S.alloc((size_t)np * np));
+  launch_receivers(c->stream, np, np, c->pr_ptr.p, c->pr_edge.p, c->pr_val.p, c->x.p, c->S.p);
+  MX_HIP_CHECK(hipGetLastError());
+  std::vector<double2> hS((size_t)np * np);
+  MX_HIP_CHECK(hipMemcpyAsync(hS.data(), c->S.p, hS.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  CK(sync(c));
+  for (int p = 0; p < np; ++p) hS[(size_t)p * np + p].x -= 1.0;
+  if (S && is_device_ptr(S))
+    MX_HIP_CHECK(hipMemcpyAsync(S, hS.data(), hS.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+  else if (S)
+    std::memcpy(S, hS.data(), hS.size() * sizeof(double2));
+  if (E) CK(copy_out(c, E, c->x.p, blk * sizeof(double2)));
+  CK(sync(c));
+  c->have_forward = false;  // the adjoint gradient is defined for point sources
+  c->tx = SourceSet();
   return rc;
 }
 

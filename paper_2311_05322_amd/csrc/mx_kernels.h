@@ -28,7 +28,15 @@ void launch_element(hipStream_t s, int32_t nt, const int32_t* ts, const double* 
                     int eps_kind, double k0sq, double2* out);
 void launch_face(hipStream_t s, int32_t n, const int32_t* ftet, const int32_t* flf, const int32_t* ts,
                  const double* xyz, const double2* eps, int eps_kind, int per_tet_k, double k0, double2 kconst,
-                 double2* out);
+                 double2* out, const double2* kface = nullptr);
+// metallic (PEC) edge elimination in the CSR operator and the dense subdomain
+// matrices, and zeroing of metallic rows of a block right-hand side
+void launch_pec_csr(hipStream_t s, int64_t n, const int64_t* rp, const int32_t* col, const int32_t* pec,
+                    double2* val);
+template <typename C>
+void launch_pec_local(hipStream_t s, int32_t nsub, const int32_t* Npad, const int64_t* mat_off, const int64_t* ptr,
+                      const int32_t* idx, C* A);
+void launch_zero_rows(hipStream_t s, int64_t n, const int32_t* rows, int nrhs, double2* B);
 void launch_gather_csr(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* src, const double2* pool,
                        double2* out);
 template <typename C>
