@@ -109,15 +109,12 @@ def assemble(topo: fem.Topology, eps, eps_kind: int, freq_hz: float, eps_b: comp
     r2 = np.repeat(topo.bface_edges, 3, axis=1).ravel()
     c2 = np.tile(topo.bface_edges, (1, 3)).ravel()
     data = fem._deterministic_csr(topo, np.r_[r1, r2], np.r_[c1, c2], np.r_[Ae.reshape(-1), Bf.reshape(-1)])
-    A = sp.csr_matrix((data, topo.col, topo.row_ptr), shape=(topo.ne, topo.ne)).tolil()
+    A = sp.csr_matrix((data, topo.col, topo.row_ptr), shape=(topo.ne, topo.ne))
     pe = pec_edges(topo, fp, pec)
     if len(pe):
-        A = A.tocsr()
         keep = np.ones(topo.ne)
         keep[pe] = 0.0
-        Dk = sp.diags(keep)
-        A = (Dk @ A @ Dk).tolil()
-        A[pe, pe] = 1.0
+        A = sp.diags(keep) @ A @ sp.diags(keep) + sp.diags(1.0 - keep)
     return A.tocsr(), fp, pe
 
 

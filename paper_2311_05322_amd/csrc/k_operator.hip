@@ -116,7 +116,9 @@ __global__ void k_element(int32_t nt, const int32_t* __restrict__ ts, const doub
 }
 
 // Face block j k B_F for (tet, local face) entries; k = kconst when
-// per_tet_k == 0, else k0 sqrt(eps of the tetrahedron).
+// per_tet_k == 0, else k0 sqrt(eps of the tetrahedron). A non-null kface
+// gives k per face instead (port faces beta_p, metallic faces 0), taking
+// precedence over kconst.
 __global__ void k_face(int32_t n, const int32_t* __restrict__ ftet, const int32_t* __restrict__ flf,
                        const int32_t* __restrict__ ts, const double* __restrict__ xyz,
                        const double2* __restrict__ eps, int eps_kind, int per_tet_k, double k0,

@@ -287,6 +287,63 @@ def chamber_problem(c: float = 0.004, mesh_seed: int = 0, tear_seed: int | None 
                     "tear_centre": ph.tear_centre, "tear_semi": ph.tear_semi})
 
 
+@dataclasses.dataclass
+class PortSpec:
+    """Rectangular waveguide aperture on the mesh boundary: centre, outward
+    unit normal, broad-side unit vector u (width a), height b along
+    normal x u, relative permittivity eps of the guide's filling."""
+    centre: tuple
+    normal: tuple
+    u: tuple
+    a: float
+    b: float
+    eps: complex
+
+
+def box_chamber(side: float, height: float, h: float, ports_per_wall: int = 4, rings=(0.4, 0.6),
+                port_cells=(5, 2), eps_port: complex = 59.0):
+    """Box chamber [-side/2, side/2]^2 x [0, height] for the waveguide-port
+    model: a Kuhn lattice of cube size about h (Morton-numbered like
+    jittered_cylinder, not jittered, so that the walls stay planar), and
+    4 * ports_per_wall * len(rings) apertures of port_cells lattice cells
+    (broad side horizontal, height along z) on the four side walls, spread
+    evenly along each wall at the heights rings * height, snapped to lattice
+    lines (ValueError if two apertures would overlap). The paper's antennas are ceramic-filled (eps_r = 59) open-ended
+    guides on rings around the imaging domain (Sec. II)."""
+    nxy = int(math.ceil(side / h))
+    nz = int(math.ceil(height / h))
+    xyz, tet = kuhn_box((nxy, nxy, nz), (-side / 2, -side / 2, 0.0), (side / 2, side / 2, height))
+    hx, hz = side / nxy, height / nz
+    cube = np.arange(tet.shape[0]) // 6
+    ci, cj, ck = cube % nxy, (cube // nxy) % nxy, cube // (nxy * nxy)
+    tet = tet[np.argsort(morton3(ci, cj, ck), kind="stable")]
+    nv = xyz.shape[0]
+    vid = np.arange(nv)
+    vi, vj, vk = vid % (nxy + 1), (vid // (nxy + 1)) % (nxy + 1), vid // ((nxy + 1) * (nxy + 1))
+    order = np.argsort(morton3(vi, vj, vk), kind="stable")
+    newid = np.empty(nv, dtype=np.int64)
+    newid[order] = np.arange(nv)
+    xyz = np.ascontiguousarray(xyz[order])
+    tet = newid[tet].astype(np.int32)
+    pa, pb = port_cells
+    a, b = pa * hx, pb * hz
+    ks = [int(round(zr * nz - pb / 2)) for zr in rings]
+    iss = [int(round((q + 0.5) * nxy / ports_per_wall - pa / 2)) for q in range(ports_per_wall)]
+    for lo_hi, n_, w_ in ((sorted(ks), nz, pb), (iss, nxy, pa)):
+        if lo_hi[0] < 0 or lo_hi[-1] + w_ > n_ or any(y - x < w_ for x, y in zip(lo_hi, lo_hi[1:])):
+            raise ValueError("apertures overlap or leave the wall at this lattice size")
+    ports = []
+    for k0 in ks:
+        zc = (k0 + pb / 2) * hz
+        for w, (nrm, u) in enumerate((((1, 0, 0), (0, 1, 0)), ((0, 1, 0), (-1, 0, 0)),
+                                      ((-1, 0, 0), (0, -1, 0)), ((0, -1, 0), (1, 0, 0)))):
+            for i0 in iss:
+                s = -side / 2 + (i0 + pa / 2) * hx      # position along u
+                c = [nrm[0] * side / 2 + u[0] * s, nrm[1] * side / 2 + u[1] * s, zc]
+                ports.append(PortSpec(tuple(c), nrm, u, a, b, complex(eps_port)))
+    return xyz, tet, ports
+
+
 def seeded_complex(shape, seed: int, scale: float = 1.0):
     """Seeded standard complex normal array (test vectors)."""
     rng = np.random.default_rng(seed)
