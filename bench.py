@@ -94,10 +94,12 @@ def measured_traffic(kernel, workload_name):
     return float(vals["bytes_per_launch"])
 
 
-def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=True, coarse=False):
+def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=True, coarse=False, block=False,
+                two_pass=False):
     import torch
     import paper_2311_05322_amd as mx
     S = np.zeros((len(p.src_pos), len(p.src_pos)), np.complex128)
+    ctx.set_krylov(block, two_pass)
 
     def step():
         ctx.assemble(None, None, eps_dev, p.eps_kind, p.freq, p.eps_b, reuse_mesh=True)
@@ -128,6 +130,7 @@ def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=Tr
         kt = ctx.kernel_times()
         ctx.set_profiling(False)
         log(f"  profiled step: iters {info['iters_max']}")
+    ctx.set_krylov(False)
     return (t1 - t0) / steps, infos, kt, S
 
 
@@ -193,6 +196,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference variant")
     ap.add_argument("--no-learned", action="store_true", help="headline without the learned coarse term")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-block", action="store_true", help="skip the block FGMRES variant")
+    ap.add_argument("--block-cgs2", action="store_true", help="also time block FGMRES with two Gram-Schmidt passes")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy kernel (read MIB MiB, write MIB MiB) three times, as the "
@@ -242,13 +247,18 @@ def main():
         ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, factor=False, coarse=True)
         load_weights(ctx, wfile)
     variants = {}
-    order = ([("c64_learned", mx.MX_PREC_C64, True)] if learned else []) + [("c64_plain", mx.MX_PREC_C64, False)]
+    order = ([("c64_learned", mx.MX_PREC_C64, True, False, False)] if learned else []) + \
+        [("c64_plain", mx.MX_PREC_C64, False, False, False)]
+    if not args.no_block:
+        order.append(("c64_block", mx.MX_PREC_C64, False, True, False))
+        if args.block_cgs2:
+            order.append(("c64_block_cgs2", mx.MX_PREC_C64, False, True, True))
     if not args.no_fp64:
-        order.append(("c128_plain", mx.MX_PREC_C128, False))
-    for name, prec, co in order:
+        order.append(("c128_plain", mx.MX_PREC_C128, False, False, False))
+    for name, prec, co, blk, two in order:
         log(f"variant {name}")
         ms, infos, kt, S = run_variant(ctx, p, eps_dev, E_dev, prec, args.steps, args.warmup, args.restart,
-                                       coarse=co)
+                                       coarse=co, block=blk, two_pass=two)
         variants[name] = {"ms": ms, "infos": infos, "kt": kt, "S": S, "tuning": ctx.tuning()}
         log(f"  autotuner: {variants[name]['tuning']}")
     ctx.close()
@@ -262,7 +272,8 @@ def main():
                "kernel_ms_per_step": {k: x[0] for k, x in v["kt"].items() if x[1]},
                "S_rel_diff_vs_headline": float(np.abs(S_mix - v["S"]).max() / np.abs(v["S"]).max())}
     others = {k: {"solves_per_s": 1.0 / v["ms"], "iters": int(v["infos"][-1]["iters_max"]),
-                  "fallback": int(v["infos"][-1]["fallback"]), "autotune": v["tuning"]}
+                  "fallback": int(v["infos"][-1]["fallback"]), "autotune": v["tuning"],
+                  "kernel_ms_per_step": {kk: x[0] for kk, x in v["kt"].items() if x[1]}}
               for k, v in variants.items()}
 
     # dominant kernel of the headline variant and its roofline

@@ -112,8 +112,10 @@ typedef struct {
   int32_t iters_max;   /* max over right-hand sides */
   int32_t cycles;      /* restart cycles */
   double t_iter;       /* seconds spent in the Krylov iteration */
-  int32_t fallback;    /* 1/2: the learned coarse term was switched off during the
-                          solve (non-finite output / a cycle with < 10% reduction) */
+  int32_t fallback;    /* 1/2/3: the learned coarse term was switched off during the
+                          solve (non-finite output / a cycle with < 10% reduction /
+                          the first steps removed < 5% of the one-level residual);
+                          4: block FGMRES fell back to the pseudo-block solver */
 } mx_solve_info;
 
 /* Sizes of the current discretisation and decomposition. */
@@ -174,6 +176,29 @@ typedef struct {
 } mx_tuning;
 int mx_set_autotune(mx_ctx* ctx, int enable);
 int mx_get_tuning(mx_ctx* ctx, mx_tuning* out);
+
+/* Krylov solver of every solve (mx_solve, mx_solve_rhs, mx_solve_ports and
+ * the adjoint solve of mx_gradient), Sec. III-C:
+ *   MX_KRYLOV_PSEUDO_BLOCK (default): one FGMRES per right-hand side, run as
+ *     one block of kernels;
+ *   MX_KRYLOV_BLOCK: block FGMRES, one block Krylov space shared by all
+ *     right-hand sides: block Arnoldi with one pass of classical block
+ *     Gram-Schmidt (a second pass only when the pass removed all but 1e-8
+ *     of a column's squared norm), the new block orthonormalised by Cholesky
+ *     QR applied twice; block Hessenberg least squares by Givens rotations
+ *     on the host;
+ *   MX_KRYLOV_BLOCK_CGS2: the same with block Gram-Schmidt applied twice and
+ *     Cholesky QR applied twice (more robust, more sweeps over the basis).
+ *   Both block modes: one-level preconditioner
+ *     (the learned term is not used), restart after `restart` block steps,
+ *     every right-hand side to the same rtol of its own ||b_j||. Used for
+ *     1..32 right-hand sides; with more, with a zero right-hand side or a
+ *     residual block of numerical rank below its width, the solve runs the
+ *     pseudo-block solver instead and reports fallback = 4. Iteration
+ *     counts are block steps (the same for every right-hand side).
+ * Errors: MX_EINVAL (unknown mode). */
+enum { MX_KRYLOV_PSEUDO_BLOCK = 0, MX_KRYLOV_BLOCK = 1, MX_KRYLOV_BLOCK_CGS2 = 2 };
+int mx_set_krylov(mx_ctx* ctx, int32_t mode);
 
 /* Port form of the boundary conditions of eq. (1) (Sec. III-B). A boundary
  * face belongs to port p when its centroid lies in that port's plane and

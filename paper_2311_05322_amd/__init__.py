@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmx.so")
 MX_OK, MX_EINVAL, MX_ENOMEM, MX_ESTATE, MX_ENOTCONV, MX_EPIVOT, MX_EHIP = 0, -1, -2, -3, -4, -5, -6
 MX_EPS_P0, MX_EPS_P1 = 0, 1
 MX_PREC_C128, MX_PREC_C64 = 0, 1
+MX_KRYLOV_PSEUDO_BLOCK, MX_KRYLOV_BLOCK, MX_KRYLOV_BLOCK_CGS2 = 0, 1, 2
 
 EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_solve", "mx_solve_rhs",
            "mx_apply_operator", "mx_apply_preconditioner", "mx_get_sizes", "mx_get_topology",
@@ -25,7 +26,7 @@ EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_sol
            "mx_set_stream", "mx_set_autotune", "mx_get_tuning", "mx_set_graphs", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_coarse_num_params", "mx_coarse_init",
            "mx_coarse_set_weights", "mx_coarse_get_weights", "mx_coarse_features", "mx_coarse_forward",
            "mx_coarse_loss_grad", "mx_coarse_collect", "mx_coarse_clear", "mx_coarse_train", "mx_set_ports",
-           "mx_solve_ports", "mx_last_error"]
+           "mx_solve_ports", "mx_set_krylov", "mx_last_error"]
 
 KERNEL_CLASSES = ["lu_panel", "lu_rowpanel", "lu_update", "lu_inv", "trsm_lower", "trsm_upper", "spmm",
                   "restrict", "prolong", "cgs", "assemble", "local", "coarse"]
@@ -125,6 +126,7 @@ def lib():
             "mx_coarse_train": [vp, i32, i32, dbl, ct.c_uint64, vp],
             "mx_set_ports": [vp, i32, ct.POINTER(Port), i32],
             "mx_solve_ports": [vp, dbl, vp, vp, ct.POINTER(SolveInfo)],
+            "mx_set_krylov": [vp, i32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -212,6 +214,13 @@ class Context:
         _check(lib().mx_get_tuning(self._h, ct.byref(t)))
         return {"spmm_variant": t.spmm_variant, "trsm_paired": t.trsm_paired,
                 "spmm_ms": list(t.spmm_ms), "trsm_ms_largest_first_paired": list(t.trsm_ms)}
+
+    def set_krylov(self, block=True, two_pass=False):
+        """Block FGMRES (one Krylov space for all right-hand sides; two_pass:
+        block Gram-Schmidt and Cholesky QR applied twice) or the default
+        pseudo-block FGMRES (one per right-hand side)."""
+        mode = (MX_KRYLOV_BLOCK_CGS2 if two_pass else MX_KRYLOV_BLOCK) if block else MX_KRYLOV_PSEUDO_BLOCK
+        _check(lib().mx_set_krylov(self._h, mode))
 
     def set_graphs(self, enable=True):
         """Replay captured HIP graphs for plain Arnoldi steps (default on)."""

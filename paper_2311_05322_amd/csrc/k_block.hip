@@ -1,0 +1,229 @@
+// Tall-skinny complex128 products of block FGMRES (block Gram-Schmidt, QR of
+// a block through its Gram matrix, solution update). Blocks are row-major
+// [rows][ld] device arrays: row r of a block of s columns holds its s
+// complex values contiguously, as the right-hand-side blocks of the solver.
+//
+//   k_bdot   P[chunk] = A[chunk rows, 0:ka]^H B[chunk rows, 0:s]   (partials)
+//   k_bsum   out = sum over chunks of P (fixed order: deterministic)
+//   k_bupd   Wout = beta Win + alpha A[:, 0:ka] H                   (H ka x s)
+//   k_bcopy  dst[:, 0:s] = src[:, 0:s] between blocks of different ld
+//
+// FP64 FMA on the vector units (MI355X: 78.6 TFLOP/s, the same as its FP64
+// matrix cores): register tiles of 4 x 4 complex outputs per thread,
+// operands broadcast from LDS.
+#include "mx_device.h"
+#include "mx_kernels.h"
+
+namespace mx {
+
+namespace {
+constexpr int BT = 256;   // threads per workgroup
+constexpr int BA = 128;   // columns of A per k_bdot workgroup (32 when ka <= 32)
+constexpr int BR = 32;    // rows per LDS stage of k_bdot
+constexpr int UR = 128;   // rows per k_bupd workgroup
+constexpr int UA = 128;   // rows of H per LDS stage of k_bupd
+}  // namespace
+
+template <int TA>
+__global__ void __launch_bounds__(BT) k_bdot(int64_t nrows, int64_t rows_per_chunk, int ka, int s,
+                                             const double2* __restrict__ A, int64_t lda,
+                                             const double2* __restrict__ B, int64_t ldb,
+                                             double2* __restrict__ P) {
+  constexpr int MA = TA / 32;  // a-columns per thread
+  __shared__ double2 As[BR][TA];
+  __shared__ double2 Bs[BR][32];
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r1 = min(nrows, r0 + rows_per_chunk);
+  const int a0 = blockIdx.y * TA;
+  const int tid = threadIdx.x;
+  const int bg = tid & 7, ag = tid >> 3;
+  double cre[MA][4], cim[MA][4];
+#pragma unroll
+  for (int i = 0; i < MA; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cre[i][j] = cim[i][j] = 0.0;
+  for (int64_t rs = r0; rs < r1; rs += BR) {
+    for (int e = tid; e < BR * TA; e += BT) {
+      const int rr = e / TA, aa = e % TA;
+      const int64_t r = rs + rr;
+      const int a = a0 + aa;
+      As[rr][aa] = (r < r1 && a < ka) ? A[r * lda + a] : make_double2(0.0, 0.0);
+    }
+    for (int e = tid; e < BR * 32; e += BT) {
+      const int rr = e / 32, bb = e % 32;
+      const int64_t r = rs + rr;
+      Bs[rr][bb] = (r < r1 && bb < s) ? B[r * ldb + bb] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < BR; ++rr) {
+      double2 av[MA], bv[4];
+#pragma unroll
+      for (int q = 0; q < MA; ++q) av[q] = As[rr][ag * MA + q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = Bs[rr][bg * 4 + q];
+#pragma unroll
+      for (int i = 0; i < MA; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          // conj(a) b
+          cre[i][j] = fma(av[i].x, bv[j].x, fma(av[i].y, bv[j].y, cre[i][j]));
+          cim[i][j] = fma(av[i].x, bv[j].y, fma(-av[i].y, bv[j].x, cim[i][j]));
+        }
+    }
+    __syncthreads();
+  }
+  double2* out = P + (int64_t)blockIdx.x * ka * s;
+#pragma unroll
+  for (int i = 0; i < MA; ++i) {
+    const int a = a0 + ag * MA + i;
+    if (a >= ka) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int b = bg * 4 + j;
+      if (b < s) out[(int64_t)a * s + b] = make_double2(cre[i][j], cim[i][j]);
+    }
+  }
+}
+
+// out[i] = sum over chunks c of P[c][i], i < n; a workgroup takes 32
+// consecutive outputs, its 8 thread groups every 8th chunk, and the 8
+// partial sums are added in group order (the same order on every run)
+__global__ void __launch_bounds__(BT) k_bsum(int nchunks, int64_t n, const double2* __restrict__ P,
+                                             double2* __restrict__ out) {
+  __shared__ double2 part[8][32];
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int64_t i = (int64_t)blockIdx.x * 32 + lane;
+  double re = 0, im = 0;
+  if (i < n)
+    for (int c = grp; c < nchunks; c += 8) {
+      const double2 v = P[(int64_t)c * n + i];
+      re += v.x;
+      im += v.y;
+    }
+  part[grp][lane] = make_double2(re, im);
+  __syncthreads();
+  if (grp == 0 && i < n) {
+    double sr = 0, si = 0;
+    for (int g = 0; g < 8; ++g) {
+      sr += part[g][lane].x;
+      si += part[g][lane].y;
+    }
+    out[i] = make_double2(sr, si);
+  }
+}
+
+// Wout[r][b] = beta Win[r][b] + alpha sum_a A[r][a] H[a][b] for b < s <= 32;
+// Win may be Wout (each output element is read and written by one thread).
+__global__ void __launch_bounds__(BT) k_bupd(int64_t nrows, int ka, int s, const double2* __restrict__ A,
+                                             int64_t lda, const double2* __restrict__ H,
+                                             const double2* Win, int64_t ldwin, double2* Wout, int64_t ldwout,
+                                             double alpha, double beta) {
+  __shared__ double2 Hs[UA][32];
+  const int tid = threadIdx.x;
+  const int bg = tid & 7, rg = tid >> 3;
+  const int64_t rbase = (int64_t)blockIdx.x * UR + rg * 4;
+  double cre[4][4], cim[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cre[i][j] = cim[i][j] = 0.0;
+  for (int a0 = 0; a0 < ka; a0 += UA) {
+    const int na = min(UA, ka - a0);
+    __syncthreads();
+    for (int e = tid; e < UA * 32; e += BT) {
+      const int aa = e / 32, bb = e % 32;
+      Hs[aa][bb] = (aa < na && bb < s) ? H[(int64_t)(a0 + aa) * s + bb] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int aa = 0; aa < na; aa += 4) {
+      double2 av[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = rbase + i;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          av[i][q] = (r < nrows && aa + q < na) ? A[r * lda + a0 + aa + q] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double2 hv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hv[j] = Hs[aa + q][bg * 4 + j];  // aa + q <= 127
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            cre[i][j] = fma(av[i][q].x, hv[j].x, fma(-av[i][q].y, hv[j].y, cre[i][j]));
+            cim[i][j] = fma(av[i][q].x, hv[j].y, fma(av[i][q].y, hv[j].x, cim[i][j]));
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = rbase + i;
+    if (r >= nrows) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int b = bg * 4 + j;
+      if (b >= s) continue;
+      double re = alpha * cre[i][j], im = alpha * cim[i][j];
+      if (beta != 0.0) {
+        const double2 w = Win[r * ldwin + b];
+        re = fma(beta, w.x, re);
+        im = fma(beta, w.y, im);
+      }
+      Wout[r * ldwout + b] = make_double2(re, im);
+    }
+  }
+}
+
+__global__ void k_bcopy(int64_t nrows, int s, const double2* __restrict__ src, int64_t lds, double2* __restrict__ dst,
+                        int64_t ldd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows * s) return;
+  const int64_t r = i / s;
+  const int b = (int)(i % s);
+  dst[r * ldd + b] = src[r * lds + b];
+}
+
+int block_chunks(int64_t nrows, int ka, int64_t* rows_per_chunk) {
+  const int ntile = ka <= 32 ? 1 : (ka + BA - 1) / BA;
+  int64_t want = ka <= 32 ? 512 : std::max<int64_t>(64, std::min<int64_t>(1024, 2048 / ntile));
+  int64_t rpc = (nrows + want - 1) / want;
+  rpc = std::max<int64_t>(BR, (rpc + BR - 1) / BR * BR);
+  *rows_per_chunk = rpc;
+  return (int)((nrows + rpc - 1) / rpc);
+}
+
+// entries of the partial-product buffer launch_bdot needs for ka <= ka_max
+int64_t block_partial_max(int ka_max, int s) { return std::max<int64_t>((int64_t)2048 * BA, (int64_t)64 * ka_max) * s; }
+
+void launch_bdot(hipStream_t st, int64_t nrows, int ka, int s, const double2* A, int64_t lda, const double2* B,
+                 int64_t ldb, double2* P, double2* out) {
+  if (nrows <= 0 || ka <= 0 || s <= 0) return;
+  int64_t rpc;
+  const int nch = block_chunks(nrows, ka, &rpc);
+  if (ka <= 32)
+    hipLaunchKernelGGL(k_bdot<32>, dim3(nch, 1), dim3(BT), 0, st, nrows, rpc, ka, s, A, lda, B, ldb, P);
+  else
+    hipLaunchKernelGGL(k_bdot<BA>, dim3(nch, (ka + BA - 1) / BA), dim3(BT), 0, st, nrows, rpc, ka, s, A, lda, B,
+                       ldb, P);
+  const int64_t n = (int64_t)ka * s;
+  hipLaunchKernelGGL(k_bsum, dim3((unsigned)((n + 31) / 32)), dim3(BT), 0, st, nch, n, P, out);
+}
+
+void launch_bupd(hipStream_t st, int64_t nrows, int ka, int s, const double2* A, int64_t lda, const double2* H,
+                 const double2* Win, int64_t ldwin, double2* Wout, int64_t ldwout, double alpha, double beta) {
+  if (nrows <= 0 || s <= 0) return;
+  hipLaunchKernelGGL(k_bupd, dim3((unsigned)((nrows + UR - 1) / UR)), dim3(BT), 0, st, nrows, ka, s, A, lda, H, Win,
+                     ldwin, Wout, ldwout, alpha, beta);
+}
+
+void launch_bcopy(hipStream_t st, int64_t nrows, int s, const double2* src, int64_t lds, double2* dst, int64_t ldd) {
+  const int64_t n = nrows * s;
+  if (n > 0) hipLaunchKernelGGL(k_bcopy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nrows, s, src, lds, dst, ldd);
+}
+
+}  // namespace mx

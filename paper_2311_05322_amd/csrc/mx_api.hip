@@ -2,6 +2,7 @@
 // operator assembly, ORAS set-up, and the pseudo-block flexible GMRES driver.
 #include <algorithm>
 #include <chrono>
+#include <complex>
 #include <functional>
 #include <random>
 #include <cmath>
@@ -291,6 +292,12 @@ struct mx_ctx {
   DBuf<double2> face_k, pt_val, pr_val;
   DBuf<int32_t> pr_edge;
   bool pec_local_ready = false;            // pl_ptr / pl_idx match the decomposition
+  // block FGMRES (mx_set_krylov): device blocks and pinned host staging
+  int krylov_mode = MX_KRYLOV_PSEUDO_BLOCK;
+  int64_t block_reorth = 0;                // one-pass block steps that took a second pass
+  DBuf<double2> bw1, bw2, bpart, bH, bG, bT;
+  double2* hb = nullptr;
+  size_t hb_cap = 0;
   // Arnoldi steps captured as HIP graphs, one per step index k; valid while
   // the buffers, sizes and tolerance they were captured with are unchanged
   // autotuner: kernel variants picked by timing them on this problem
@@ -694,7 +701,381 @@ uint64_t step_signature(const mx_ctx* c, int nrhs, int m, double rtol) {
   return h;
 }
 
+// ---------------------------------------------------------------------------
+// Block FGMRES: one block Krylov space shared by all right-hand sides
+// (block Arnoldi, Saad, Iterative Methods for Sparse Linear Systems, Sec. 6.12)
+// ---------------------------------------------------------------------------
+typedef std::complex<double> cd;
+constexpr int kBlockFallback = 1000;  // internal: run the pseudo-block solver instead
+
+// G = R^H R for the Hermitian Gram matrix G (s x s, row-major) of a block,
+// through the Cholesky factor of D^-1 G D^-1 (D = diag(G)^(1/2)), so that the
+// column scales of the block do not enter the rank test: false when a scaled
+// pivot is not above tol (the block has numerical rank below s).
+bool gram_cholesky(const double2* G, int s, std::vector<cd>& R, double tol) {
+  std::vector<double> d(s);
+  for (int i = 0; i < s; ++i) {
+    const double g = G[(size_t)i * s + i].x;
+    if (!(g > 0) || !std::isfinite(g)) return false;
+    d[i] = std::sqrt(g);
+  }
+  std::vector<cd> L((size_t)s * s, 0.0);
+  for (int j = 0; j < s; ++j) {
+    double piv = G[(size_t)j * s + j].x / (d[j] * d[j]);
+    for (int k = 0; k < j; ++k) piv -= std::norm(L[(size_t)j * s + k]);
+    if (!(piv > tol)) return false;
+    const double ljj = std::sqrt(piv);
+    L[(size_t)j * s + j] = ljj;
+    for (int i = j + 1; i < s; ++i) {
+      const double2 g = G[(size_t)i * s + j];
+      cd v = cd(g.x, g.y) / (d[i] * d[j]);
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * s + k] * std::conj(L[(size_t)j * s + k]);
+      L[(size_t)i * s + j] = v / ljj;
+    }
+  }
+  R.assign((size_t)s * s, 0.0);
+  for (int i = 0; i < s; ++i)
+    for (int j = i; j < s; ++j) R[(size_t)i * s + j] = std::conj(L[(size_t)j * s + i]) * d[j];
+  return true;
+}
+
+// T = R^-1 for upper triangular R (row-major)
+void upper_inverse(const std::vector<cd>& R, int s, double2* T) {
+  std::vector<cd> X((size_t)s * s, 0.0);
+  for (int j = 0; j < s; ++j) {
+    X[(size_t)j * s + j] = 1.0 / R[(size_t)j * s + j];
+    for (int i = j - 1; i >= 0; --i) {
+      cd v = 0;
+      for (int k = i + 1; k <= j; ++k) v += R[(size_t)i * s + k] * X[(size_t)k * s + j];
+      X[(size_t)i * s + j] = -v / R[(size_t)i * s + i];
+    }
+  }
+  for (size_t e = 0; e < X.size(); ++e) T[e] = make_double2(X[e].real(), X[e].imag());
+}
+
+int ensure_block_host(mx_ctx* c, size_t n) {
+  if (n <= c->hb_cap) return MX_OK;
+  if (c->hb) (void)hipHostFree(c->hb);
+  c->hb = nullptr;
+  c->hb_cap = 0;
+  MX_HIP_CHECK(hipHostMalloc((void**)&c->hb, n * sizeof(double2), hipHostMallocDefault));
+  c->hb_cap = n;
+  return MX_OK;
+}
+
+// W (ld s) = Q R by Cholesky QR applied twice: Q written to out (ld s), tmp
+// (ld s) scratch, R (upper, row-major) on the host. ok = false when the
+// block has numerical rank below s (out is then not written).
+// G1 (host, optional): W^H W when the caller already has it.
+int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, std::vector<cd>& R, bool& ok,
+            const double2* G1 = nullptr) {
+  const int64_t ne = c->topo.ne;
+  hipStream_t st = c->stream;
+  const size_t ss = (size_t)s * s;
+  double2* hG = c->hb;
+  double2* hT = c->hb + ss;
+  std::vector<cd> R1, R2;
+  // pass 1 (rank test on the scaled Gram matrix; 1e-14 keeps cond(W D^-1) below ~1e7)
+  if (G1) {
+    if (G1 != hG) std::memcpy(hG, G1, ss * sizeof(double2));
+  } else {
+    launch_bdot(st, ne, s, s, W, s, W, s, c->bpart.p, c->bG.p);
+    MX_HIP_CHECK(hipMemcpyAsync(hG, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
+    CK(sync(c));
+  }
+  ok = gram_cholesky(hG, s, R1, 1e-14);
+  if (!ok) return MX_OK;
+  upper_inverse(R1, s, hT);
+  MX_HIP_CHECK(hipMemcpyAsync(c->bT.p, hT, ss * sizeof(double2), hipMemcpyHostToDevice, st));
+  launch_bupd(st, ne, s, s, W, s, c->bT.p, nullptr, 0, tmp, s, 1.0, 0.0);
+  // pass 2 on the (nearly orthonormal) first factor
+  launch_bdot(st, ne, s, s, tmp, s, tmp, s, c->bpart.p, c->bG.p);
+  MX_HIP_CHECK(hipMemcpyAsync(hG, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
+  CK(sync(c));
+  ok = gram_cholesky(hG, s, R2, 1e-10);
+  if (!ok) return MX_OK;
+  upper_inverse(R2, s, hT);
+  MX_HIP_CHECK(hipMemcpyAsync(c->bT.p, hT, ss * sizeof(double2), hipMemcpyHostToDevice, st));
+  launch_bupd(st, ne, s, s, tmp, s, c->bT.p, nullptr, 0, out, s, 1.0, 0.0);
+  MX_HIP_CHECK(hipGetLastError());
+  R.assign(ss, 0.0);  // R = R2 R1
+  for (int i = 0; i < s; ++i)
+    for (int j = i; j < s; ++j) {
+      cd v = 0;
+      for (int k = i; k <= j; ++k) v += R2[(size_t)i * s + k] * R1[(size_t)k * s + j];
+      R[(size_t)i * s + j] = v;
+    }
+  return MX_OK;
+}
+
+// Least squares of block FGMRES: the block Hessenberg matrix reduced to upper
+// triangular form by complex Givens rotations as its block columns arrive,
+// the same rotations applied to the right-hand side block [S0; 0].
+struct BlockLsq {
+  int s = 0, m = 0;
+  int64_t nrow = 0, ncol = 0;
+  std::vector<cd> Hr;     // rotated block Hessenberg, row-major [(m+1)s][ms]
+  std::vector<cd> G;      // rotated right-hand sides, row-major [(m+1)s][s]
+  std::vector<int32_t> ri, rj;
+  std::vector<double> rc;
+  std::vector<cd> rsn;
+  int kdone = 0;
+  void reset(int s_, int m_, const std::vector<cd>& S0) {
+    s = s_;
+    m = m_;
+    nrow = (int64_t)(m + 1) * s;
+    ncol = (int64_t)m * s;
+    Hr.assign((size_t)(nrow * ncol), 0.0);
+    G.assign((size_t)(nrow * s), 0.0);
+    for (size_t e = 0; e < (size_t)s * s; ++e) G[e] = S0[e];
+    ri.clear(); rj.clear(); rc.clear(); rsn.clear();
+    kdone = 0;
+  }
+  // [a; b] <- [c, sn; -conj(sn), c] [a; b], in real arithmetic (no library
+  // complex multiplication in the O(k s^3) loops)
+  static void rot(cd& a, cd& b, double c, cd sn) {
+    const double ar = a.real(), ai = a.imag(), br = b.real(), bi = b.imag();
+    const double sr = sn.real(), si = sn.imag();
+    a = cd(c * ar + sr * br - si * bi, c * ai + sr * bi + si * br);
+    b = cd(c * br - sr * ar - si * ai, c * bi - sr * ai + si * ar);
+  }
+  // block column k: P row-major [(k+2)s][s], rows (k+1)s.. hold R_{k+1} (upper)
+  void add(int k, std::vector<cd>& P) {
+    const int64_t rows = (int64_t)(k + 2) * s;
+    // rotations of the previous block columns, on all s columns at once
+    const size_t nold = ri.size();
+    for (size_t t = 0; t < nold; ++t) {
+      cd* a = &P[(size_t)ri[t] * s];
+      cd* b = &P[(size_t)rj[t] * s];
+      const double c = rc[t];
+      const cd sn = rsn[t];
+      for (int q = 0; q < s; ++q) rot(a[q], b[q], c, sn);
+    }
+    // triangularise this block column
+    for (int jj = 0; jj < s; ++jj) {
+      const int64_t cc = (int64_t)k * s + jj;
+      for (int64_t r = cc + 1; r <= (int64_t)(k + 1) * s + jj; ++r) {
+        cd& a = P[(size_t)cc * s + jj];
+        cd& b = P[(size_t)r * s + jj];
+        double c;
+        cd sn;
+        if (b == 0.0) {
+          c = 1.0;
+          sn = 0.0;
+        } else if (a == 0.0) {
+          c = 0.0;
+          sn = std::conj(b) / std::abs(b);
+        } else {
+          const double den = std::hypot(std::abs(a), std::abs(b));
+          c = std::abs(a) / den;
+          sn = (a / std::abs(a)) * std::conj(b) / den;
+        }
+        for (int q = jj; q < s; ++q) rot(P[(size_t)cc * s + q], P[(size_t)r * s + q], c, sn);
+        P[(size_t)r * s + jj] = 0.0;
+        for (int q = 0; q < s; ++q) rot(G[(size_t)cc * s + q], G[(size_t)r * s + q], c, sn);
+        ri.push_back((int32_t)cc);
+        rj.push_back((int32_t)r);
+        rc.push_back(c);
+        rsn.push_back(sn);
+      }
+    }
+    for (int64_t i = 0; i < rows; ++i)
+      for (int q = 0; q < s; ++q) Hr[(size_t)(i * ncol + (int64_t)k * s + q)] = P[(size_t)i * s + q];
+    kdone = k + 1;
+  }
+  // residual norm of right-hand side b after the last block column
+  double colres(int b) const {
+    double t = 0;
+    for (int64_t i = (int64_t)kdone * s; i < (int64_t)(kdone + 1) * s; ++i) t += std::norm(G[(size_t)i * s + b]);
+    return std::sqrt(t);
+  }
+  // Y [(kdone s) x s] by back substitution
+  void solve(double2* Y) const {
+    const int64_t n = (int64_t)kdone * s;
+    std::vector<cd> y((size_t)(n * s), 0.0);
+    std::vector<double> vr(s), vi(s);
+    for (int64_t i = n - 1; i >= 0; --i) {
+      const cd d = Hr[(size_t)(i * ncol + i)];
+      for (int q = 0; q < s; ++q) {
+        vr[q] = G[(size_t)i * s + q].real();
+        vi[q] = G[(size_t)i * s + q].imag();
+      }
+      for (int64_t j = i + 1; j < n; ++j) {
+        const double hr = Hr[(size_t)(i * ncol + j)].real(), hi = Hr[(size_t)(i * ncol + j)].imag();
+        const cd* yj = &y[(size_t)j * s];
+        for (int q = 0; q < s; ++q) {
+          vr[q] -= hr * yj[q].real() - hi * yj[q].imag();
+          vi[q] -= hr * yj[q].imag() + hi * yj[q].real();
+        }
+      }
+      for (int q = 0; q < s; ++q) y[(size_t)i * s + q] = d != 0.0 ? cd(vr[q], vi[q]) / d : cd(0.0);
+    }
+    for (size_t e = 0; e < y.size(); ++e) Y[e] = make_double2(y[e].real(), y[e].imag());
+  }
+};
+
+// Block right-preconditioned FGMRES on b (device) -> x (device, ctx->x) with
+// the one-level preconditioner. Layout: the basis blocks V_0..V_m side by side,
+// row r of the basis holding (m+1)s values (ld (m+1)s), and the preconditioned
+// blocks Z_0..Z_{m-1} likewise (ld ms), so that V^H W, W - V H and X + Z Y are
+// single tall-skinny products. Each step: Z_k = M^-1 V_k, W = A Z_k, block
+// classical Gram-Schmidt twice, W = V_{k+1} R_{k+1} by Cholesky QR twice.
+// Returns kBlockFallback (nothing written to x) when a right-hand side is zero
+// or the residual block has numerical rank below s.
+int block_fgmres(mx_ctx* c, int s, double rtol, mx_solve_info* info) {
+  const bool two_pass = c->krylov_mode == MX_KRYLOV_BLOCK_CGS2;
+  const int m = c->ws_m;
+  const int64_t ne = c->topo.ne;
+  const int64_t blk = ne * (int64_t)s;
+  const int64_t LV = (int64_t)(m + 1) * s, LZ = (int64_t)m * s;
+  hipStream_t st = c->stream;
+  auto t0 = std::chrono::steady_clock::now();
+  CK(autotune(c, s));
+  CK(c->bw1.alloc(blk));
+  CK(c->bw2.alloc(blk));
+  CK(c->bpart.alloc(block_partial_max((int)LV, s)));
+  CK(c->bH.alloc(LV * s));
+  CK(c->bG.alloc((size_t)s * s));
+  CK(c->bT.alloc((size_t)s * s));
+  CK(ensure_block_host(c, 2 * (size_t)s * s + 2 * (size_t)LV * s));
+  double2* hh1 = c->hb + 2 * (size_t)s * s;
+  double2* hh2 = hh1 + (size_t)LV * s;
+  launch_norm(st, ne, s, c->b.p, c->normpart.p, c->bnorm.p);
+  MX_HIP_CHECK(hipMemcpyAsync(c->h_vec, c->bnorm.p, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(sync(c));
+  std::vector<double> bn(s), rr(s);
+  for (int j = 0; j < s; ++j) {
+    bn[j] = c->h_vec[j];
+    if (!(bn[j] > 0)) return kBlockFallback;
+  }
+  c->coarse_off_now = true;  // the learned term is not used with the block solver
+  launch_fill_zero<double2>(st, blk, c->x.p);
+  MX_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, blk * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  auto true_residual = [&]() -> int {
+    launch_norm(st, ne, s, c->r.p, c->normpart.p, c->beta.p);
+    MX_HIP_CHECK(hipMemcpyAsync(c->h_vec, c->beta.p, s * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(sync(c));
+    for (int j = 0; j < s; ++j) rr[j] = c->h_vec[j] / bn[j];
+    return MX_OK;
+  };
+  CK(true_residual());
+  BlockLsq ls;
+  int total = 0, cycles = 0, rc = MX_OK;
+  std::vector<cd> Rk, P;
+  for (;;) {
+    double worst = 0;
+    for (int j = 0; j < s; ++j) worst = std::max(worst, rr[j]);
+    if (worst <= rtol) break;
+    if (total >= c->maxit) {
+      rc = set_err(MX_ENOTCONV, "block FGMRES reached maxit=" + std::to_string(c->maxit));
+      break;
+    }
+    // R = V_0 S0
+    bool ok = false;
+    c->prof.begin(K_CGS);
+    CK(cholqr2(c, s, c->r.p, c->bw1.p, c->bw2.p, Rk, ok));
+    c->prof.end(K_CGS);
+    if (!ok) {
+      if (total > 0) return set_err(MX_ENOTCONV, "block FGMRES: the residual block lost rank");
+      return kBlockFallback;
+    }
+    launch_bcopy(st, ne, s, c->bw2.p, s, c->V.p, LV);
+    ls.reset(s, m, Rk);
+    int kk = 0;
+    for (int k = 0; k < m && total < c->maxit; ++k) {
+      // bw2: V_k (contiguous); bw1: Z_k; r: W
+      CK(apply_precond(c, c->bw2.p, c->bw1.p, s));
+      launch_bcopy(st, ne, s, c->bw1.p, s, c->Z.p + (int64_t)k * s, LZ);
+      CK(spmm(c, c->bw1.p, c->r.p, s));
+      c->prof.begin(K_CGS);
+      const int ka = (k + 1) * s;
+      bool reorth = false;
+      launch_bdot(st, ne, ka, s, c->V.p, LV, c->r.p, s, c->bpart.p, c->bH.p);
+      MX_HIP_CHECK(hipMemcpyAsync(hh1, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
+      if (two_pass) {
+        launch_bupd(st, ne, ka, s, c->V.p, LV, c->bH.p, c->r.p, s, c->r.p, s, -1.0, 1.0);
+        launch_bdot(st, ne, ka, s, c->V.p, LV, c->r.p, s, c->bpart.p, c->bH.p);
+        MX_HIP_CHECK(hipMemcpyAsync(hh2, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
+        launch_bupd(st, ne, ka, s, c->V.p, LV, c->bH.p, c->r.p, s, c->r.p, s, -1.0, 1.0);
+        CK(cholqr2(c, s, c->r.p, c->bw1.p, c->bw2.p, Rk, ok));
+      } else {
+        // one projection pass, repeated only when W lay almost entirely in
+        // the basis (its column norms fell by more than 1e4 in the pass, so
+        // that one pass leaves a loss of orthogonality above ~1e-12); then
+        // Cholesky QR twice
+        const size_t ss = (size_t)s * s;
+        double2* hG0 = hh2;
+        double2* hG1 = c->hb;
+        launch_bdot(st, ne, s, s, c->r.p, s, c->r.p, s, c->bpart.p, c->bG.p);
+        MX_HIP_CHECK(hipMemcpyAsync(hG0, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
+        launch_bupd(st, ne, ka, s, c->V.p, LV, c->bH.p, c->r.p, s, c->r.p, s, -1.0, 1.0);
+        launch_bdot(st, ne, s, s, c->r.p, s, c->r.p, s, c->bpart.p, c->bG.p);
+        MX_HIP_CHECK(hipMemcpyAsync(hG1, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
+        CK(sync(c));
+        double rho = 1.0;
+        for (int j = 0; j < s; ++j) rho = std::min(rho, hG1[(size_t)j * s + j].x / hG0[(size_t)j * s + j].x);
+        reorth = !(rho >= 1e-8);
+        if (reorth) {
+          ++c->block_reorth;
+          launch_bdot(st, ne, ka, s, c->V.p, LV, c->r.p, s, c->bpart.p, c->bH.p);
+          MX_HIP_CHECK(hipMemcpyAsync(hh2, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
+          launch_bupd(st, ne, ka, s, c->V.p, LV, c->bH.p, c->r.p, s, c->r.p, s, -1.0, 1.0);
+        }
+        CK(cholqr2(c, s, c->r.p, c->bw1.p, c->bw2.p, Rk, ok, reorth ? nullptr : hG1));
+      }
+      c->prof.end(K_CGS);
+      if (!ok) break;  // W lost rank: this step is not used, restart
+      launch_bcopy(st, ne, s, c->bw2.p, s, c->V.p + (int64_t)(k + 1) * s, LV);
+      P.assign((size_t)(k + 2) * s * s, 0.0);
+      if (two_pass || reorth)
+        for (size_t e = 0; e < (size_t)ka * s; ++e) P[e] = cd(hh1[e].x + hh2[e].x, hh1[e].y + hh2[e].y);
+      else
+        for (size_t e = 0; e < (size_t)ka * s; ++e) P[e] = cd(hh1[e].x, hh1[e].y);
+      for (size_t e = 0; e < (size_t)s * s; ++e) P[(size_t)ka * s + e] = Rk[e];
+      ls.add(k, P);
+      ++total;
+      kk = k + 1;
+      double est = 0;
+      for (int j = 0; j < s; ++j) est = std::max(est, ls.colres(j) / bn[j]);
+      if (est <= rtol) break;
+    }
+    if (kk == 0) return set_err(MX_ENOTCONV, "block FGMRES: the first block of a cycle lost rank");
+    // X += [Z_0 .. Z_kk-1] Y
+    ls.solve(c->hb + 2 * (size_t)s * s);
+    MX_HIP_CHECK(hipMemcpyAsync(c->bH.p, c->hb + 2 * (size_t)s * s, (size_t)kk * s * s * sizeof(double2),
+                                hipMemcpyHostToDevice, st));
+    launch_bupd(st, ne, kk * s, s, c->Z.p, LZ, c->bH.p, c->x.p, s, c->x.p, s, 1.0, 1.0);
+    CK(spmm(c, c->x.p, c->r.p, s));
+    launch_bminus(st, blk, c->b.p, c->r.p);
+    MX_HIP_CHECK(hipGetLastError());
+    CK(true_residual());
+    ++cycles;
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    for (int j = 0; j < s; ++j) {
+      if (info->iters) info->iters[j] = total;
+      if (info->relres) info->relres[j] = rr[j];
+    }
+    info->iters_max = total;
+    info->cycles = cycles;
+    info->fallback = 0;
+    info->t_iter = std::chrono::duration<double>(t1 - t0).count();
+  }
+  return rc;
+}
+
+// The solver of every solve: block FGMRES when selected and applicable, else
+// the pseudo-block FGMRES described with the autotuner above.
 int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::function<int()>* on_cycle = nullptr) {
+  bool block_fallback = false;
+  if (c->krylov_mode != MX_KRYLOV_PSEUDO_BLOCK && !on_cycle) {
+    if (nrhs <= 32) {
+      const int rcb = block_fgmres(c, nrhs, rtol, info);
+      if (rcb != kBlockFallback) return rcb;
+    }
+    block_fallback = true;
+  }
   const int m = c->ws_m;
   const int64_t ne = c->topo.ne;
   const int64_t blk = ne * (int64_t)nrhs;
@@ -930,7 +1311,7 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
     }
     info->iters_max = mx_;
     info->cycles = cycles;
-    info->fallback = fallback;
+    info->fallback = fallback ? fallback : (block_fallback ? 4 : 0);
     info->t_iter = std::chrono::duration<double>(t1 - t0).count();
   }
   return rc;
@@ -1287,6 +1668,7 @@ int mx_destroy(mx_ctx* c) {
   if (c->h_conv) (void)hipHostFree(c->h_conv);
   if (c->h_vec) (void)hipHostFree(c->h_vec);
   if (c->h_kd) (void)hipHostFree(c->h_kd);
+  if (c->hb) (void)hipHostFree(c->hb);
   c->drop_graphs();
   c->prof.reset();
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -1610,6 +1992,14 @@ int mx_solve(mx_ctx* c, const mx_sources* tx, const mx_sources* rx, double rtol,
   c->last_rtol = rtol;
   if (rc == MX_ENOTCONV) g_err = "FGMRES reached maxit";
   return rc;
+}
+
+int mx_set_krylov(mx_ctx* c, int32_t mode) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  if (mode != MX_KRYLOV_PSEUDO_BLOCK && mode != MX_KRYLOV_BLOCK && mode != MX_KRYLOV_BLOCK_CGS2)
+    return set_err(MX_EINVAL, "unknown Krylov mode");
+  c->krylov_mode = mode;
+  return MX_OK;
 }
 
 int mx_set_ports(mx_ctx* c, int32_t nports, const mx_port* ports, int32_t pec) {

@@ -131,4 +131,12 @@ void launch_scatter_rhs(hipStream_t s, int64_t n, const int32_t* edge, const int
 void launch_receivers(hipStream_t s, int nrx, int nrhs, const int64_t* ptr, const int32_t* edge, const double2* val,
                       const double2* U, double2* S);
 
+// block FGMRES products (k_block.hip); s <= 32 columns per block
+int64_t block_partial_max(int ka_max, int s);
+void launch_bdot(hipStream_t st, int64_t nrows, int ka, int s, const double2* A, int64_t lda, const double2* B,
+                 int64_t ldb, double2* P, double2* out);
+void launch_bupd(hipStream_t st, int64_t nrows, int ka, int s, const double2* A, int64_t lda, const double2* H,
+                 const double2* Win, int64_t ldwin, double2* Wout, int64_t ldwout, double alpha, double beta);
+void launch_bcopy(hipStream_t st, int64_t nrows, int s, const double2* src, int64_t lds, double2* dst, int64_t ldd);
+
 }  // namespace mx
