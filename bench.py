@@ -6,7 +6,8 @@ values (topology cached), dense ORAS subdomain matrices + batched LU, and
 block FGMRES of every transmitter to relative residual 1e-8 (true residual
 checked).  The headline variant uses complex64 subdomain factors on the
 matrix cores under an FP64 outer iteration; the plain FP64 one-level Schwarz
-solver is timed in the same run as the reference.
+solver is timed in the same run as the reference, and so is block FGMRES (one
+Krylov space for all transmitters, variant c64_block).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload chamber1m|cube8]
 Prints one JSON line on stdout (progress goes to stderr).

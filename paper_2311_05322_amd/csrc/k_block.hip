@@ -5,12 +5,13 @@
 //
 //   k_bdot   P[chunk] = A[chunk rows, 0:ka]^H B[chunk rows, 0:s]   (partials)
 //   k_bsum   out = sum over chunks of P (fixed order: deterministic)
-//   k_bupd   Wout = beta Win + alpha A[:, 0:ka] H                   (H ka x s)
+//   k_bupd   Wout = beta Win + alpha A[:, 0:ka] H (H ka x s; Win may be Wout:
+//            each output element is read and written by one lane)
 //   k_bcopy  dst[:, 0:s] = src[:, 0:s] between blocks of different ld
 //
-// FP64 FMA on the vector units (MI355X: 78.6 TFLOP/s, the same as its FP64
-// matrix cores): register tiles of 4 x 4 complex outputs per thread,
-// operands broadcast from LDS.
+// Wide products run on the FP64 matrix cores (16x16x4 MFMA, operands straight
+// from memory, no LDS broadcast); the narrow Gram products (ka <= 32) on the
+// vector units with 1 x 4 complex register tiles and LDS-staged operands.
 #include "mx_device.h"
 #include "mx_kernels.h"
 
@@ -20,8 +21,8 @@ namespace {
 constexpr int BT = 256;   // threads per workgroup
 constexpr int BA = 128;   // columns of A per k_bdot workgroup (32 when ka <= 32)
 constexpr int BR = 32;    // rows per LDS stage of k_bdot
-constexpr int UR = 128;   // rows per k_bupd workgroup
-constexpr int UA = 128;   // rows of H per LDS stage of k_bupd
+constexpr int UR = 128;   // rows per k_bupd_mfma workgroup
+constexpr int UA = 128;   // rows of H per LDS stage of k_bupd_mfma
 }  // namespace
 
 template <int TA>
@@ -86,6 +87,126 @@ __global__ void __launch_bounds__(BT) k_bdot(int64_t nrows, int64_t rows_per_chu
   }
 }
 
+// The same partial products on the FP64 matrix cores, for ka > 32: a
+// workgroup takes a 128-wide tile of A's columns (wave w: columns 32w..32w+31
+// as two 16-wide MFMA tiles) and all 32 columns of B (two tiles), and walks
+// the rows of its chunk 4 at a time (the MFMA depth); lane l holds row
+// 4c + (l >> 4) of column l & 15 of each tile, loaded straight from memory.
+__global__ void __launch_bounds__(BT) k_bdot_mfma(int64_t nrows, int64_t rows_per_chunk, int ka, int s,
+                                                  const double2* __restrict__ A, int64_t lda,
+                                                  const double2* __restrict__ B, int64_t ldb,
+                                                  double2* __restrict__ P) {
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r1 = min(nrows, r0 + rows_per_chunk);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int abase = blockIdx.y * BA + 32 * w;
+  if (abase >= ka) return;  // whole wave idle (no barriers in this kernel)
+  const int kq = lane >> 4, cl = lane & 15;
+  Acc_t<double> cre[2][2], cim[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cre[t][u][q] = cim[t][u][q] = 0.0;
+  const bool aok0 = abase + cl < ka, aok1 = abase + 16 + cl < ka;
+  const bool bok0 = cl < s, bok1 = 16 + cl < s;
+  for (int64_t rs = r0; rs < r1; rs += 4) {
+    const int64_t r = rs + kq;
+    const bool rok = r < r1;
+    double2 av[2], bv[2];
+    av[0] = rok && aok0 ? A[r * lda + abase + cl] : make_double2(0.0, 0.0);
+    av[1] = rok && aok1 ? A[r * lda + abase + 16 + cl] : make_double2(0.0, 0.0);
+    bv[0] = rok && bok0 ? B[r * ldb + cl] : make_double2(0.0, 0.0);
+    bv[1] = rok && bok1 ? B[r * ldb + 16 + cl] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        // conj(a) b: re = ar br + ai bi, im = ar bi - ai br
+        cre[t][u] = mfma(av[t].x, bv[u].x, cre[t][u]);
+        cre[t][u] = mfma(av[t].y, bv[u].y, cre[t][u]);
+        cim[t][u] = mfma(av[t].x, bv[u].y, cim[t][u]);
+        cim[t][u] = mfma(-av[t].y, bv[u].x, cim[t][u]);
+      }
+  }
+  double2* out = P + (int64_t)blockIdx.x * ka * s;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = abase + 16 * t + acc_row<double>(lane, q);
+        const int b = 16 * u + cl;
+        if (a < ka && b < s) out[(int64_t)a * s + b] = make_double2(cre[t][u][q], cim[t][u][q]);
+      }
+}
+
+// Wout = beta Win + alpha A H on the FP64 matrix cores: a workgroup takes 128
+// rows (wave w: rows 32w..32w+31 as two 16-row MFMA tiles) and all 32
+// columns; H is staged through LDS 128 rows at a time; lane l holds A's row
+// l & 15 of each tile at column 4c + (l >> 4).
+__global__ void __launch_bounds__(BT) k_bupd_mfma(int64_t nrows, int ka, int s, const double2* __restrict__ A,
+                                                  int64_t lda, const double2* __restrict__ H,
+                                                  const double2* Win, int64_t ldwin, double2* Wout,
+                                                  int64_t ldwout, double alpha, double beta) {
+  __shared__ double2 Hs[UA][32];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int64_t rw = (int64_t)blockIdx.x * UR + 32 * w;
+  Acc_t<double> cre[2][2], cim[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cre[t][u][q] = cim[t][u][q] = 0.0;
+  const bool rok0 = rw + cl < nrows, rok1 = rw + 16 + cl < nrows;
+  const double2* A0 = A + (rw + cl) * lda;
+  const double2* A1 = A + (rw + 16 + cl) * lda;
+  for (int a0 = 0; a0 < ka; a0 += UA) {
+    const int na = min(UA, ka - a0);
+    __syncthreads();
+    for (int e = tid; e < UA * 32; e += BT) {
+      const int aa = e / 32, bb = e % 32;
+      Hs[aa][bb] = (aa < na && bb < s) ? H[(int64_t)(a0 + aa) * s + bb] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int aa = 0; aa < na; aa += 4) {
+      const int a = a0 + aa + kq;
+      const bool aok = aa + kq < na;
+      double2 av[2], hv[2];
+      av[0] = rok0 && aok ? A0[a] : make_double2(0.0, 0.0);
+      av[1] = rok1 && aok ? A1[a] : make_double2(0.0, 0.0);
+      hv[0] = Hs[aa + kq][cl];
+      hv[1] = Hs[aa + kq][16 + cl];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) cmfma<double>(av[t], hv[u], cre[t][u], cim[t][u]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = rw + 16 * t + acc_row<double>(lane, q);
+        const int b = 16 * u + cl;
+        if (r >= nrows || b >= s) continue;
+        double re = alpha * cre[t][u][q], im = alpha * cim[t][u][q];
+        if (beta != 0.0) {
+          const double2 v = Win[r * ldwin + b];
+          re = fma(beta, v.x, re);
+          im = fma(beta, v.y, im);
+        }
+        Wout[r * ldwout + b] = make_double2(re, im);
+      }
+}
+
 // out[i] = sum over chunks c of P[c][i], i < n; a workgroup takes 32
 // consecutive outputs, its 8 thread groups every 8th chunk, and the 8
 // partial sums are added in group order (the same order on every run)
@@ -110,72 +231,6 @@ __global__ void __launch_bounds__(BT) k_bsum(int nchunks, int64_t n, const doubl
       si += part[g][lane].y;
     }
     out[i] = make_double2(sr, si);
-  }
-}
-
-// Wout[r][b] = beta Win[r][b] + alpha sum_a A[r][a] H[a][b] for b < s <= 32;
-// Win may be Wout (each output element is read and written by one thread).
-__global__ void __launch_bounds__(BT) k_bupd(int64_t nrows, int ka, int s, const double2* __restrict__ A,
-                                             int64_t lda, const double2* __restrict__ H,
-                                             const double2* Win, int64_t ldwin, double2* Wout, int64_t ldwout,
-                                             double alpha, double beta) {
-  __shared__ double2 Hs[UA][32];
-  const int tid = threadIdx.x;
-  const int bg = tid & 7, rg = tid >> 3;
-  const int64_t rbase = (int64_t)blockIdx.x * UR + rg * 4;
-  double cre[4][4], cim[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) cre[i][j] = cim[i][j] = 0.0;
-  for (int a0 = 0; a0 < ka; a0 += UA) {
-    const int na = min(UA, ka - a0);
-    __syncthreads();
-    for (int e = tid; e < UA * 32; e += BT) {
-      const int aa = e / 32, bb = e % 32;
-      Hs[aa][bb] = (aa < na && bb < s) ? H[(int64_t)(a0 + aa) * s + bb] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    for (int aa = 0; aa < na; aa += 4) {
-      double2 av[4][4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t r = rbase + i;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          av[i][q] = (r < nrows && aa + q < na) ? A[r * lda + a0 + aa + q] : make_double2(0.0, 0.0);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double2 hv[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) hv[j] = Hs[aa + q][bg * 4 + j];  // aa + q <= 127
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            cre[i][j] = fma(av[i][q].x, hv[j].x, fma(-av[i][q].y, hv[j].y, cre[i][j]));
-            cim[i][j] = fma(av[i][q].x, hv[j].y, fma(av[i][q].y, hv[j].x, cim[i][j]));
-          }
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t r = rbase + i;
-    if (r >= nrows) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int b = bg * 4 + j;
-      if (b >= s) continue;
-      double re = alpha * cre[i][j], im = alpha * cim[i][j];
-      if (beta != 0.0) {
-        const double2 w = Win[r * ldwin + b];
-        re = fma(beta, w.x, re);
-        im = fma(beta, w.y, im);
-      }
-      Wout[r * ldwout + b] = make_double2(re, im);
-    }
   }
 }
 
@@ -208,7 +263,7 @@ void launch_bdot(hipStream_t st, int64_t nrows, int ka, int s, const double2* A,
   if (ka <= 32)
     hipLaunchKernelGGL(k_bdot<32>, dim3(nch, 1), dim3(BT), 0, st, nrows, rpc, ka, s, A, lda, B, ldb, P);
   else
-    hipLaunchKernelGGL(k_bdot<BA>, dim3(nch, (ka + BA - 1) / BA), dim3(BT), 0, st, nrows, rpc, ka, s, A, lda, B,
+    hipLaunchKernelGGL(k_bdot_mfma, dim3(nch, (ka + BA - 1) / BA), dim3(BT), 0, st, nrows, rpc, ka, s, A, lda, B,
                        ldb, P);
   const int64_t n = (int64_t)ka * s;
   hipLaunchKernelGGL(k_bsum, dim3((unsigned)((n + 31) / 32)), dim3(BT), 0, st, nch, n, P, out);
@@ -217,8 +272,8 @@ void launch_bdot(hipStream_t st, int64_t nrows, int ka, int s, const double2* A,
 void launch_bupd(hipStream_t st, int64_t nrows, int ka, int s, const double2* A, int64_t lda, const double2* H,
                  const double2* Win, int64_t ldwin, double2* Wout, int64_t ldwout, double alpha, double beta) {
   if (nrows <= 0 || s <= 0) return;
-  hipLaunchKernelGGL(k_bupd, dim3((unsigned)((nrows + UR - 1) / UR)), dim3(BT), 0, st, nrows, ka, s, A, lda, H, Win,
-                     ldwin, Wout, ldwout, alpha, beta);
+  hipLaunchKernelGGL(k_bupd_mfma, dim3((unsigned)((nrows + UR - 1) / UR)), dim3(BT), 0, st, nrows, ka, s, A, lda, H,
+                     Win, ldwin, Wout, ldwout, alpha, beta);
 }
 
 void launch_bcopy(hipStream_t st, int64_t nrows, int s, const double2* src, int64_t lds, double2* dst, int64_t ldd) {
