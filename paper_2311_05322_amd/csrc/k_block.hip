@@ -102,13 +102,15 @@ __global__ void __launch_bounds__(BT) k_bdot_mfma(int64_t nrows, int64_t rows_pe
   const int abase = blockIdx.y * BA + 32 * w;
   if (abase >= ka) return;  // whole wave idle (no barriers in this kernel)
   const int kq = lane >> 4, cl = lane & 15;
-  Acc_t<double> cre[2][2], cim[2][2];
+  // 3-multiplication form: t1 = sum ar br, t2 = sum ai bi,
+  // t3 = sum (ar - ai)(br + bi); conj(a) b = (t1 + t2, t3 - t1 + t2)
+  Acc_t<double> t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cre[t][u][q] = cim[t][u][q] = 0.0;
+      for (int q = 0; q < 4; ++q) t1[t][u][q] = t2[t][u][q] = t3[t][u][q] = 0.0;
   const bool aok0 = abase + cl < ka, aok1 = abase + 16 + cl < ka;
   const bool bok0 = cl < s, bok1 = 16 + cl < s;
   for (int64_t rs = r0; rs < r1; rs += 4) {
@@ -119,15 +121,15 @@ __global__ void __launch_bounds__(BT) k_bdot_mfma(int64_t nrows, int64_t rows_pe
     av[1] = rok && aok1 ? A[r * lda + abase + 16 + cl] : make_double2(0.0, 0.0);
     bv[0] = rok && bok0 ? B[r * ldb + cl] : make_double2(0.0, 0.0);
     bv[1] = rok && bok1 ? B[r * ldb + 16 + cl] : make_double2(0.0, 0.0);
+    const double ad[2] = {av[0].x - av[0].y, av[1].x - av[1].y};
+    const double bs[2] = {bv[0].x + bv[0].y, bv[1].x + bv[1].y};
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        // conj(a) b: re = ar br + ai bi, im = ar bi - ai br
-        cre[t][u] = mfma(av[t].x, bv[u].x, cre[t][u]);
-        cre[t][u] = mfma(av[t].y, bv[u].y, cre[t][u]);
-        cim[t][u] = mfma(av[t].x, bv[u].y, cim[t][u]);
-        cim[t][u] = mfma(-av[t].y, bv[u].x, cim[t][u]);
+        t1[t][u] = mfma(av[t].x, bv[u].x, t1[t][u]);
+        t2[t][u] = mfma(av[t].y, bv[u].y, t2[t][u]);
+        t3[t][u] = mfma(ad[t], bs[u], t3[t][u]);
       }
   }
   double2* out = P + (int64_t)blockIdx.x * ka * s;
@@ -139,7 +141,9 @@ __global__ void __launch_bounds__(BT) k_bdot_mfma(int64_t nrows, int64_t rows_pe
       for (int q = 0; q < 4; ++q) {
         const int a = abase + 16 * t + acc_row<double>(lane, q);
         const int b = 16 * u + cl;
-        if (a < ka && b < s) out[(int64_t)a * s + b] = make_double2(cre[t][u][q], cim[t][u][q]);
+        if (a < ka && b < s)
+          out[(int64_t)a * s + b] =
+              make_double2(t1[t][u][q] + t2[t][u][q], t3[t][u][q] - t1[t][u][q] + t2[t][u][q]);
       }
 }
 
@@ -156,13 +160,15 @@ __global__ void __launch_bounds__(BT) k_bupd_mfma(int64_t nrows, int ka, int s, 
   const int lane = tid & 63, w = tid >> 6;
   const int kq = lane >> 4, cl = lane & 15;
   const int64_t rw = (int64_t)blockIdx.x * UR + 32 * w;
-  Acc_t<double> cre[2][2], cim[2][2];
+  // 3-multiplication form: t1 = sum ar hr, t2 = sum ai hi,
+  // t3 = sum (ar + ai)(hr + hi); a h = (t1 - t2, t3 - t1 - t2)
+  Acc_t<double> t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cre[t][u][q] = cim[t][u][q] = 0.0;
+      for (int q = 0; q < 4; ++q) t1[t][u][q] = t2[t][u][q] = t3[t][u][q] = 0.0;
   const bool rok0 = rw + cl < nrows, rok1 = rw + 16 + cl < nrows;
   const double2* A0 = A + (rw + cl) * lda;
   const double2* A1 = A + (rw + 16 + cl) * lda;
@@ -182,10 +188,16 @@ __global__ void __launch_bounds__(BT) k_bupd_mfma(int64_t nrows, int ka, int s, 
       av[1] = rok1 && aok ? A1[a] : make_double2(0.0, 0.0);
       hv[0] = Hs[aa + kq][cl];
       hv[1] = Hs[aa + kq][16 + cl];
+      const double as[2] = {av[0].x + av[0].y, av[1].x + av[1].y};
+      const double hs[2] = {hv[0].x + hv[0].y, hv[1].x + hv[1].y};
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int u = 0; u < 2; ++u) cmfma<double>(av[t], hv[u], cre[t][u], cim[t][u]);
+        for (int u = 0; u < 2; ++u) {
+          t1[t][u] = mfma(av[t].x, hv[u].x, t1[t][u]);
+          t2[t][u] = mfma(av[t].y, hv[u].y, t2[t][u]);
+          t3[t][u] = mfma(as[t], hs[u], t3[t][u]);
+        }
     }
   }
 #pragma unroll
@@ -197,7 +209,8 @@ __global__ void __launch_bounds__(BT) k_bupd_mfma(int64_t nrows, int ka, int s, 
         const int64_t r = rw + 16 * t + acc_row<double>(lane, q);
         const int b = 16 * u + cl;
         if (r >= nrows || b >= s) continue;
-        double re = alpha * cre[t][u][q], im = alpha * cim[t][u][q];
+        double re = alpha * (t1[t][u][q] - t2[t][u][q]);
+        double im = alpha * (t3[t][u][q] - t1[t][u][q] - t2[t][u][q]);
         if (beta != 0.0) {
           const double2 v = Win[r * ldwin + b];
           re = fma(beta, v.x, re);

@@ -122,8 +122,21 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
         const C* row = A + (int64_t)r * N;
 #pragma unroll
         for (int j = 0; j < W; ++j) a[i][j] = row[c0 + j];
-        // W consecutive L entries per load (32 bytes: one sector per lane)
-        for (int l = 0; l < s0; l += W) {
+        // whole 128-byte lines of L per step (the row segment starts on a
+        // line: N and k0 are multiples of 64), then W entries at a time; with
+        // 8 rows per thread the W-wide loads keep a[][] within the registers
+        constexpr int LQ = RPT <= 4 ? 128 / (int)sizeof(C) : W;
+        int l = 0;
+        for (; l + LQ <= s0; l += LQ) {
+          C lv[LQ];
+#pragma unroll
+          for (int q = 0; q < LQ; ++q) lv[q] = row[k0 + l + q];
+#pragma unroll
+          for (int q = 0; q < LQ; ++q)
+#pragma unroll
+            for (int j = 0; j < W; ++j) a[i][j] = csubT(a[i][j], cmulT(lv[q], Utop[l + q][j]));
+        }
+        for (; l < s0; l += W) {
           C lv[W];
 #pragma unroll
           for (int q = 0; q < W; ++q) lv[q] = row[k0 + l + q];
@@ -134,7 +147,9 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
         }
       }
     }
-    // (C) factor the W columns with partial pivoting
+    // (C) factor the W columns with partial pivoting (unrolled: a[][] is
+    // indexed with constants only, so it stays in registers)
+#pragma unroll
     for (int j = 0; j < W; ++j) {
       const int c = c0 + j;
       R best = -1;
