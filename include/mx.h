@@ -191,11 +191,14 @@ int mx_get_tuning(mx_ctx* ctx, mx_tuning* out);
  *     Cholesky QR applied twice (more robust, more sweeps over the basis).
  *   Both block modes: one-level preconditioner
  *     (the learned term is not used), restart after `restart` block steps,
- *     every right-hand side to the same rtol of its own ||b_j||. Used for
- *     1..32 right-hand sides; with more, with a zero right-hand side or a
- *     residual block of numerical rank below its width, the solve runs the
- *     pseudo-block solver instead and reports fallback = 4. Iteration
- *     counts are block steps (the same for every right-hand side).
+ *     every right-hand side to the same rtol of its own ||b_j||. More than 32
+ *     right-hand sides are split into balanced groups of at most 32, each
+ *     with its own block Krylov space; the groups advance in lockstep (one
+ *     preconditioner and operator application over the whole width). With a
+ *     zero right-hand side, or a residual block of numerical rank below its
+ *     width at the start, the solve runs the pseudo-block solver instead and
+ *     reports fallback = 4. Iteration counts are block steps of the
+ *     right-hand side's group.
  * Errors: MX_EINVAL (unknown mode). */
 enum { MX_KRYLOV_PSEUDO_BLOCK = 0, MX_KRYLOV_BLOCK = 1, MX_KRYLOV_BLOCK_CGS2 = 2 };
 int mx_set_krylov(mx_ctx* ctx, int32_t mode);

@@ -8,7 +8,7 @@ paper's study of run time against antenna count (Sec. IV, Table II) on the
 synthetic phantom; the reconstruction-quality columns of that table need the
 paper's shoulder model and are not reproduced.
 
-python -m paper_2311_05322_amd.antenna_sweep [--counts 16,32,64,96] [--steps 2]
+python -m paper_2311_05322_amd.antenna_sweep [--counts 16,32,64,96] [--steps 2] [--krylov block]
 Prints one JSON line per count and a markdown table at the end.
 """
 from __future__ import annotations
@@ -34,9 +34,12 @@ def main():
     ap.add_argument("--c", type=float, default=0.004, help="lattice cube size (4 mm: 1.02M edges)")
     ap.add_argument("--nsub", type=int, default=512)
     ap.add_argument("--precision", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--krylov", choices=["pseudo", "block"], default="pseudo",
+                    help="pseudo-block FGMRES or block FGMRES (groups of at most 32 transmitters)")
     a = ap.parse_args()
     prec = mx.MX_PREC_C64 if a.precision == "c64" else mx.MX_PREC_C128
     ctx = mx.Context(0)
+    ctx.set_krylov(a.krylov == "block")
     rows = []
     first = True
     for n in (int(x) for x in a.counts.split(",")):
@@ -58,7 +61,7 @@ def main():
         dt = (time.perf_counter() - t0) / a.steps
         row = {"antennas": n, "s_per_solve": dt, "s_per_transmitter": dt / n,
                "iters": int(infos[-1]["iters_max"]), "converged": bool(infos[-1]["converged"]),
-               "precision": a.precision, "ne": int(ctx.sizes().ne), "nsub": a.nsub}
+               "precision": a.precision, "krylov": a.krylov, "ne": int(ctx.sizes().ne), "nsub": a.nsub}
         rows.append(row)
         print(json.dumps(row), flush=True)
     ctx.close()

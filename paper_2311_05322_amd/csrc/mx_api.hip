@@ -763,12 +763,12 @@ int ensure_block_host(mx_ctx* c, size_t n) {
   return MX_OK;
 }
 
-// W (ld s) = Q R by Cholesky QR applied twice: Q written to out (ld s), tmp
-// (ld s) scratch, R (upper, row-major) on the host. ok = false when the
+// W = Q R by Cholesky QR applied twice (W, tmp, out: s columns, row stride
+// ld): Q written to out, tmp scratch, R (upper, row-major) on the host. ok = false when the
 // block has numerical rank below s (out is then not written).
 // G1 (host, optional): W^H W when the caller already has it.
-int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, std::vector<cd>& R, bool& ok,
-            const double2* G1 = nullptr) {
+int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, int64_t ld, std::vector<cd>& R,
+            bool& ok, const double2* G1 = nullptr) {
   const int64_t ne = c->topo.ne;
   hipStream_t st = c->stream;
   const size_t ss = (size_t)s * s;
@@ -779,7 +779,7 @@ int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, std:
   if (G1) {
     if (G1 != hG) std::memcpy(hG, G1, ss * sizeof(double2));
   } else {
-    launch_bdot(st, ne, s, s, W, s, W, s, c->bpart.p, c->bG.p);
+    launch_bdot(st, ne, s, s, W, ld, W, ld, c->bpart.p, c->bG.p);
     MX_HIP_CHECK(hipMemcpyAsync(hG, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
     CK(sync(c));
   }
@@ -787,16 +787,16 @@ int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, std:
   if (!ok) return MX_OK;
   upper_inverse(R1, s, hT);
   MX_HIP_CHECK(hipMemcpyAsync(c->bT.p, hT, ss * sizeof(double2), hipMemcpyHostToDevice, st));
-  launch_bupd(st, ne, s, s, W, s, c->bT.p, nullptr, 0, tmp, s, 1.0, 0.0);
+  launch_bupd(st, ne, s, s, W, ld, c->bT.p, nullptr, 0, tmp, ld, 1.0, 0.0);
   // pass 2 on the (nearly orthonormal) first factor
-  launch_bdot(st, ne, s, s, tmp, s, tmp, s, c->bpart.p, c->bG.p);
+  launch_bdot(st, ne, s, s, tmp, ld, tmp, ld, c->bpart.p, c->bG.p);
   MX_HIP_CHECK(hipMemcpyAsync(hG, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
   CK(sync(c));
   ok = gram_cholesky(hG, s, R2, 1e-10);
   if (!ok) return MX_OK;
   upper_inverse(R2, s, hT);
   MX_HIP_CHECK(hipMemcpyAsync(c->bT.p, hT, ss * sizeof(double2), hipMemcpyHostToDevice, st));
-  launch_bupd(st, ne, s, s, tmp, s, c->bT.p, nullptr, 0, out, s, 1.0, 0.0);
+  launch_bupd(st, ne, s, s, tmp, ld, c->bT.p, nullptr, 0, out, ld, 1.0, 0.0);
   MX_HIP_CHECK(hipGetLastError());
   R.assign(ss, 0.0);  // R = R2 R1
   for (int i = 0; i < s; ++i)
@@ -915,36 +915,45 @@ struct BlockLsq {
 };
 
 // Block right-preconditioned FGMRES on b (device) -> x (device, ctx->x) with
-// the one-level preconditioner. Layout: the basis blocks V_0..V_m side by side,
-// row r of the basis holding (m+1)s values (ld (m+1)s), and the preconditioned
-// blocks Z_0..Z_{m-1} likewise (ld ms), so that V^H W, W - V H and X + Z Y are
-// single tall-skinny products. Each step: Z_k = M^-1 V_k, W = A Z_k, block
-// classical Gram-Schmidt twice, W = V_{k+1} R_{k+1} by Cholesky QR twice.
-// Returns kBlockFallback (nothing written to x) when a right-hand side is zero
-// or the residual block has numerical rank below s.
-int block_fgmres(mx_ctx* c, int s, double rtol, mx_solve_info* info) {
+// the one-level preconditioner. The right-hand sides are split into groups of
+// at most 32 columns; every group has its own block Krylov space, and the
+// groups advance in lockstep so that the preconditioner and the operator are
+// applied to the whole width at once. Layout: a group's basis blocks
+// V_0..V_m sit side by side, row r of the basis holding (m+1)s values
+// (ld (m+1)s), its preconditioned blocks Z_0..Z_{m-1} likewise (ld ms), so
+// that V^H W, W - V H and X + Z Y are single tall-skinny products. Each step
+// of a group: Z_k = M^-1 V_k, W = A Z_k, one pass of block classical
+// Gram-Schmidt (a second one when W lay almost entirely in the basis),
+// W = V_{k+1} R_{k+1} by Cholesky QR twice. Returns kBlockFallback (x not
+// meaningful) when a right-hand side is zero or a residual block has
+// numerical rank below its width at the first cycle.
+int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info) {
   const bool two_pass = c->krylov_mode == MX_KRYLOV_BLOCK_CGS2;
   const int m = c->ws_m;
   const int64_t ne = c->topo.ne;
-  const int64_t blk = ne * (int64_t)s;
-  const int64_t LV = (int64_t)(m + 1) * s, LZ = (int64_t)m * s;
+  const int64_t blk = ne * (int64_t)S;
+  const int G = (S + 31) / 32;
+  std::vector<int> g0(G + 1), gs(G);
+  for (int g = 0; g <= G; ++g) g0[g] = (int)((int64_t)g * S / G);
+  for (int g = 0; g < G; ++g) gs[g] = g0[g + 1] - g0[g];
   hipStream_t st = c->stream;
   auto t0 = std::chrono::steady_clock::now();
-  CK(autotune(c, s));
+  CK(autotune(c, S));
+  const int64_t LVmax = (int64_t)(m + 1) * 32;
   CK(c->bw1.alloc(blk));
   CK(c->bw2.alloc(blk));
-  CK(c->bpart.alloc(block_partial_max((int)LV, s)));
-  CK(c->bH.alloc(LV * s));
-  CK(c->bG.alloc((size_t)s * s));
-  CK(c->bT.alloc((size_t)s * s));
-  CK(ensure_block_host(c, 2 * (size_t)s * s + 2 * (size_t)LV * s));
-  double2* hh1 = c->hb + 2 * (size_t)s * s;
-  double2* hh2 = hh1 + (size_t)LV * s;
-  launch_norm(st, ne, s, c->b.p, c->normpart.p, c->bnorm.p);
-  MX_HIP_CHECK(hipMemcpyAsync(c->h_vec, c->bnorm.p, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(c->bpart.alloc(block_partial_max((int)LVmax, 32)));
+  CK(c->bH.alloc(LVmax * 32));
+  CK(c->bG.alloc(32 * 32));
+  CK(c->bT.alloc(32 * 32));
+  CK(ensure_block_host(c, 2 * 32 * 32 + 2 * (size_t)LVmax * 32));
+  double2* hh1 = c->hb + 2 * 32 * 32;
+  double2* hh2 = hh1 + (size_t)LVmax * 32;
+  launch_norm(st, ne, S, c->b.p, c->normpart.p, c->bnorm.p);
+  MX_HIP_CHECK(hipMemcpyAsync(c->h_vec, c->bnorm.p, S * sizeof(double), hipMemcpyDeviceToHost, st));
   CK(sync(c));
-  std::vector<double> bn(s), rr(s);
-  for (int j = 0; j < s; ++j) {
+  std::vector<double> bn(S), rr(S);
+  for (int j = 0; j < S; ++j) {
     bn[j] = c->h_vec[j];
     if (!(bn[j] > 0)) return kBlockFallback;
   }
@@ -952,100 +961,136 @@ int block_fgmres(mx_ctx* c, int s, double rtol, mx_solve_info* info) {
   launch_fill_zero<double2>(st, blk, c->x.p);
   MX_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, blk * sizeof(double2), hipMemcpyDeviceToDevice, st));
   auto true_residual = [&]() -> int {
-    launch_norm(st, ne, s, c->r.p, c->normpart.p, c->beta.p);
-    MX_HIP_CHECK(hipMemcpyAsync(c->h_vec, c->beta.p, s * sizeof(double), hipMemcpyDeviceToHost, st));
+    launch_norm(st, ne, S, c->r.p, c->normpart.p, c->beta.p);
+    MX_HIP_CHECK(hipMemcpyAsync(c->h_vec, c->beta.p, S * sizeof(double), hipMemcpyDeviceToHost, st));
     CK(sync(c));
-    for (int j = 0; j < s; ++j) rr[j] = c->h_vec[j] / bn[j];
+    for (int j = 0; j < S; ++j) rr[j] = c->h_vec[j] / bn[j];
     return MX_OK;
   };
   CK(true_residual());
-  BlockLsq ls;
+  std::vector<BlockLsq> ls(G);
+  std::vector<char> active(G, 1), running(G, 0);
+  std::vector<int> kk(G, 0), steps(G, 0);
+  auto Vg = [&](int g) { return c->V.p + (int64_t)(m + 1) * ne * g0[g]; };
+  auto Zg = [&](int g) { return c->Z.p + (int64_t)m * ne * g0[g]; };
   int total = 0, cycles = 0, rc = MX_OK;
   std::vector<cd> Rk, P;
   for (;;) {
-    double worst = 0;
-    for (int j = 0; j < s; ++j) worst = std::max(worst, rr[j]);
-    if (worst <= rtol) break;
+    int nact = 0;
+    for (int g = 0; g < G; ++g) {
+      double worst = 0;
+      for (int j = g0[g]; j < g0[g + 1]; ++j) worst = std::max(worst, rr[j]);
+      active[g] = active[g] && worst > rtol;
+      nact += active[g];
+    }
+    if (nact == 0) break;
     if (total >= c->maxit) {
       rc = set_err(MX_ENOTCONV, "block FGMRES reached maxit=" + std::to_string(c->maxit));
       break;
     }
-    // R = V_0 S0
-    bool ok = false;
+    // R_g = V_0 S0 for every unfinished group
     c->prof.begin(K_CGS);
-    CK(cholqr2(c, s, c->r.p, c->bw1.p, c->bw2.p, Rk, ok));
-    c->prof.end(K_CGS);
-    if (!ok) {
-      if (total > 0) return set_err(MX_ENOTCONV, "block FGMRES: the residual block lost rank");
-      return kBlockFallback;
+    for (int g = 0; g < G; ++g) {
+      running[g] = 0;
+      kk[g] = 0;
+      if (!active[g]) continue;
+      bool ok = false;
+      CK(cholqr2(c, gs[g], c->r.p + g0[g], c->bw1.p + g0[g], c->bw2.p + g0[g], S, Rk, ok));
+      if (!ok) {
+        c->prof.end(K_CGS);
+        if (total > 0) return set_err(MX_ENOTCONV, "block FGMRES: a residual block lost rank");
+        return kBlockFallback;
+      }
+      launch_bcopy(st, ne, gs[g], c->bw2.p + g0[g], S, Vg(g), (int64_t)(m + 1) * gs[g]);
+      ls[g].reset(gs[g], m, Rk);
+      running[g] = 1;
     }
-    launch_bcopy(st, ne, s, c->bw2.p, s, c->V.p, LV);
-    ls.reset(s, m, Rk);
-    int kk = 0;
+    c->prof.end(K_CGS);
     for (int k = 0; k < m && total < c->maxit; ++k) {
-      // bw2: V_k (contiguous); bw1: Z_k; r: W
-      CK(apply_precond(c, c->bw2.p, c->bw1.p, s));
-      launch_bcopy(st, ne, s, c->bw1.p, s, c->Z.p + (int64_t)k * s, LZ);
-      CK(spmm(c, c->bw1.p, c->r.p, s));
+      bool any = false;
+      for (int g = 0; g < G; ++g) any = any || running[g];
+      if (!any) break;
+      // bw2: V_k of every group; bw1: Z_k; r: W (whole width)
+      CK(apply_precond(c, c->bw2.p, c->bw1.p, S));
+      for (int g = 0; g < G; ++g)
+        if (running[g])
+          launch_bcopy(st, ne, gs[g], c->bw1.p + g0[g], S, Zg(g) + (int64_t)k * gs[g], (int64_t)m * gs[g]);
+      CK(spmm(c, c->bw1.p, c->r.p, S));
       c->prof.begin(K_CGS);
-      const int ka = (k + 1) * s;
-      bool reorth = false;
-      launch_bdot(st, ne, ka, s, c->V.p, LV, c->r.p, s, c->bpart.p, c->bH.p);
-      MX_HIP_CHECK(hipMemcpyAsync(hh1, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
-      if (two_pass) {
-        launch_bupd(st, ne, ka, s, c->V.p, LV, c->bH.p, c->r.p, s, c->r.p, s, -1.0, 1.0);
-        launch_bdot(st, ne, ka, s, c->V.p, LV, c->r.p, s, c->bpart.p, c->bH.p);
-        MX_HIP_CHECK(hipMemcpyAsync(hh2, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
-        launch_bupd(st, ne, ka, s, c->V.p, LV, c->bH.p, c->r.p, s, c->r.p, s, -1.0, 1.0);
-        CK(cholqr2(c, s, c->r.p, c->bw1.p, c->bw2.p, Rk, ok));
-      } else {
-        // one projection pass, repeated only when W lay almost entirely in
-        // the basis (its column norms fell by more than 1e4 in the pass, so
-        // that one pass leaves a loss of orthogonality above ~1e-12); then
-        // Cholesky QR twice
+      for (int g = 0; g < G; ++g) {
+        if (!running[g]) continue;
+        const int s = gs[g];
+        const int64_t LV = (int64_t)(m + 1) * s;
+        double2* W = c->r.p + g0[g];
+        const int ka = (k + 1) * s;
         const size_t ss = (size_t)s * s;
-        double2* hG0 = hh2;
-        double2* hG1 = c->hb;
-        launch_bdot(st, ne, s, s, c->r.p, s, c->r.p, s, c->bpart.p, c->bG.p);
-        MX_HIP_CHECK(hipMemcpyAsync(hG0, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
-        launch_bupd(st, ne, ka, s, c->V.p, LV, c->bH.p, c->r.p, s, c->r.p, s, -1.0, 1.0);
-        launch_bdot(st, ne, s, s, c->r.p, s, c->r.p, s, c->bpart.p, c->bG.p);
-        MX_HIP_CHECK(hipMemcpyAsync(hG1, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
-        CK(sync(c));
-        double rho = 1.0;
-        for (int j = 0; j < s; ++j) rho = std::min(rho, hG1[(size_t)j * s + j].x / hG0[(size_t)j * s + j].x);
-        reorth = !(rho >= 1e-8);
-        if (reorth) {
-          ++c->block_reorth;
-          launch_bdot(st, ne, ka, s, c->V.p, LV, c->r.p, s, c->bpart.p, c->bH.p);
+        bool reorth = false, ok = false;
+        launch_bdot(st, ne, ka, s, Vg(g), LV, W, S, c->bpart.p, c->bH.p);
+        MX_HIP_CHECK(hipMemcpyAsync(hh1, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
+        if (two_pass) {
+          launch_bupd(st, ne, ka, s, Vg(g), LV, c->bH.p, W, S, W, S, -1.0, 1.0);
+          launch_bdot(st, ne, ka, s, Vg(g), LV, W, S, c->bpart.p, c->bH.p);
           MX_HIP_CHECK(hipMemcpyAsync(hh2, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
-          launch_bupd(st, ne, ka, s, c->V.p, LV, c->bH.p, c->r.p, s, c->r.p, s, -1.0, 1.0);
+          launch_bupd(st, ne, ka, s, Vg(g), LV, c->bH.p, W, S, W, S, -1.0, 1.0);
+          CK(cholqr2(c, s, W, c->bw1.p + g0[g], c->bw2.p + g0[g], S, Rk, ok));
+        } else {
+          // one projection pass, repeated only when W lay almost entirely in
+          // the basis (its column norms fell by more than 1e4 in the pass, so
+          // that one pass leaves a loss of orthogonality above ~1e-12); then
+          // Cholesky QR twice
+          double2* hG0 = hh2;
+          double2* hG1 = c->hb;
+          launch_bdot(st, ne, s, s, W, S, W, S, c->bpart.p, c->bG.p);
+          MX_HIP_CHECK(hipMemcpyAsync(hG0, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
+          launch_bupd(st, ne, ka, s, Vg(g), LV, c->bH.p, W, S, W, S, -1.0, 1.0);
+          launch_bdot(st, ne, s, s, W, S, W, S, c->bpart.p, c->bG.p);
+          MX_HIP_CHECK(hipMemcpyAsync(hG1, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
+          CK(sync(c));
+          double rho = 1.0;
+          for (int j = 0; j < s; ++j) rho = std::min(rho, hG1[(size_t)j * s + j].x / hG0[(size_t)j * s + j].x);
+          reorth = !(rho >= 1e-8);
+          if (reorth) {
+            ++c->block_reorth;
+            launch_bdot(st, ne, ka, s, Vg(g), LV, W, S, c->bpart.p, c->bH.p);
+            MX_HIP_CHECK(hipMemcpyAsync(hh2, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
+            launch_bupd(st, ne, ka, s, Vg(g), LV, c->bH.p, W, S, W, S, -1.0, 1.0);
+          }
+          CK(cholqr2(c, s, W, c->bw1.p + g0[g], c->bw2.p + g0[g], S, Rk, ok, reorth ? nullptr : hG1));
         }
-        CK(cholqr2(c, s, c->r.p, c->bw1.p, c->bw2.p, Rk, ok, reorth ? nullptr : hG1));
+        if (!ok) {  // W lost rank: this step of the group is not used, the group restarts
+          running[g] = 0;
+          continue;
+        }
+        launch_bcopy(st, ne, s, c->bw2.p + g0[g], S, Vg(g) + (int64_t)(k + 1) * s, LV);
+        P.assign((size_t)(k + 2) * ss, 0.0);
+        if (two_pass || reorth)
+          for (size_t e = 0; e < (size_t)ka * s; ++e) P[e] = cd(hh1[e].x + hh2[e].x, hh1[e].y + hh2[e].y);
+        else
+          for (size_t e = 0; e < (size_t)ka * s; ++e) P[e] = cd(hh1[e].x, hh1[e].y);
+        for (size_t e = 0; e < ss; ++e) P[(size_t)ka * s + e] = Rk[e];
+        ls[g].add(k, P);
+        kk[g] = k + 1;
+        ++steps[g];
+        double est = 0;
+        for (int j = 0; j < s; ++j) est = std::max(est, ls[g].colres(j) / bn[g0[g] + j]);
+        if (est <= rtol) running[g] = 0;
       }
       c->prof.end(K_CGS);
-      if (!ok) break;  // W lost rank: this step is not used, restart
-      launch_bcopy(st, ne, s, c->bw2.p, s, c->V.p + (int64_t)(k + 1) * s, LV);
-      P.assign((size_t)(k + 2) * s * s, 0.0);
-      if (two_pass || reorth)
-        for (size_t e = 0; e < (size_t)ka * s; ++e) P[e] = cd(hh1[e].x + hh2[e].x, hh1[e].y + hh2[e].y);
-      else
-        for (size_t e = 0; e < (size_t)ka * s; ++e) P[e] = cd(hh1[e].x, hh1[e].y);
-      for (size_t e = 0; e < (size_t)s * s; ++e) P[(size_t)ka * s + e] = Rk[e];
-      ls.add(k, P);
       ++total;
-      kk = k + 1;
-      double est = 0;
-      for (int j = 0; j < s; ++j) est = std::max(est, ls.colres(j) / bn[j]);
-      if (est <= rtol) break;
     }
-    if (kk == 0) return set_err(MX_ENOTCONV, "block FGMRES: the first block of a cycle lost rank");
-    // X += [Z_0 .. Z_kk-1] Y
-    ls.solve(c->hb + 2 * (size_t)s * s);
-    MX_HIP_CHECK(hipMemcpyAsync(c->bH.p, c->hb + 2 * (size_t)s * s, (size_t)kk * s * s * sizeof(double2),
-                                hipMemcpyHostToDevice, st));
-    launch_bupd(st, ne, kk * s, s, c->Z.p, LZ, c->bH.p, c->x.p, s, c->x.p, s, 1.0, 1.0);
-    CK(spmm(c, c->x.p, c->r.p, s));
+    // X_g += [Z_0 .. Z_kk-1] Y_g
+    for (int g = 0; g < G; ++g) {
+      if (!active[g]) continue;
+      if (kk[g] == 0) return set_err(MX_ENOTCONV, "block FGMRES: the first block of a cycle lost rank");
+      const int s = gs[g];
+      ls[g].solve(c->hb + 2 * 32 * 32);
+      MX_HIP_CHECK(hipMemcpyAsync(c->bH.p, c->hb + 2 * 32 * 32, (size_t)kk[g] * s * s * sizeof(double2),
+                                  hipMemcpyHostToDevice, st));
+      launch_bupd(st, ne, kk[g] * s, s, Zg(g), (int64_t)m * s, c->bH.p, c->x.p + g0[g], S, c->x.p + g0[g], S, 1.0,
+                  1.0);
+      CK(sync(c));  // the host buffer of Y is reused by the next group
+    }
+    CK(spmm(c, c->x.p, c->r.p, S));
     launch_bminus(st, blk, c->b.p, c->r.p);
     MX_HIP_CHECK(hipGetLastError());
     CK(true_residual());
@@ -1053,11 +1098,14 @@ int block_fgmres(mx_ctx* c, int s, double rtol, mx_solve_info* info) {
   }
   auto t1 = std::chrono::steady_clock::now();
   if (info) {
-    for (int j = 0; j < s; ++j) {
-      if (info->iters) info->iters[j] = total;
-      if (info->relres) info->relres[j] = rr[j];
-    }
-    info->iters_max = total;
+    int mx_ = 0;
+    for (int g = 0; g < G; ++g)
+      for (int j = g0[g]; j < g0[g + 1]; ++j) {
+        if (info->iters) info->iters[j] = steps[g];
+        if (info->relres) info->relres[j] = rr[j];
+        mx_ = std::max(mx_, steps[g]);
+      }
+    info->iters_max = mx_;
     info->cycles = cycles;
     info->fallback = 0;
     info->t_iter = std::chrono::duration<double>(t1 - t0).count();
@@ -1070,10 +1118,8 @@ int block_fgmres(mx_ctx* c, int s, double rtol, mx_solve_info* info) {
 int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::function<int()>* on_cycle = nullptr) {
   bool block_fallback = false;
   if (c->krylov_mode != MX_KRYLOV_PSEUDO_BLOCK && !on_cycle) {
-    if (nrhs <= 32) {
-      const int rcb = block_fgmres(c, nrhs, rtol, info);
-      if (rcb != kBlockFallback) return rcb;
-    }
+    const int rcb = block_fgmres(c, nrhs, rtol, info);
+    if (rcb != kBlockFallback) return rcb;
     block_fallback = true;
   }
   const int m = c->ws_m;

@@ -2,9 +2,9 @@
 two-pass block Gram-Schmidt) against the oracle: the fields
 of the direct solve (1e-6 with complex128 factors, 1e-5 with complex64), the
 oracle's block FGMRES step count with the same ORAS preconditioner, the
-single-column case equal to the pseudo-block solver, and the fallback to the
-pseudo-block solver for a zero or a repeated right-hand side and for blocks
-wider than 32."""
+single-column case equal to the pseudo-block solver, groups of at most 32
+columns in lockstep for wider blocks, and the fallback to the pseudo-block
+solver for a zero or a repeated right-hand side."""
 import numpy as np
 import pytest
 
@@ -107,11 +107,13 @@ def test_ragged_and_fallbacks():
         b[:, 1] = 0
         x, info = c.ctx.solve_rhs(b, rtol=1e-9)
         assert info["converged"] and info["fallback"] == 4 and np.abs(x[:, 1]).max() == 0
-        # 40 columns: wider than the block solver takes
-        rng = np.random.default_rng(0)
-        b40 = c.B @ rng.standard_normal((c.B.shape[1], 40))
-        x, info = c.ctx.solve_rhs(b40, rtol=1e-8)
-        assert info["converged"] and info["fallback"] == 4
+        # 40 columns: two groups of 20 in lockstep, each its own block space
+        b40 = workload.seeded_complex((c.B.shape[0], 40), 3)
+        x, info = c.ctx.solve_rhs(b40, rtol=1e-9)
+        assert info["converged"] and info["fallback"] == 0
+        u40 = fem.solve_direct(c.A, b40)
+        err = np.linalg.norm(x - u40, axis=0) / np.linalg.norm(u40, axis=0)
+        assert err.max() <= 1e-5, err
     finally:
         c.ctx.close()
 
