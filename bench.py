@@ -325,6 +325,10 @@ def main():
         "variants": others,
         "iters": iters,
         "speedup_vs_fp64_gpu": (value / ref["solves_per_s"]) if ref else None,
+        "fastest_variant": (lambda k: {"name": k, "solves_per_s": others[k]["solves_per_s"],
+                                       "iters": others[k]["iters"],
+                                       "speedup_vs_fp64_gpu": (others[k]["solves_per_s"] / ref["solves_per_s"])
+                                       if ref else None})(max(others, key=lambda k: others[k]["solves_per_s"])),
         "fp64_reference": ref,
         "kernel_ms_per_step": {k: v[0] for k, v in kt_mix.items() if v[1]},
         "roofline": roof,
