@@ -34,10 +34,12 @@ def gpu_cost_grad(ctx, xyz, tet, eps, eb, pos, mom, S_meas, w, alpha, prec, firs
     return J, g, S
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-5)])
-def test_gradient_matches_oracle(prec, tol):
+@pytest.mark.parametrize("prec,tol,block", [(0, 1e-6, False), (1, 1e-5, False), (0, 1e-6, True)],
+                         ids=["c128", "c64", "c128-blockfgmres"])
+def test_gradient_matches_oracle(prec, tol, block):
     xyz, tet, t, eps, eb, pos, mom, S_meas, w = p1_case()
     ctx = mx.Context(0)
+    ctx.set_krylov(block)  # forward and adjoint solves with block FGMRES
     alpha = 1e-6
     J, g, S = gpu_cost_grad(ctx, xyz, tet, eps, eb, pos, mom, S_meas, w, alpha, prec, first=True)
     Jr, gr, Sr = gradient.gradient(t, eps, 1e9, eb, pos, mom, S_meas, w, alpha)
