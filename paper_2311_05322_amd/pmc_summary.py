@@ -22,7 +22,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = {"k_lu_update": ["csrc/k_dense.hip", "csrc/mx_device.h"],
            "k_trsm": ["csrc/k_dense.hip", "csrc/mx_device.h"],
-           "k_spmm": ["csrc/k_operator.hip", "csrc/mx_device.h"]}
+           "k_spmm": ["csrc/k_operator.hip", "csrc/mx_device.h"],
+           "k_spmm_bcast": ["csrc/k_operator.hip", "csrc/mx_device.h"]}
 
 
 def source_hash(kernel: str) -> str:
