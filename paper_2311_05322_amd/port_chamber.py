@@ -10,7 +10,7 @@ dense ORAS subdomain matrices + batched LU, block FGMRES of all ports to
 relative residual 1e-8, scattering matrix.
 
 python -m paper_2311_05322_amd.port_chamber [--h 0.0042] [--ports-per-wall 4]
-    [--precision c64,c128] [--steps 2]
+    [--precision c64,c64-block,c128] [--steps 2]
 Prints one JSON line per precision (progress on stderr).
 """
 from __future__ import annotations
@@ -46,7 +46,8 @@ def main():
     ap.add_argument("--ports-per-wall", type=int, default=4, help="apertures per wall and ring (two rings)")
     ap.add_argument("--nsub", type=int, default=512)
     ap.add_argument("--overlap", type=int, default=1)
-    ap.add_argument("--precision", default="c64,c128")
+    ap.add_argument("--precision", default="c64,c128",
+                    help="comma-separated runs: c64, c128, or c64-block (block FGMRES, complex64 factors)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
@@ -61,7 +62,8 @@ def main():
         print(f"mesh + ports: {time.perf_counter() - t:.1f} s, ne={ctx.sizes().ne}, ports={len(pts)}",
               file=sys.stderr, flush=True)
         for name in a.precision.split(","):
-            prec = mx.MX_PREC_C64 if name == "c64" else mx.MX_PREC_C128
+            prec = mx.MX_PREC_C128 if name == "c128" else mx.MX_PREC_C64
+            ctx.set_krylov(name.endswith("-block"))
 
             def step():
                 ctx.assemble(None, None, eps, mx.MX_EPS_P0, freq, eb, reuse_mesh=True)
