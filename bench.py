@@ -248,7 +248,9 @@ def main():
         ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, factor=False, coarse=True)
         load_weights(ctx, wfile)
     variants = {}
-    order = ([("c64_learned", mx.MX_PREC_C64, True, False, False)] if learned else []) + \
+    # the learned variant runs in block mode: judged learned steps first, then
+    # block FGMRES from that iterate once plain ORAS has switched the term off
+    order = ([("c64_learned", mx.MX_PREC_C64, True, True, False)] if learned else []) + \
         [("c64_plain", mx.MX_PREC_C64, False, False, False)]
     if not args.no_block:
         order.append(("c64_block", mx.MX_PREC_C64, False, True, False))
@@ -321,6 +323,8 @@ def main():
         "config": {"workload": args.workload, "ne": int(sz.ne), "nnz": int(sz.nnz), "nsub": int(sz.nsub),
                    "overlap": p.overlap, "n_i_max": int(n_i.max()), "nrhs": nrhs, "rtol": p.rtol,
                    "restart": args.restart, "coarse": "learned" if head == "c64_learned" else "none",
+                   "krylov": ("judged learned steps, then block FGMRES" if head == "c64_learned"
+                              else "pseudo-block FGMRES"),
                    "precision": "complex64 LU + FP64 FGMRES"},
         "variants": others,
         "iters": iters,

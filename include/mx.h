@@ -189,8 +189,11 @@ int mx_get_tuning(mx_ctx* ctx, mx_tuning* out);
  *     on the host;
  *   MX_KRYLOV_BLOCK_CGS2: the same with block Gram-Schmidt applied twice and
  *     Cholesky QR applied twice (more robust, more sweeps over the basis).
- *   Both block modes: one-level preconditioner
- *     (the learned term is not used), restart after `restart` block steps,
+ *   Both block modes: one-level preconditioner; with the learned term set up
+ *     (coarse = 1), a solve starts with the pseudo-block solver and the
+ *     judged learned term and continues with block FGMRES from the current
+ *     iterate once the judge has switched the term off; restart after
+ *     `restart` block steps,
  *     every right-hand side to the same rtol of its own ||b_j||. More than 32
  *     right-hand sides are split into balanced groups of at most 32, each
  *     with its own block Krylov space; the groups advance in lockstep (one

@@ -218,7 +218,9 @@ class Context:
     def set_krylov(self, block=True, two_pass=False):
         """Block FGMRES (one Krylov space for all right-hand sides; two_pass:
         block Gram-Schmidt and Cholesky QR applied twice) or the default
-        pseudo-block FGMRES (one per right-hand side)."""
+        pseudo-block FGMRES (one per right-hand side). With the learned term
+        set up, block mode runs the judged learned steps first and continues
+        with block FGMRES once the term is switched off."""
         mode = (MX_KRYLOV_BLOCK_CGS2 if two_pass else MX_KRYLOV_BLOCK) if block else MX_KRYLOV_PSEUDO_BLOCK
         _check(lib().mx_set_krylov(self._h, mode))
 

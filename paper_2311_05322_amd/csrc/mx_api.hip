@@ -924,10 +924,11 @@ struct BlockLsq {
 // that V^H W, W - V H and X + Z Y are single tall-skinny products. Each step
 // of a group: Z_k = M^-1 V_k, W = A Z_k, one pass of block classical
 // Gram-Schmidt (a second one when W lay almost entirely in the basis),
-// W = V_{k+1} R_{k+1} by Cholesky QR twice. Returns kBlockFallback (x not
-// meaningful) when a right-hand side is zero or a residual block has
-// numerical rank below its width at the first cycle.
-int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info) {
+// W = V_{k+1} R_{k+1} by Cholesky QR twice. from_x: start from the iterate
+// in ctx->x instead of 0. Returns kBlockFallback (x unchanged) when a
+// right-hand side is zero or a residual block has numerical rank below its
+// width at the first cycle.
+int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x = false) {
   const bool two_pass = c->krylov_mode == MX_KRYLOV_BLOCK_CGS2;
   const int m = c->ws_m;
   const int64_t ne = c->topo.ne;
@@ -958,8 +959,13 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info) {
     if (!(bn[j] > 0)) return kBlockFallback;
   }
   c->coarse_off_now = true;  // the learned term is not used with the block solver
-  launch_fill_zero<double2>(st, blk, c->x.p);
-  MX_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, blk * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  if (from_x) {  // continue from the current iterate
+    CK(spmm(c, c->x.p, c->r.p, S));
+    launch_bminus(st, blk, c->b.p, c->r.p);
+  } else {
+    launch_fill_zero<double2>(st, blk, c->x.p);
+    MX_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, blk * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  }
   auto true_residual = [&]() -> int {
     launch_norm(st, ne, S, c->r.p, c->normpart.p, c->beta.p);
     MX_HIP_CHECK(hipMemcpyAsync(c->h_vec, c->beta.p, S * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1117,7 +1123,12 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info) {
 // the pseudo-block FGMRES described with the autotuner above.
 int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::function<int()>* on_cycle = nullptr) {
   bool block_fallback = false;
-  if (c->krylov_mode != MX_KRYLOV_PSEUDO_BLOCK && !on_cycle) {
+  const bool block_mode = c->krylov_mode != MX_KRYLOV_PSEUDO_BLOCK && !on_cycle;
+  // with the learned term on, block mode first runs the pseudo-block solver
+  // with the judged learned term and hands over to block FGMRES once the
+  // judge has switched the term off
+  bool learned_first = block_mode && c->coarse_use && c->coarse_geom && c->coarse_weights;
+  if (block_mode && !learned_first) {
     const int rcb = block_fgmres(c, nrhs, rtol, info);
     if (rcb != kBlockFallback) return rcb;
     block_fallback = true;
@@ -1243,6 +1254,25 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
       all = all && done[j];
     }
     if (all) break;
+    if (learned_first && c->coarse_off_now) {
+      std::vector<int32_t> bit(nrhs, 0);
+      std::vector<double> brr(nrhs, 0.0);
+      mx_solve_info binfo{};
+      binfo.iters = bit.data();
+      binfo.relres = brr.data();
+      const int rcb = block_fgmres(c, nrhs, rtol, &binfo, true);
+      if (rcb != kBlockFallback) {
+        for (int j = 0; j < nrhs; ++j) {
+          iters[j] += bit[j];
+          rr[j] = brr[j];
+        }
+        cycles += binfo.cycles;
+        rc = rcb;
+        break;
+      }
+      learned_first = false;  // continue with the pseudo-block solver
+      block_fallback = true;
+    }
     if (total >= c->maxit) {
       rc = set_err(MX_ENOTCONV, "FGMRES reached maxit=" + std::to_string(c->maxit));
       break;
@@ -1320,6 +1350,7 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
       int nconv = 0;
       for (int j = 0; j < nrhs; ++j) nconv += c->h_conv[j] != 0 || done[j];
       if (nconv == nrhs || total >= c->maxit) break;
+      if (learned_first && c->coarse_off_now) break;  // hand over to block FGMRES
     }
     if (ksteps < 0) {
       CK(true_residual());

@@ -100,3 +100,21 @@ def test_nonfinite_weights_fall_back(setup):
     _, _, info = ctx.solve(p.src_pos, p.src_mom, rtol=1e-8, want_E=False)
     assert info["converged"] and info["fallback"] == 1
     ctx.coarse_set_weights(theta, sx, sy)
+
+
+def test_block_mode_hands_over_after_the_judge(setup):
+    """Block mode with the learned term: the judged learned steps run first,
+    block FGMRES continues from that iterate; the answer is the direct solve's."""
+    p, t, dec, ctx = setup
+    ctx.setup_schwarz(16, 1, precision=mx.MX_PREC_C64, coarse=True)
+    ctx.set_krylov(True)
+    try:
+        E, _, info = ctx.solve(p.src_pos, p.src_mom, rtol=1e-10)
+    finally:
+        ctx.set_krylov(False)
+    print("iterations", info["iters_max"], "cycles", info["cycles"], "fallback", info["fallback"])
+    assert info["converged"] and np.all(info["relres"] <= 1e-10)
+    A = fem.assemble(t, p.eps, p.eps_kind, p.freq, p.eps_b)
+    U = fem.solve_direct(A, fem.dipole_rhs(t, p.src_pos, p.src_mom, p.freq))
+    err = np.linalg.norm(E - U, axis=0) / np.linalg.norm(U, axis=0)
+    assert err.max() <= 1e-5
