@@ -82,67 +82,106 @@ __global__ void __launch_bounds__(256) k_pool(int nsub, const int64_t* __restric
                                               const double* __restrict__ wts, const double2* __restrict__ v,
                                               int nrhs, int j0, int nj, const double* __restrict__ scale,
                                               float* __restrict__ X, int64_t xrows_stride) {
+  // one workgroup per subdomain; thread (kg, j): right-hand side j, lattice
+  // coefficients k = kg + 8m (m < 24); the subdomain's rows are staged
+  // through LDS 32 at a time (P rows with the optional weight, v rows cast)
+  constexpr int RCH = 32;
+  __shared__ float Ps[RCH][NCO];
+  __shared__ float2 Vs[RCH][32];
   const int i = blockIdx.x;
-  const int k = blockIdx.y * 64 + (threadIdx.x & 63);
-  const int jg = threadIdx.x >> 6;   // 0..3
-  float ar[8], ai[8];
+  const int tid = threadIdx.x;
+  const int j = tid & 31, kg = tid >> 5;
+  float ar[24], ai[24];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) { ar[q] = 0.f; ai[q] = 0.f; }
+  for (int m = 0; m < 24; ++m) { ar[m] = 0.f; ai[m] = 0.f; }
   const int64_t r0 = dof_ptr[i], r1 = dof_ptr[i + 1];
-  for (int64_t l = r0; l < r1; ++l) {
-    float pw = P[l * NCO + k];
-    if (wts) pw *= (float)wts[l];
-    const double2* vr = v + (int64_t)dofs[l] * nrhs + j0;
+  for (int64_t rb = r0; rb < r1; rb += RCH) {
+    const int nr = (int)min((int64_t)RCH, r1 - rb);
+    __syncthreads();
+    for (int e = tid; e < RCH * NCO; e += 256) {
+      const int r = e / NCO, k = e % NCO;
+      float pw = 0.f;
+      if (r < nr) {
+        pw = P[(rb + r) * NCO + k];
+        if (wts) pw *= (float)wts[rb + r];
+      }
+      Ps[r][k] = pw;
+    }
+    for (int e = tid; e < RCH * 32; e += 256) {
+      const int r = e / 32, jj = e % 32;
+      float2 x = make_float2(0.f, 0.f);
+      if (r < nr && jj < nj) {
+        const double2 d = v[(int64_t)dofs[rb + r] * nrhs + j0 + jj];
+        x = make_float2((float)d.x, (float)d.y);
+      }
+      Vs[r][jj] = x;
+    }
+    __syncthreads();
+    for (int r = 0; r < nr; ++r) {
+      const float2 x = Vs[r][j];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int j = jg + 4 * q;
-      if (j < nj) {
-        double2 x = vr[j];
-        ar[q] += pw * (float)x.x;
-        ai[q] += pw * (float)x.y;
+      for (int m = 0; m < 24; ++m) {
+        const float pw = Ps[r][kg + 8 * m];
+        ar[m] += pw * x.x;
+        ai[m] += pw * x.y;
       }
     }
   }
+  if (j < nj) {
+    const double sj = scale[j0 + j];
+    const float inv = sj > 0 ? (float)(1.0 / sj) : 0.f;
+    float* xr = X + ((int64_t)(j0 + j) * nsub + i) * xrows_stride;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int j = jg + 4 * q;
-    if (j < nj) {
-      const double sj = scale[j0 + j];
-      const float inv = sj > 0 ? (float)(1.0 / sj) : 0.f;
-      float* xr = X + ((int64_t)(j0 + j) * nsub + i) * xrows_stride;
-      xr[k] = ar[q] * inv;
-      xr[NCO + k] = ai[q] * inv;
+    for (int m = 0; m < 24; ++m) {
+      xr[kg + 8 * m] = ar[m] * inv;
+      xr[NCO + kg + 8 * m] = ai[m] * inv;
     }
   }
 }
 
 // xloc[vec_off[i] + l][j] += alpha * s_j * sum_k P[l][k] (c_re[k] + j c_im[k])
 template <typename C>
-__global__ void __launch_bounds__(256) k_coarse_apply(int64_t nrows, const int32_t* __restrict__ row_sub,
-                                                      const int64_t* __restrict__ dof_ptr,
+__global__ void __launch_bounds__(256) k_coarse_apply(const int64_t* __restrict__ dof_ptr,
                                                       const int64_t* __restrict__ vec_off, const float* __restrict__ P,
-                                                      const float* __restrict__ Cn, int nsub, int nrhs,
+                                                      const float* __restrict__ Cn, int nsub, int nrhs, int j0, int nj,
                                                       const double* __restrict__ scale, float alpha,
                                                       C* __restrict__ xloc) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= nrows * nrhs) return;
-  const int64_t row = idx / nrhs;
-  const int j = (int)(idx - row * nrhs);
-  const int i = row_sub[row];
-  const float* pr = P + row * NCO;
-  const float* cr = Cn + ((int64_t)j * nsub + i) * NIN;
-  float re = 0.f, im = 0.f;
-  for (int k = 0; k < NCO; ++k) {
-    float p = pr[k];
-    re += p * cr[k];
-    im += p * cr[NCO + k];
+  // workgroup (subdomain i, row slice): the subdomain's coefficients for the
+  // block of right-hand sides staged in LDS as [k][j]; thread (row group,
+  // j) walks its rows with the P row broadcast over the j lanes
+  __shared__ float2 Cs[NCO][32];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int j = tid & 31, rg = tid >> 5;
+  for (int e = tid; e < NCO * 32; e += 256) {
+    const int k = e / 32, jj = e % 32;
+    float2 c = make_float2(0.f, 0.f);
+    if (jj < nj) {
+      const float* cr = Cn + ((int64_t)(j0 + jj) * nsub + i) * NIN;
+      c = make_float2(cr[k], cr[NCO + k]);
+    }
+    Cs[k][jj] = c;
   }
-  const float f = alpha * (float)scale[j];
-  const int64_t o = (vec_off[i] + (row - dof_ptr[i])) * nrhs + j;
-  C x = xloc[o];
-  x.x += f * re;
-  x.y += f * im;
-  xloc[o] = x;
+  __syncthreads();
+  if (j >= nj) return;
+  const float f = alpha * (float)scale[j0 + j];
+  const int64_t r0 = dof_ptr[i], r1 = dof_ptr[i + 1];
+  for (int64_t row = r0 + (int64_t)blockIdx.y * 8 + rg; row < r1; row += 8 * (int64_t)gridDim.y) {
+    const float4* pr = reinterpret_cast<const float4*>(P + row * NCO);
+    float re = 0.f, im = 0.f;
+#pragma unroll 4
+    for (int k4 = 0; k4 < NCO / 4; ++k4) {
+      const float4 p = pr[k4];
+      const float2 c0 = Cs[4 * k4][j], c1 = Cs[4 * k4 + 1][j], c2 = Cs[4 * k4 + 2][j], c3 = Cs[4 * k4 + 3][j];
+      re += p.x * c0.x + p.y * c1.x + p.z * c2.x + p.w * c3.x;
+      im += p.x * c0.y + p.y * c1.y + p.z * c2.y + p.w * c3.y;
+    }
+    const int64_t o = (vec_off[i] + (row - r0)) * nrhs + j0 + j;
+    C x = xloc[o];
+    x.x += f * re;
+    x.y += f * im;
+    xloc[o] = x;
+  }
 }
 
 // G-apply: out[(j*nsub+i)][0:384] = G_i (in[(j*nsub+i)][0:192] , [192:384]) (real G on Re and Im)
@@ -367,8 +406,8 @@ void launch_pool(hipStream_t s, int nsub, const int64_t* dof_ptr, const int32_t*
                  const double* wts, const double2* v, int nrhs, const double* scale, float* X) {
   for (int j0 = 0; j0 < nrhs; j0 += 32) {
     int nj = nrhs - j0 < 32 ? nrhs - j0 : 32;
-    hipLaunchKernelGGL(k_pool, dim3(nsub, NCO / 64), dim3(256), 0, s, nsub, dof_ptr, dofs, P, wts, v, nrhs, j0, nj,
-                       scale, X, (int64_t)NIN);
+    hipLaunchKernelGGL(k_pool, dim3(nsub), dim3(256), 0, s, nsub, dof_ptr, dofs, P, wts, v, nrhs, j0, nj, scale, X,
+                       (int64_t)NIN);
   }
 }
 
@@ -376,10 +415,13 @@ template <typename C>
 void launch_coarse_apply(hipStream_t s, int64_t nrows, const int32_t* row_sub, const int64_t* dof_ptr,
                          const int64_t* vec_off, const float* P, const float* Cn, int nsub, int nrhs,
                          const double* scale, float alpha, C* xloc) {
-  int64_t n = nrows * nrhs;
-  if (n > 0)
-    hipLaunchKernelGGL(k_coarse_apply<C>, dim3(nblk(n, 256)), dim3(256), 0, s, nrows, row_sub, dof_ptr, vec_off, P,
-                       Cn, nsub, nrhs, scale, alpha, xloc);
+  (void)row_sub;
+  if (nrows <= 0 || nsub <= 0) return;
+  for (int j0 = 0; j0 < nrhs; j0 += 32) {
+    const int nj = nrhs - j0 < 32 ? nrhs - j0 : 32;
+    hipLaunchKernelGGL(k_coarse_apply<C>, dim3(nsub, 8), dim3(256), 0, s, dof_ptr, vec_off, P, Cn, nsub, nrhs, j0,
+                       nj, scale, alpha, xloc);
+  }
 }
 template void launch_coarse_apply<float2>(hipStream_t, int64_t, const int32_t*, const int64_t*, const int64_t*,
                                           const float*, const float*, int, int, const double*, float, float2*);
