@@ -3,15 +3,15 @@
 // [rows][ld] device arrays: row r of a block of s columns holds its s
 // complex values contiguously, as the right-hand-side blocks of the solver.
 //
-//   k_bdot   P[chunk] = A[chunk rows, 0:ka]^H B[chunk rows, 0:s]   (partials)
+//   k_bdot_* P[chunk] = A[chunk rows, 0:ka]^H B[chunk rows, 0:s]   (partials;
+//            _mfma for ka > 32, _narrow for ka <= 32)
 //   k_bsum   out = sum over chunks of P (fixed order: deterministic)
 //   k_bupd   Wout = beta Win + alpha A[:, 0:ka] H (H ka x s; Win may be Wout:
 //            each output element is read and written by one lane)
 //   k_bcopy  dst[:, 0:s] = src[:, 0:s] between blocks of different ld
 //
-// Wide products run on the FP64 matrix cores (16x16x4 MFMA, operands straight
-// from memory, no LDS broadcast); the narrow Gram products (ka <= 32) on the
-// vector units with 1 x 4 complex register tiles and LDS-staged operands.
+// All products run on the FP64 matrix cores (16x16x4 MFMA, complex products in
+// the 3-multiplication form, operands straight from memory).
 #include "mx_device.h"
 #include "mx_kernels.h"
 
@@ -19,73 +19,11 @@ namespace mx {
 
 namespace {
 constexpr int BT = 256;   // threads per workgroup
-constexpr int BA = 128;   // columns of A per k_bdot workgroup (32 when ka <= 32)
-constexpr int BR = 32;    // rows per LDS stage of k_bdot
+constexpr int BA = 128;   // columns of A per k_bdot_mfma workgroup
+constexpr int BR = 32;    // row-chunk granularity of the block dots
 constexpr int UR = 128;   // rows per k_bupd_mfma workgroup
 constexpr int UA = 128;   // rows of H per LDS stage of k_bupd_mfma
 }  // namespace
-
-template <int TA>
-__global__ void __launch_bounds__(BT) k_bdot(int64_t nrows, int64_t rows_per_chunk, int ka, int s,
-                                             const double2* __restrict__ A, int64_t lda,
-                                             const double2* __restrict__ B, int64_t ldb,
-                                             double2* __restrict__ P) {
-  constexpr int MA = TA / 32;  // a-columns per thread
-  __shared__ double2 As[BR][TA];
-  __shared__ double2 Bs[BR][32];
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
-  const int64_t r1 = min(nrows, r0 + rows_per_chunk);
-  const int a0 = blockIdx.y * TA;
-  const int tid = threadIdx.x;
-  const int bg = tid & 7, ag = tid >> 3;
-  double cre[MA][4], cim[MA][4];
-#pragma unroll
-  for (int i = 0; i < MA; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) cre[i][j] = cim[i][j] = 0.0;
-  for (int64_t rs = r0; rs < r1; rs += BR) {
-    for (int e = tid; e < BR * TA; e += BT) {
-      const int rr = e / TA, aa = e % TA;
-      const int64_t r = rs + rr;
-      const int a = a0 + aa;
-      As[rr][aa] = (r < r1 && a < ka) ? A[r * lda + a] : make_double2(0.0, 0.0);
-    }
-    for (int e = tid; e < BR * 32; e += BT) {
-      const int rr = e / 32, bb = e % 32;
-      const int64_t r = rs + rr;
-      Bs[rr][bb] = (r < r1 && bb < s) ? B[r * ldb + bb] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < BR; ++rr) {
-      double2 av[MA], bv[4];
-#pragma unroll
-      for (int q = 0; q < MA; ++q) av[q] = As[rr][ag * MA + q];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) bv[q] = Bs[rr][bg * 4 + q];
-#pragma unroll
-      for (int i = 0; i < MA; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          // conj(a) b
-          cre[i][j] = fma(av[i].x, bv[j].x, fma(av[i].y, bv[j].y, cre[i][j]));
-          cim[i][j] = fma(av[i].x, bv[j].y, fma(-av[i].y, bv[j].x, cim[i][j]));
-        }
-    }
-    __syncthreads();
-  }
-  double2* out = P + (int64_t)blockIdx.x * ka * s;
-#pragma unroll
-  for (int i = 0; i < MA; ++i) {
-    const int a = a0 + ag * MA + i;
-    if (a >= ka) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int b = bg * 4 + j;
-      if (b < s) out[(int64_t)a * s + b] = make_double2(cre[i][j], cim[i][j]);
-    }
-  }
-}
 
 // The same partial products on the FP64 matrix cores, for ka > 32: a
 // workgroup takes a 128-wide tile of A's columns (wave w: columns 32w..32w+31
@@ -145,6 +83,69 @@ __global__ void __launch_bounds__(BT) k_bdot_mfma(int64_t nrows, int64_t rows_pe
           out[(int64_t)a * s + b] =
               make_double2(t1[t][u][q] + t2[t][u][q], t3[t][u][q] - t1[t][u][q] + t2[t][u][q]);
       }
+}
+
+// The narrow products (ka <= 32, e.g. Gram matrices) on the FP64 matrix
+// cores: every wave computes the whole 32 x 32 output over every fourth group
+// of 4 rows of the chunk, and the four waves' sums are added in wave order
+// through LDS before the chunk's partial is written.
+__global__ void __launch_bounds__(BT) k_bdot_narrow(int64_t nrows, int64_t rows_per_chunk, int ka, int s,
+                                                    const double2* __restrict__ A, int64_t lda,
+                                                    const double2* __restrict__ B, int64_t ldb,
+                                                    double2* __restrict__ P) {
+  __shared__ double2 red[4][32][32];
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r1 = min(nrows, r0 + rows_per_chunk);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int kq = lane >> 4, cl = lane & 15;
+  Acc_t<double> t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t1[t][u][q] = t2[t][u][q] = t3[t][u][q] = 0.0;
+  const bool aok0 = cl < ka, aok1 = 16 + cl < ka;
+  const bool bok0 = cl < s, bok1 = 16 + cl < s;
+  for (int64_t rs = r0 + 4 * w; rs < r1; rs += 16) {
+    const int64_t r = rs + kq;
+    const bool rok = r < r1;
+    double2 av[2], bv[2];
+    av[0] = rok && aok0 ? A[r * lda + cl] : make_double2(0.0, 0.0);
+    av[1] = rok && aok1 ? A[r * lda + 16 + cl] : make_double2(0.0, 0.0);
+    bv[0] = rok && bok0 ? B[r * ldb + cl] : make_double2(0.0, 0.0);
+    bv[1] = rok && bok1 ? B[r * ldb + 16 + cl] : make_double2(0.0, 0.0);
+    const double ad[2] = {av[0].x - av[0].y, av[1].x - av[1].y};
+    const double bs[2] = {bv[0].x + bv[0].y, bv[1].x + bv[1].y};
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        t1[t][u] = mfma(av[t].x, bv[u].x, t1[t][u]);
+        t2[t][u] = mfma(av[t].y, bv[u].y, t2[t][u]);
+        t3[t][u] = mfma(ad[t], bs[u], t3[t][u]);
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        red[w][16 * t + acc_row<double>(lane, q)][16 * u + cl] =
+            make_double2(t1[t][u][q] + t2[t][u][q], t3[t][u][q] - t1[t][u][q] + t2[t][u][q]);
+  __syncthreads();
+  double2* out = P + (int64_t)blockIdx.x * ka * s;
+  for (int e = threadIdx.x; e < 32 * 32; e += BT) {
+    const int a = e / 32, b = e % 32;
+    if (a >= ka || b >= s) continue;
+    double re = 0, im = 0;
+    for (int ww = 0; ww < 4; ++ww) {
+      re += red[ww][a][b].x;
+      im += red[ww][a][b].y;
+    }
+    out[(int64_t)a * s + b] = make_double2(re, im);
+  }
 }
 
 // Wout = beta Win + alpha A H on the FP64 matrix cores: a workgroup takes 128
@@ -274,7 +275,7 @@ void launch_bdot(hipStream_t st, int64_t nrows, int ka, int s, const double2* A,
   int64_t rpc;
   const int nch = block_chunks(nrows, ka, &rpc);
   if (ka <= 32)
-    hipLaunchKernelGGL(k_bdot<32>, dim3(nch, 1), dim3(BT), 0, st, nrows, rpc, ka, s, A, lda, B, ldb, P);
+    hipLaunchKernelGGL(k_bdot_narrow, dim3(nch, 1), dim3(BT), 0, st, nrows, rpc, ka, s, A, lda, B, ldb, P);
   else
     hipLaunchKernelGGL(k_bdot_mfma, dim3(nch, (ka + BA - 1) / BA), dim3(BT), 0, st, nrows, rpc, ka, s, A, lda, B,
                        ldb, P);
