@@ -18,7 +18,8 @@
 //                  reduction, then L11 -> L11^{-1} in place and the composed
 //                  row permutation of the panel;
 //   k_lu_rowpanel  applies the permutation to the columns outside the panel
-//                  and forms U12 = L11^{-1} A12 (MFMA);
+//                  and forms U12 = L11^{-1} A12 (MFMA); k_lu_rowswap the
+//                  permutation alone;
 //   k_lu_update    A22 -= L21 U12 on 64x64 tiles (MFMA, LDS-staged operands),
 //                  the trailing matrix once per group of LU_GROUP panels.
 #include "mx_device.h"
@@ -314,7 +315,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
 // mode 2: U12 only, from the rows k0..k0+63 as they stand (the permutation
 // already applied and any deferred update of those rows already done).
 // --------------------------------------------------------------------------
-template <typename R>
+template <typename R, int XR>
 __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                      const int32_t* __restrict__ Npad,
                                                      const int32_t* __restrict__ order,
@@ -329,7 +330,9 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
   C* A = pool + mat_off[s];
   const int32_t* ps = pswap + (int64_t)s * (2 * MAXSW + 1);
   const int n = mode == 2 ? NB : ps[0];
-  __shared__ C X[MAXSW][NB + 1];
+  // XR rows of staging: MAXSW for the permutation modes, NB for mode 2 (half
+  // the LDS, so twice the workgroups per CU)
+  __shared__ C X[XR][NB + 1];
   const int tid = threadIdx.x;
   for (int e = tid; e < n * NB; e += 256) {
     int q = e / NB, j = e % NB;
@@ -377,6 +380,39 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
       v.y = cim[ct][r];
       A[(int64_t)(k0 + row) * N + cb + 16 * ct + (lane & 15)] = v;
     }
+}
+
+// The permutation alone (a group's later panels): the rows ps[1+MAXSW+q]
+// move to ps[1+q] in one 64-column tile outside the panel; every thread holds
+// the values it moves in registers, and all reads finish (workgroup barrier)
+// before any write.
+template <typename R>
+__global__ void __launch_bounds__(256) k_lu_rowswap(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                                    const int32_t* __restrict__ Npad,
+                                                    const int32_t* __restrict__ order,
+                                                    const int32_t* __restrict__ pswap, int k0) {
+  typedef C_t<R> C;
+  constexpr int PER = MAXSW * NB / 256;
+  const int s = order[blockIdx.y];
+  const int N = Npad[s];
+  const int cb = blockIdx.x * NB;
+  if (cb >= N || cb == k0 || k0 >= N) return;  // the whole workgroup
+  C* A = pool + mat_off[s];
+  const int32_t* ps = pswap + (int64_t)s * (2 * MAXSW + 1);
+  const int n = ps[0];
+  const int tid = threadIdx.x;
+  C v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u;
+    if (e < n * NB) v[u] = A[(int64_t)ps[1 + MAXSW + e / NB] * N + cb + e % NB];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u;
+    if (e < n * NB) A[(int64_t)ps[1 + e / NB] * N + cb + e % NB] = v[u];
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -868,8 +904,12 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
       launch_panel<R>(st, pool, mat_off, Npad, order, piv, vec_off, status, pswap, Nmax, nact, ki);
       MX_TE(K_LU_PANEL);
       MX_TB(K_LU_ROWPANEL);
-      hipLaunchKernelGGL((k_lu_rowpanel<R>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad, order, pswap,
-                         ki, i == 0 ? 0 : 1);
+      if (i > 0 && sizeof(R) == 4)  // complex64: the moved values fit in registers
+        hipLaunchKernelGGL((k_lu_rowswap<R>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad, order, pswap,
+                           ki);
+      else
+        hipLaunchKernelGGL((k_lu_rowpanel<R, MAXSW>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad,
+                           order, pswap, ki, i == 0 ? 0 : 1);
       MX_TE(K_LU_ROWPANEL);
       const int kn = ki + NB;
       if (i == 0 || kn >= Nmax) continue;
@@ -878,8 +918,8 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
                          order, g0, i * NB, ki, kn);
       MX_TE(K_LU_UPDATE);
       MX_TB(K_LU_ROWPANEL);
-      hipLaunchKernelGGL((k_lu_rowpanel<R>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad, order, pswap,
-                         ki, 2);
+      hipLaunchKernelGGL((k_lu_rowpanel<R, NB>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad, order,
+                         pswap, ki, 2);
       MX_TE(K_LU_ROWPANEL);
     }
     const int ke = g0 + LU_GROUP * NB;
