@@ -72,3 +72,26 @@ def test_receiver_normalisation():
     R = ports.port_functionals(t, pts, fp, pe)
     u0 = fem.edge_interpolant(t, lambda x: ports.mode(pts[0], x).astype(complex))
     assert abs(R[:, 0] @ u0 - 1.0) <= 2e-2
+
+
+def test_box_chamber_apertures():
+    """The generated port chamber: every aperture is covered by whole boundary
+    faces (5 x 2 lattice cells = 20 triangles), apertures do not overlap, the
+    field direction v = n x u is vertical, and reciprocity holds on a coarse
+    lattice with the phantom inside."""
+    xyz, tet, pts = workload.box_chamber(0.24, 0.2, 0.03, 1, (0.25, 0.75))
+    t = fem.Topology(xyz, tet)
+    fp = ports.classify(t, pts)
+    assert len(pts) == 8 and np.array_equal(np.bincount(fp[fp >= 0], minlength=8), np.full(8, 20))
+    for p in pts:
+        v = np.cross(p.normal, p.u)
+        assert np.allclose(v, (0, 0, 1))
+    with pytest.raises(ValueError):
+        workload.box_chamber(0.24, 0.2, 0.03, 2)       # two 5-cell apertures on an 8-cell wall
+    lab = workload.shoulder_phantom(0).labels(workload.tet_centroids(xyz, tet))
+    eps = workload.eps_of_labels(lab, F)
+    eb = workload.eps_r(*workload.MATERIALS["matching"], F)
+    A, fp, pe = ports.assemble(t, eps, 0, F, eb, pts, pec=True)
+    U = fem.solve_direct(A, ports.port_rhs(t, pts, fp, pe, F))
+    S = ports.scattering(ports.port_functionals(t, pts, fp, pe), U)
+    assert np.abs(S - S.T).max() <= 1e-10 * np.abs(S).max()
