@@ -128,9 +128,9 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
 #pragma unroll
         for (int j = 0; j < W; ++j) a[i][j] = row[c0 + j];
         // whole 128-byte lines of L per step (the row segment starts on a
-        // line: N and k0 are multiples of 64), then W entries at a time; with
-        // 8 rows per thread the W-wide loads keep a[][] within the registers
-        constexpr int LQ = RPT <= 4 ? 128 / (int)sizeof(C) : W;
+        // line: N and k0 are multiples of 64), half lines with 8 rows per
+        // thread (register budget), then W entries at a time
+        constexpr int LQ = RPT <= 4 ? 128 / (int)sizeof(C) : 64 / (int)sizeof(C);
         int l = 0;
         for (; l + LQ <= s0; l += LQ) {
           C lv[LQ];
