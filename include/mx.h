@@ -185,8 +185,8 @@ int mx_get_tuning(mx_ctx* ctx, mx_tuning* out);
  *     right-hand sides: block Arnoldi with one pass of classical block
  *     Gram-Schmidt (a second pass only when the pass removed all but 1e-8
  *     of a column's squared norm), the new block orthonormalised by Cholesky
- *     QR applied twice; block Hessenberg least squares by Givens rotations
- *     on the host;
+ *     QR (a second pass unless the block is well conditioned); block
+ *     Hessenberg least squares by Givens rotations on the host;
  *   MX_KRYLOV_BLOCK_CGS2: the same with block Gram-Schmidt applied twice and
  *     Cholesky QR applied twice (more robust, more sweeps over the basis).
  *   Both block modes: one-level preconditioner; with the learned term set up

@@ -712,7 +712,7 @@ constexpr int kBlockFallback = 1000;  // internal: run the pseudo-block solver i
 // through the Cholesky factor of D^-1 G D^-1 (D = diag(G)^(1/2)), so that the
 // column scales of the block do not enter the rank test: false when a scaled
 // pivot is not above tol (the block has numerical rank below s).
-bool gram_cholesky(const double2* G, int s, std::vector<cd>& R, double tol) {
+bool gram_cholesky(const double2* G, int s, std::vector<cd>& R, double tol, double* min_pivot = nullptr) {
   std::vector<double> d(s);
   for (int i = 0; i < s; ++i) {
     const double g = G[(size_t)i * s + i].x;
@@ -720,10 +720,12 @@ bool gram_cholesky(const double2* G, int s, std::vector<cd>& R, double tol) {
     d[i] = std::sqrt(g);
   }
   std::vector<cd> L((size_t)s * s, 0.0);
+  double pmin = 1.0;
   for (int j = 0; j < s; ++j) {
     double piv = G[(size_t)j * s + j].x / (d[j] * d[j]);
     for (int k = 0; k < j; ++k) piv -= std::norm(L[(size_t)j * s + k]);
     if (!(piv > tol)) return false;
+    pmin = std::min(pmin, piv);
     const double ljj = std::sqrt(piv);
     L[(size_t)j * s + j] = ljj;
     for (int i = j + 1; i < s; ++i) {
@@ -736,6 +738,7 @@ bool gram_cholesky(const double2* G, int s, std::vector<cd>& R, double tol) {
   R.assign((size_t)s * s, 0.0);
   for (int i = 0; i < s; ++i)
     for (int j = i; j < s; ++j) R[(size_t)i * s + j] = std::conj(L[(size_t)j * s + i]) * d[j];
+  if (min_pivot) *min_pivot = pmin;
   return true;
 }
 
@@ -763,9 +766,10 @@ int ensure_block_host(mx_ctx* c, size_t n) {
   return MX_OK;
 }
 
-// W = Q R by Cholesky QR applied twice (W, tmp, out: s columns, row stride
-// ld): Q written to out, tmp scratch, R (upper, row-major) on the host. ok = false when the
-// block has numerical rank below s (out is then not written).
+// W = Q R by Cholesky QR (W, tmp, out: s columns, row stride ld), applied a
+// second time unless the scaled block is well conditioned: Q written to out,
+// tmp scratch, R (upper, row-major) on the host. ok = false when the block
+// has numerical rank below s (out is then not written).
 // G1 (host, optional): W^H W when the caller already has it.
 int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, int64_t ld, std::vector<cd>& R,
             bool& ok, const double2* G1 = nullptr) {
@@ -783,10 +787,19 @@ int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, int6
     MX_HIP_CHECK(hipMemcpyAsync(hG, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
     CK(sync(c));
   }
-  ok = gram_cholesky(hG, s, R1, 1e-14);
+  double pmin = 0;
+  ok = gram_cholesky(hG, s, R1, 1e-14, &pmin);
   if (!ok) return MX_OK;
   upper_inverse(R1, s, hT);
   MX_HIP_CHECK(hipMemcpyAsync(c->bT.p, hT, ss * sizeof(double2), hipMemcpyHostToDevice, st));
+  if (pmin >= 1e-4) {
+    // the scaled block has condition number below ~100: one pass leaves Q
+    // orthonormal to ~1e-12, the second is skipped
+    launch_bupd(st, ne, s, s, W, ld, c->bT.p, nullptr, 0, out, ld, 1.0, 0.0);
+    MX_HIP_CHECK(hipGetLastError());
+    R = R1;
+    return MX_OK;
+  }
   launch_bupd(st, ne, s, s, W, ld, c->bT.p, nullptr, 0, tmp, ld, 1.0, 0.0);
   // pass 2 on the (nearly orthonormal) first factor
   launch_bdot(st, ne, s, s, tmp, ld, tmp, ld, c->bpart.p, c->bG.p);
@@ -924,9 +937,10 @@ struct BlockLsq {
 // that V^H W, W - V H and X + Z Y are single tall-skinny products. Each step
 // of a group: Z_k = M^-1 V_k, W = A Z_k, one pass of block classical
 // Gram-Schmidt (a second one when W lay almost entirely in the basis),
-// W = V_{k+1} R_{k+1} by Cholesky QR twice. from_x: start from the iterate
-// in ctx->x instead of 0. Returns kBlockFallback (x unchanged) when a
-// right-hand side is zero or a residual block has numerical rank below its
+// W = V_{k+1} R_{k+1} by Cholesky QR (twice unless well conditioned).
+// from_x: start from the iterate in ctx->x instead of 0. Returns
+// kBlockFallback (x unchanged) when a right-hand side is zero or a residual
+// block has numerical rank below its
 // width at the first cycle.
 int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x = false) {
   const bool two_pass = c->krylov_mode == MX_KRYLOV_BLOCK_CGS2;
@@ -1043,7 +1057,7 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x
           // one projection pass, repeated only when W lay almost entirely in
           // the basis (its column norms fell by more than 1e4 in the pass, so
           // that one pass leaves a loss of orthogonality above ~1e-12); then
-          // Cholesky QR twice
+          // Cholesky QR (twice unless well conditioned)
           double2* hG0 = hh2;
           double2* hG1 = c->hb;
           launch_bdot(st, ne, s, s, W, S, W, S, c->bpart.p, c->bG.p);
