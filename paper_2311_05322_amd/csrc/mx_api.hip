@@ -940,8 +940,7 @@ struct BlockLsq {
 // W = V_{k+1} R_{k+1} by Cholesky QR (twice unless well conditioned).
 // from_x: start from the iterate in ctx->x instead of 0. Returns
 // kBlockFallback (x unchanged) when a right-hand side is zero or a residual
-// block has numerical rank below its
-// width at the first cycle.
+// block has numerical rank below its width at the first cycle.
 int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x = false) {
   const bool two_pass = c->krylov_mode == MX_KRYLOV_BLOCK_CGS2;
   const int m = c->ws_m;
