@@ -1057,16 +1057,22 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x
           // the basis (its column norms fell by more than 1e4 in the pass, so
           // that one pass leaves a loss of orthogonality above ~1e-12); then
           // Cholesky QR (twice unless well conditioned)
-          double2* hG0 = hh2;
+          // (||W_j||^2 = ||W'_j||^2 + ||H1_j||^2 for the orthonormal basis)
           double2* hG1 = c->hb;
-          launch_bdot(st, ne, s, s, W, S, W, S, c->bpart.p, c->bG.p);
-          MX_HIP_CHECK(hipMemcpyAsync(hG0, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
           launch_bupd(st, ne, ka, s, Vg(g), LV, c->bH.p, W, S, W, S, -1.0, 1.0);
           launch_bdot(st, ne, s, s, W, S, W, S, c->bpart.p, c->bG.p);
           MX_HIP_CHECK(hipMemcpyAsync(hG1, c->bG.p, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
           CK(sync(c));
           double rho = 1.0;
-          for (int j = 0; j < s; ++j) rho = std::min(rho, hG1[(size_t)j * s + j].x / hG0[(size_t)j * s + j].x);
+          for (int j = 0; j < s; ++j) {
+            double h2 = 0;
+            for (int a = 0; a < ka; ++a) {
+              const double2 h = hh1[(size_t)a * s + j];
+              h2 += h.x * h.x + h.y * h.y;
+            }
+            const double w2 = hG1[(size_t)j * s + j].x;
+            rho = std::min(rho, w2 / (w2 + h2));
+          }
           reorth = !(rho >= 1e-8);
           if (reorth) {
             ++c->block_reorth;
