@@ -605,19 +605,27 @@ __global__ void __launch_bounds__(64) k_perm(int32_t nsub, const int32_t* __rest
 // sides per workgroup, 256-row super-blocks, 64-row diagonal blocks applied
 // through their stored inverses.
 //
-// Off-diagonal part of a super-block: wave w owns rows 64w..64w+63 and
-// accumulates A[rows, K] X[K] on its own, with no workgroup barrier: it
-// streams its factor rows and the matching right-hand-side rows straight
-// into MFMA operand registers, one 16-column chunk ahead of the chunk being
-// multiplied (the right-hand-side rows are shared by the four waves and
-// come from L1/L2). The diagonal part then runs on the super-block's
-// residual held in LDS: each 64-row diagonal block is multiplied by its
-// stored inverse and the remaining rows of the super-block are updated,
-// spread over all four waves in 16-row tiles.
+// Off-diagonal part of a super-block: each wave owns 16*RT rows (RT = 4 for
+// complex64: four waves; RT = 2 for complex128: eight waves) and accumulates
+// A[rows, K] X[K] on its own, with no workgroup barrier: it streams its
+// factor rows and the matching right-hand-side rows straight into MFMA
+// operand registers (complex64: one 16-column chunk ahead of the chunk being
+// multiplied); the right-hand-side rows are shared by the waves and come from
+// L1/L2. Two workgroups share a compute unit for complex64; for complex128
+// the workgroup's LDS admits one per compute unit, and its eight waves keep
+// two on each SIMD so that one wave's loads are covered by the other's
+// products. The diagonal part then runs on the super-block's residual held in
+// LDS: each 64-row diagonal block is multiplied by its stored inverse and the
+// remaining rows of the super-block are updated, spread over all waves in
+// 16-row tiles.
 // --------------------------------------------------------------------------
 constexpr int SB = 256;
 constexpr int KC = 16;
 constexpr int RC = 32;
+template <typename R> struct TrsmShape;
+template <> struct TrsmShape<float> { static constexpr int RT = 4; };
+template <> struct TrsmShape<double> { static constexpr int RT = 2; };
+template <typename R> constexpr int trsm_waves() { return SB / (16 * TrsmShape<R>::RT); }
 
 template <typename R, bool LOWER>
 __device__ inline C_t<R> diag_inv_elem(const C_t<R>* A, int N, int b0, int i, int k) {
@@ -637,7 +645,7 @@ __device__ inline C_t<R> diag_inv_elem(const C_t<R>* A, int N, int b0, int i, in
 // same permuted k, columns 16*ct + lane%16.
 template <typename R>
 struct trsm_ops {
-  C_t<R> a[4][4];
+  C_t<R> a[TrsmShape<R>::RT][4];
   C_t<R> b[4][2];
 };
 
@@ -645,7 +653,7 @@ template <typename R>
 __device__ __forceinline__ void trsm_load(trsm_ops<R>& o, const C_t<R>* __restrict__ Arow, int N,
                                           const C_t<R>* __restrict__ X, int nrhs, int j0, int nc, int kc, int lane) {
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt) {
+  for (int rt = 0; rt < TrsmShape<R>::RT; ++rt) {
     const C_t<R>* ap = Arow + (int64_t)(16 * rt + (lane & 15)) * N + kc + 4 * (lane >> 4);
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) o.a[rt][s4] = ap[s4];
@@ -660,29 +668,15 @@ __device__ __forceinline__ void trsm_load(trsm_ops<R>& o, const C_t<R>* __restri
 }
 
 template <typename R>
-__device__ __forceinline__ void trsm_mul(const trsm_ops<R>& o, Acc_t<R> (&cre)[4][2], Acc_t<R> (&cim)[4][2]) {
-#pragma unroll
-  for (int s4 = 0; s4 < 4; ++s4) {
-    C_t<R> bn[2];
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) bn[ct].y = -o.b[s4][ct].y;
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) cmfma_nb<R>(o.a[rt][s4], o.b[s4][ct], bn[ct], cre[rt][ct], cim[rt][ct]);
-  }
-}
-
-template <typename R>
-__device__ __forceinline__ void trsm_mul3(const trsm_ops<R>& o, Acc_t<R> (&t1)[4][2], Acc_t<R> (&t2)[4][2],
-                                          Acc_t<R> (&t3)[4][2]) {
+__device__ __forceinline__ void trsm_mul3(const trsm_ops<R>& o, Acc_t<R> (&t1)[TrsmShape<R>::RT][2],
+                                          Acc_t<R> (&t2)[TrsmShape<R>::RT][2], Acc_t<R> (&t3)[TrsmShape<R>::RT][2]) {
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4) {
     R bs[2];
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) bs[ct] = o.b[s4][ct].x + o.b[s4][ct].y;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
+    for (int rt = 0; rt < TrsmShape<R>::RT; ++rt) {
       const R as = o.a[rt][s4].x + o.a[rt][s4].y;
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
@@ -695,12 +689,13 @@ __device__ __forceinline__ void trsm_mul3(const trsm_ops<R>& o, Acc_t<R> (&t1)[4
 }
 
 template <typename R, bool LOWER>
-__global__ void __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1)
+__global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
     k_trsm(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off, const int32_t* __restrict__ Npad,
            const int64_t* __restrict__ vec_off, const int32_t* __restrict__ order, C_t<R>* __restrict__ xloc,
            int nrhs) {
   typedef C_t<R> C;
   typedef Acc_t<R> Acc;
+  constexpr int TRT = TrsmShape<R>::RT, TNW = trsm_waves<R>();
   const int s = order[blockIdx.x];
   const int N = Npad[s];
   const C* A = pool + mat_off[s];
@@ -714,20 +709,20 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1)
     const int sbi = LOWER ? q : nsb - 1 - q;
     const int b0 = sbi * SB;
     const int nd = min(SB, N - b0) / NB;
-    if (w < nd) {
-      const C* Arow = A + (int64_t)(b0 + NB * w) * N;
-      Acc cre[4][2], cim[4][2];
+    if (w < nd * (NB / (16 * TRT))) {  // this wave's rows lie in the super-block
+      const C* Arow = A + (int64_t)(b0 + 16 * TRT * w) * N;
+      Acc cre[TRT][2], cim[TRT][2];
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) { cre[rt][ct] = zacc<R>(); cim[rt][ct] = zacc<R>(); }
       // off-diagonal part over K = [kbeg, kbeg + KC * nch)
       const int kbeg = LOWER ? 0 : b0 + nd * NB;
       const int nch = ((LOWER ? b0 : N) - kbeg) / KC;
       if (nch > 0) {
-        Acc t3[4][2];
+        Acc t3[TRT][2];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
+        for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct) t3[rt][ct] = zacc<R>();
         if constexpr (sizeof(R) == 4) {
@@ -740,7 +735,6 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1)
             if (c + 1 < nch) trsm_mul3<R>(o1, cre, cim, t3);
           }
         } else {
-          // complex128: the three accumulator sets take 192 registers
           trsm_ops<R> o0;
           for (int c = 0; c < nch; ++c) {
             trsm_load<R>(o0, Arow, N, X, nrhs, j0, nc, kbeg + c * KC, lane);
@@ -749,7 +743,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1)
         }
         // cre = sum a.re b.re, cim = sum a.im b.im, t3 = sum (a.re + a.im)(b.re + b.im)
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
+        for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct) {
             const Acc t1 = cre[rt][ct], t2 = cim[rt][ct];
@@ -758,12 +752,12 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1)
           }
       }
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = NB * w + 16 * rt + acc_row<R>(lane, r);
+            const int row = 16 * TRT * w + 16 * rt + acc_row<R>(lane, r);
             const int col = 16 * ct + (lane & 15);
             C x = col < nc ? X[(int64_t)(b0 + row) * nrhs + j0 + col] : czero<C>();
             x.x -= cre[rt][ct][r];
@@ -772,40 +766,46 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1)
           }
     }
     __syncthreads();
-    // diagonal part
+    // diagonal part: waves 0..3 hold the four 16-row tiles of a diagonal block
+    const bool dw = w < NB / 16;
     for (int dq = 0; dq < nd; ++dq) {
       const int d = LOWER ? dq : nd - 1 - dq;
       const int db = b0 + NB * d;
-      C dv[NB / 4];
-#pragma unroll
-      for (int kk = 0; kk < NB / 4; ++kk) dv[kk] = diag_inv_elem<R, LOWER>(A, N, db, 16 * w + (lane & 15), 4 * kk + (lane >> 4));
       Acc yre[2], yim[2];
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) { yre[ct] = zacc<R>(); yim[ct] = zacc<R>(); }
+      if (dw) {
+        C dv[NB / 4];
 #pragma unroll
-      for (int kk = 0; kk < NB / 4; ++kk)
+        for (int kk = 0; kk < NB / 4; ++kk)
+          dv[kk] = diag_inv_elem<R, LOWER>(A, N, db, 16 * w + (lane & 15), 4 * kk + (lane >> 4));
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          C bv = Tb[NB * d + 4 * kk + (lane >> 4)][16 * ct + (lane & 15)];
-          cmfma<R>(dv[kk], bv, yre[ct], yim[ct]);
-        }
+        for (int kk = 0; kk < NB / 4; ++kk)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            C bv = Tb[NB * d + 4 * kk + (lane >> 4)][16 * ct + (lane & 15)];
+            cmfma<R>(dv[kk], bv, yre[ct], yim[ct]);
+          }
+      }
       __syncthreads();
+      if (dw) {
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
+        for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * w + acc_row<R>(lane, r);
-          const int col = 16 * ct + (lane & 15);
-          C v;
-          v.x = yre[ct][r];
-          v.y = yim[ct][r];
-          Tb[NB * d + row][col] = v;
-          if (col < nc) X[(int64_t)(db + row) * nrhs + j0 + col] = v;
-        }
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * w + acc_row<R>(lane, r);
+            const int col = 16 * ct + (lane & 15);
+            C v;
+            v.x = yre[ct][r];
+            v.y = yim[ct][r];
+            Tb[NB * d + row][col] = v;
+            if (col < nc) X[(int64_t)(db + row) * nrhs + j0 + col] = v;
+          }
+      }
       __syncthreads();
       // update the remaining diagonal blocks of this super-block, 16-row tiles
       const int nrem = LOWER ? (nd - 1 - d) : d;
-      for (int t = w; t < 4 * nrem; t += 4) {
+      for (int t = w; t < 4 * nrem; t += TNW) {
         const int dd = LOWER ? d + 1 + t / 4 : t / 4;
         const int rt = t % 4;
         C av[NB / 4];
@@ -865,11 +865,9 @@ static void launch_panel(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, c
                        status, pswap, k0);
 }
 
-// Panels are taken in pairs (k0, k0 + 64). After the first panel only the
-// second panel's columns are updated; after the second, the two panels'
-// update of the rest of the matrix is applied in one 128-deep pass. The rows
-// of the second panel receive the first panel's update between the row
-// permutation and U12 = L11^{-1} A12 of the second panel.
+// Batched LU with partial pivoting of all subdomain matrices (largest first,
+// a subdomain drops out of a launch once its order is passed), then the
+// inverses of the 64x64 diagonal blocks of U used by the triangular solves.
 template <typename R>
 void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
                int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
@@ -953,10 +951,10 @@ void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, con
   if (nsub <= 0 || nrhs <= 0) return;
   dim3 grid(nsub, ceil_div(nrhs, RC));
   MX_TB(K_TRSM_LOWER);
-  hipLaunchKernelGGL((k_trsm<R, true>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs);
+  hipLaunchKernelGGL((k_trsm<R, true>), grid, dim3(64 * trsm_waves<R>()), 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs);
   MX_TE(K_TRSM_LOWER);
   MX_TB(K_TRSM_UPPER);
-  hipLaunchKernelGGL((k_trsm<R, false>), grid, dim3(256), 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs);
+  hipLaunchKernelGGL((k_trsm<R, false>), grid, dim3(64 * trsm_waves<R>()), 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs);
   MX_TE(K_TRSM_UPPER);
 }
 template void launch_trsm<float>(hipStream_t, const float2*, const int64_t*, const int32_t*, const int64_t*,
