@@ -417,13 +417,14 @@ __global__ void __launch_bounds__(256) k_lu_rowswap(C_t<R>* __restrict__ pool, c
 
 // --------------------------------------------------------------------------
 // trailing update A[r0.., c0..] -= A[r0.., kl..kl+kd) A[kl..kl+kd), c0..] on
-// 64x64 tiles (kd = 64: one panel; kd = 128: two panels at once, which halves
-// the passes over the trailing matrix), complex products in the
-// 3-multiplication form (three real MFMA products instead of four); the
-// panels are staged in 32-deep chunks (33.5 KB of LDS for complex64, 67 KB
-// for complex128), for complex64 with the next chunk already in registers
-// while the current one is multiplied; the C tile is loaded before the
-// staging.
+// 64x64 tiles (kd = 512 for the update of the trailing matrix after a group
+// of eight panels, one 512-deep pass instead of eight 64-deep ones; smaller
+// kd for the in-group updates of one 64-wide column or row block), complex
+// products in the 3-multiplication form (three real MFMA products instead of
+// four); the panels are staged in 32-deep chunks (33.5 KB of LDS for
+// complex64, 67 KB for complex128), for complex64 with the next chunk already
+// in registers while the current one is multiplied; the C tile is loaded
+// before the staging.
 // --------------------------------------------------------------------------
 constexpr int KCH = 32;
 
