@@ -22,7 +22,7 @@ constexpr int BT = 256;   // threads per workgroup
 constexpr int BA = 128;   // columns of A per k_bdot_mfma workgroup
 constexpr int BR = 32;    // row-chunk granularity of the block dots
 constexpr int UR = 128;   // rows per k_bupd_mfma workgroup
-constexpr int UA = 128;   // rows of H per LDS stage of k_bupd_mfma
+constexpr int UA = 64;    // rows of H per LDS stage of k_bupd_mfma (32 KB)
 }  // namespace
 
 // The same partial products on the FP64 matrix cores, for ka > 32: a
@@ -30,7 +30,9 @@ constexpr int UA = 128;   // rows of H per LDS stage of k_bupd_mfma
 // as two 16-wide MFMA tiles) and all 32 columns of B (two tiles), and walks
 // the rows of its chunk 4 at a time (the MFMA depth); lane l holds row
 // 4c + (l >> 4) of column l & 15 of each tile, loaded straight from memory.
-__global__ void __launch_bounds__(BT) k_bdot_mfma(int64_t nrows, int64_t rows_per_chunk, int ka, int s,
+// Capped at 170 registers, the accumulators move out of the AGPRs and the
+// kernel fits in 128, four waves per SIMD (two at the default allocation).
+__global__ void __launch_bounds__(BT, 3) k_bdot_mfma(int64_t nrows, int64_t rows_per_chunk, int ka, int s,
                                                   const double2* __restrict__ A, int64_t lda,
                                                   const double2* __restrict__ B, int64_t ldb,
                                                   double2* __restrict__ P) {
@@ -150,9 +152,10 @@ __global__ void __launch_bounds__(BT) k_bdot_narrow(int64_t nrows, int64_t rows_
 
 // Wout = beta Win + alpha A H on the FP64 matrix cores: a workgroup takes 128
 // rows (wave w: rows 32w..32w+31 as two 16-row MFMA tiles) and all 32
-// columns; H is staged through LDS 128 rows at a time; lane l holds A's row
-// l & 15 of each tile at column 4c + (l >> 4).
-__global__ void __launch_bounds__(BT) k_bupd_mfma(int64_t nrows, int ka, int s, const double2* __restrict__ A,
+// columns; H is staged through LDS 64 rows at a time (32 KB, so that LDS
+// admits three workgroups per CU, the register cap's occupancy); lane l holds
+// A's row l & 15 of each tile at column 4c + (l >> 4).
+__global__ void __launch_bounds__(BT, 3) k_bupd_mfma(int64_t nrows, int ka, int s, const double2* __restrict__ A,
                                                   int64_t lda, const double2* __restrict__ H,
                                                   const double2* Win, int64_t ldwin, double2* Wout,
                                                   int64_t ldwout, double alpha, double beta) {
