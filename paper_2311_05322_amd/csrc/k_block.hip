@@ -153,9 +153,10 @@ __global__ void __launch_bounds__(BT) k_bdot_narrow(int64_t nrows, int64_t rows_
 // Wout = beta Win + alpha A H on the FP64 matrix cores: a workgroup takes 128
 // rows (wave w: rows 32w..32w+31 as two 16-row MFMA tiles) and all 32
 // columns; H is staged through LDS 64 rows at a time (32 KB, so that LDS
-// admits three workgroups per CU, the register cap's occupancy); lane l holds
-// A's row l & 15 of each tile at column 4c + (l >> 4).
-__global__ void __launch_bounds__(BT, 3) k_bupd_mfma(int64_t nrows, int ka, int s, const double2* __restrict__ A,
+// admits four workgroups per CU, the register cap's occupancy: four waves per
+// SIMD, with two values spilled outside the loops); lane l holds A's row
+// l & 15 of each tile at column 4c + (l >> 4).
+__global__ void __launch_bounds__(BT, 4) k_bupd_mfma(int64_t nrows, int ka, int s, const double2* __restrict__ A,
                                                   int64_t lda, const double2* __restrict__ H,
                                                   const double2* Win, int64_t ldwin, double2* Wout,
                                                   int64_t ldwout, double alpha, double beta) {
