@@ -8,12 +8,12 @@
  *     (curl E) x n + j k n x (E x n) = 0                   on dOmega,
  *
  * (time factor exp(+j omega t), k = k0 sqrt(eps_r)); this is the forward
- * problem of the microwave-imaging method (paper Sec. III-B, eq. (1) and
+ * problem of the microwave-imaging method (paper Sec. IV-B, eq. (1) and
  * its weak form (2), with the open-side impedance condition on the whole
  * outer boundary and point dipoles in place of the waveguide ports).  The
- * linear systems A u_j = b_j (Sec. III-C) are solved with right-
+ * linear systems A u_j = b_j (Sec. IV-C) are solved with right-
  * preconditioned flexible GMRES and a one-level Optimized Restricted Additive
- * Schwarz preconditioner (Sec. III-C), with all transmitters as one block of
+ * Schwarz preconditioner (Sec. IV-C), with all transmitters as one block of
  * right-hand sides.  Receiver responses S_ij = r_i^T u_j follow the
  * scattering functional (eq. (3)) with point receivers.
  *
@@ -91,7 +91,7 @@ typedef struct {
   const mx_c128* moment;
 } mx_sources;
 
-/* Waveguide port (Sec. III-B, eq. (1)): a planar rectangle on the mesh
+/* Waveguide port (Sec. IV-B, eq. (1)): a planar rectangle on the mesh
  * boundary with outward unit normal `normal`, broad-side direction `u`
  * (orthogonalised against the normal), width a along u and height b along
  * v = normal x u, centred at `centre`, filled with relative permittivity eps.
@@ -178,7 +178,7 @@ int mx_set_autotune(mx_ctx* ctx, int enable);
 int mx_get_tuning(mx_ctx* ctx, mx_tuning* out);
 
 /* Krylov solver of every solve (mx_solve, mx_solve_rhs, mx_solve_ports and
- * the adjoint solve of mx_gradient), Sec. III-C:
+ * the adjoint solve of mx_gradient), Sec. IV-C:
  *   MX_KRYLOV_PSEUDO_BLOCK (default): one FGMRES per right-hand side, run as
  *     one block of kernels;
  *   MX_KRYLOV_BLOCK: block FGMRES, one block Krylov space shared by all
@@ -206,7 +206,7 @@ int mx_get_tuning(mx_ctx* ctx, mx_tuning* out);
 enum { MX_KRYLOV_PSEUDO_BLOCK = 0, MX_KRYLOV_BLOCK = 1, MX_KRYLOV_BLOCK_CGS2 = 2 };
 int mx_set_krylov(mx_ctx* ctx, int32_t mode);
 
-/* Port form of the boundary conditions of eq. (1) (Sec. III-B). A boundary
+/* Port form of the boundary conditions of eq. (1) (Sec. IV-B). A boundary
  * face belongs to port p when its centroid lies in that port's plane and
  * rectangle (relative tolerance 1e-6 of a + b); port faces carry
  * j beta_p int (E x n).(v x n) in place of the impedance term. With pec != 0
@@ -252,7 +252,7 @@ int mx_get_kernel_times(mx_ctx* ctx, mx_kernel_times* out);
 int mx_assemble(mx_ctx* ctx, const mx_mesh* mesh, const mx_c128* eps, int eps_kind,
                 double freq_hz, mx_c128 eps_b);
 
-/* ORAS set-up (Sec. III-C): recursive coordinate bisection into nsub = 2^L
+/* ORAS set-up (Sec. IV-C): recursive coordinate bisection into nsub = 2^L
  * parts, `overlap` layers of vertex-adjacent tetrahedra, integer partition
  * of unity, local matrices with impedance transmission conditions, and the
  * batched dense LU of all subdomain matrices (one set of launches).  The
@@ -273,7 +273,7 @@ int mx_setup_schwarz(mx_ctx* ctx, int32_t nsub, int32_t overlap, const mx_schwar
 int mx_solve(mx_ctx* ctx, const mx_sources* tx, const mx_sources* rx, double rtol,
              mx_c128* E, mx_c128* S, mx_solve_info* info);
 
-/* Cost and adjoint-state gradient of the inverse problem (Sec. III-D, eq. (4)):
+/* Cost and adjoint-state gradient of the inverse problem (Sec. IV-D, eq. (4)):
  *   J = 1/2 sum_ij w_ij |S_ij - S_meas_ij|^2 + alpha/2 int |grad kappa|^2,
  *   kappa = k0^2 eps, eps piecewise linear (MX_EPS_P1),
  * for the transmitters and receivers of the immediately preceding mx_solve

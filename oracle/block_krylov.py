@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The Krylov solver of Sec. III-C is GMRES; with many transmitters per
+The Krylov solver of Sec. IV-C is GMRES; with many transmitters per
 permittivity (one per antenna) the right-hand sides form a block B, and the
 block variant builds a single block Krylov space from the residual block
 R0 = B - A X0 and minimises every column's residual over it. Readings where

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Problem (paper Sec. III-B, eq. (1) and its weak form (2)): find E in
+Problem (paper Sec. IV-B, eq. (1) and its weak form (2)): find E in
 H(curl) with
 
     int curl E . curl v - k^2 E . v  +  int_{dOmega} j k (E x n).(v x n)
@@ -12,7 +12,7 @@ k^2 = k0^2 eps_r, exp(+j omega t).  The outer boundary carries the
 first-order impedance (absorbing) condition of the open sides; the source is
 a point dipole J = p delta(x - x_s) instead of the waveguide port.  The
 discrete space is the first-order Nedelec (edge) element on tetrahedra
-(Sec. III-C: r = 1).  No conjugation appears in (2), so the matrix is
+(Sec. IV-D: r = 1).  No conjugation appears in (2), so the matrix is
 complex symmetric.
 """
 from __future__ import annotations

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Cost (Sec. III-D, eq. (4)), with kappa = k^2 = k0^2 eps:
+Cost (Sec. IV-D, eq. (4)), with kappa = k^2 = k0^2 eps:
 
     J(eps) = 1/2 sum_ij w_ij |S_ij(eps) - S^meas_ij|^2 + alpha R,
     R      = 1/2 int |grad kappa|^2,

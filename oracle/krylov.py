@@ -1,4 +1,4 @@
-"""Right-preconditioned flexible GMRES (the Krylov solver of Sec. III-C).
+"""Right-preconditioned flexible GMRES (the Krylov solver of Sec. IV-C).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Not a method of the paper: the paper's preconditioner is one-level ORAS
-(Sec. III-C).  This component is the solver's own addition; its definition
+(Sec. IV-C).  This component is the solver's own addition; its definition
 (fixed here and mirrored by the GPU kernels):
 
 * Coarse lattice of subdomain i: the axis-aligned bounding box [lo, hi] of the

@@ -1,6 +1,6 @@
 """Waveguide ports and metallic walls (TEST INFRASTRUCTURE ONLY).
 
-Boundary conditions of eq. (1) in their port form (Sec. III-B): metallic
+Boundary conditions of eq. (1) in their port form (Sec. IV-B): metallic
 walls Gamma_m (n x E = 0), transmitting/receiving waveguide ports where the
 dominant TE10 mode is imposed through (curl E) x n + j beta n x (E x n) = g,
 g = 2 j beta E^TE10, and the scattering coefficients of eq. (3).

@@ -3,7 +3,7 @@ colouring and the ORAS subdomain matrices.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The paper (Sec. III-C) solves each linear system with GMRES preconditioned
+The paper (Sec. IV-C) solves each linear system with GMRES preconditioned
 by Optimized Restricted Additive Schwarz: the mesh is split into overlapping
 subdomains small enough for direct solvers, each subdomain problem carries
 an impedance (transmission) condition on its artificial boundary, and the

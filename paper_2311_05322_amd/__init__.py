@@ -57,7 +57,7 @@ class Sources(ct.Structure):
 
 class Port(ct.Structure):
     """Waveguide port: rectangle (centre, outward normal, broad side u, a x b)
-    filled with relative permittivity eps; TE10 incidence (Sec. III-B)."""
+    filled with relative permittivity eps; TE10 incidence (Sec. IV-B)."""
     _fields_ = [("centre", ct.c_double * 3), ("normal", ct.c_double * 3), ("u", ct.c_double * 3),
                 ("a", ct.c_double), ("b", ct.c_double), ("eps", c128)]
 

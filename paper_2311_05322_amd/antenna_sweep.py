@@ -4,7 +4,7 @@ The transmitters are N unit z-dipoles on the ring r = 0.11 m (z = 0.10 m) of
 the 1.02M-edge chamber; every N is one block right-hand side. One step is the
 same as in bench.py: operator values, dense ORAS matrices + batched LU, block
 FGMRES of all N transmitters to relative residual 1e-8. The sweep mirrors the
-paper's study of run time against antenna count (Sec. IV, Table II) on the
+paper's study of run time against antenna count (Sec. VI, Table II) on the
 synthetic phantom; the reconstruction-quality columns of that table need the
 paper's shoulder model and are not reproduced.
 

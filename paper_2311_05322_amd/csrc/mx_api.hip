@@ -1503,7 +1503,7 @@ int coarse_prepare(mx_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// waveguide ports (Sec. III-B, eq. (1))
+// waveguide ports (Sec. IV-B, eq. (1))
 // ---------------------------------------------------------------------------
 double2 port_beta(double k0, const mx_port& p) {
   const double2 z = make_double2(k0 * k0 * p.eps.re - (M_PI / p.a) * (M_PI / p.a), k0 * k0 * p.eps.im);

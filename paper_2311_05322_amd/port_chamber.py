@@ -1,7 +1,7 @@
 """All-port solves of the waveguide-port chamber model on one GPU.
 
 The antennas are open-ended ceramic-filled waveguides (eps_r = 59, TE10,
-Sec. II and III-B): rectangular apertures on the side walls of a box chamber
+Sec. III and IV-B): rectangular apertures on the side walls of a box chamber
 with metallic walls elsewhere, the shoulder phantom inside and the matching
 liquid around it. Every port transmits in turn (g = 2 j beta e_TE10 on its
 aperture, all ports as one block right-hand side) and every port receives

@@ -1,4 +1,4 @@
-"""Quasi-Newton reconstruction of the permittivity (Sec. III-D).
+"""Quasi-Newton reconstruction of the permittivity (Sec. IV-D).
 
 The unknown is the piecewise-linear relative permittivity of an inverse mesh
 (one complex value per vertex). The cost is eq. (4): the misfit of the
@@ -9,7 +9,7 @@ both on the GPU; the outer iteration is limited-memory BFGS with an Armijo
 backtracking line search on the vector of real and imaginary parts, which
 costs O(m nv) host arithmetic per iteration next to two all-transmitter solves.
 
-Metrics of Sec. IV: err = ||Re eps_rec - Re eps_exact|| / ||Re eps_exact||
+Metrics of Sec. VI, eqs. (6)-(7): err = ||Re eps_rec - Re eps_exact|| / ||Re eps_exact||
 (whole domain and injury area), ctr = mean over the injury area of
 eps_rec(injured data) - eps_rec(healthy data).
 

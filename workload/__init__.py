@@ -5,13 +5,13 @@ per-vertex relative permittivities, and point-dipole positions.  It contains
 none of the solver's arithmetic (no basis functions, no element matrices, no
 linear algebra), so both the CPU oracle and the GPU path may import it.
 
-The paper (Sec. III-A) builds conformal meshes of a CAD shoulder with MMG;
+The paper (Sec. IV-A) builds conformal meshes of a CAD shoulder with MMG;
 neither the CAD model nor the mesher is available, so a seeded, jittered
 Kuhn lattice clipped to a cylinder stands in for the chamber mesh, and a
 shoulder-like phantom (bone, muscle, tendon, tear ellipsoid) assigns the
 Table I tissue classes.  Permittivities use the paper's material law
 eps_r = eps' - j sigma / (omega eps0) with the exp(+j omega t) convention
-(Sec. III-B).
+(Sec. IV-B).
 """
 from __future__ import annotations
 
@@ -36,7 +36,7 @@ MATERIALS = {
 
 
 def eps_r(eps_prime: float, sigma: float, freq_hz: float) -> complex:
-    """Complex relative permittivity eps' - j sigma/(omega eps0) (Sec. III-B)."""
+    """Complex relative permittivity eps' - j sigma/(omega eps0) (Sec. IV-B)."""
     return complex(eps_prime, -sigma / (2.0 * math.pi * freq_hz * EPS0))
 
 
@@ -309,7 +309,7 @@ def box_chamber(side: float, height: float, h: float, ports_per_wall: int = 4, r
     (broad side horizontal, height along z) on the four side walls, spread
     evenly along each wall at the heights rings * height, snapped to lattice
     lines (ValueError if two apertures would overlap). The paper's antennas are ceramic-filled (eps_r = 59) open-ended
-    guides on rings around the imaging domain (Sec. II)."""
+    guides on rings around the imaging domain (Sec. III)."""
     nxy = int(math.ceil(side / h))
     nz = int(math.ceil(height / h))
     xyz, tet = kuhn_box((nxy, nxy, nz), (-side / 2, -side / 2, 0.0), (side / 2, side / 2, height))
