@@ -116,6 +116,11 @@ typedef struct {
                           solve (non-finite output / a cycle with < 10% reduction /
                           the first steps removed < 5% of the one-level residual);
                           4: block FGMRES fell back to the pseudo-block solver */
+  double t_assemble;   /* seconds of the mx_assemble that built the operator in use
+                          (operator values; includes topology when a mesh was given) */
+  double t_setup;      /* seconds of the mx_setup_schwarz that built the factors in use
+                          (local matrices + factorisation; partition when rebuilt) */
+  double t_lu;         /* of t_setup: device time of the batched factorisation */
 } mx_solve_info;
 
 /* Sizes of the current discretisation and decomposition. */
@@ -149,8 +154,11 @@ typedef struct {
   int64_t launches[MX_K_NCLASS]; /* number of timed intervals per class         */
 } mx_kernel_times;
 
-/* Create a context on HIP device `device` (own stream). */
-int mx_create(mx_ctx** out, int device);
+/* Create a context on HIP device `device`.  hip_stream (a hipStream_t passed
+ * as void*) is the stream all work of the context runs on; NULL gives the
+ * context a stream of its own.  The caller keeps a passed stream alive while
+ * the context uses it.  Errors: MX_EINVAL (NULL out, no such device), MX_EHIP. */
+int mx_create(mx_ctx** out, int device, void* hip_stream);
 int mx_destroy(mx_ctx* ctx);
 
 /* Run all further work of the context on the caller's HIP stream
@@ -248,7 +256,11 @@ int mx_get_kernel_times(mx_ctx* ctx, mx_kernel_times* out);
  *             host or device
  *   freq_hz   frequency (> 0)
  *   eps_b     permittivity used in the outer impedance condition
- * Errors: MX_EINVAL for bad sizes, non-finite eps or a degenerate tet. */
+ * Tetrahedra may have either orientation (vertex ids are sorted and |det|
+ * is used).
+ * Errors: MX_EINVAL for bad sizes, a frequency that is not positive (k0 = 0
+ * would leave the curl-curl operator singular), non-finite eps or a
+ * degenerate (zero-volume) tet. */
 int mx_assemble(mx_ctx* ctx, const mx_mesh* mesh, const mx_c128* eps, int eps_kind,
                 double freq_hz, mx_c128 eps_b);
 
@@ -258,7 +270,10 @@ int mx_assemble(mx_ctx* ctx, const mx_mesh* mesh, const mx_c128* eps, int eps_ki
  * batched dense LU of all subdomain matrices (one set of launches).  The
  * partition is cached while the mesh, nsub and overlap are unchanged.
  * opts may be NULL (complex128, restart 30, maxit 2000, factor 1).
- * Errors: MX_EINVAL (nsub not a power of two, overlap < 1), MX_EPIVOT. */
+ * Errors: MX_EINVAL (nsub not a power of two, overlap < 1), MX_EPIVOT (a
+ * subdomain matrix has a column with no usable pivot: zero or non-finite,
+ * e.g. entries beyond the complex64 range; the message names the subdomain
+ * and the column; the factors are not usable and solves return MX_ESTATE). */
 int mx_setup_schwarz(mx_ctx* ctx, int32_t nsub, int32_t overlap, const mx_schwarz_opts* opts);
 
 /* All-transmitter solve: b_j = -j omega mu0 p_j . N_e(x_j) for every source

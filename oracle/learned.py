@@ -23,14 +23,21 @@ Not a method of the paper: the paper's preconditioner is one-level ORAS
 * Training target: c*_i minimising ||D_i^{1/2} (R_i (e - M^{-1} r)/s - P_i c)||^2
   + lam ||c||^2, lam = 1e-6 tr(P^T D P)/192, for residual/error pairs (r, e)
   of the plain solver; loss = mean over nodes and channels of (c - c*)^2.
+* Inside FGMRES the correction enters as z = M^{-1} v + theta_j q_j with one
+  complex weight per transmitter minimising ||v_j - A z_j|| (theta_combination).
 * BF16 arithmetic: the operands of every matrix product (weights and
   activations) rounded to bfloat16 (round to nearest even), products
   accumulated in higher precision; biases, GELU and the loss are not rounded.
+* Optimiser: Adam on FP32 master weights.
 
 Pinned by: exact reproduction of linear fields by P_i (partition of unity of
-the trilinear hats), the backward pass against central finite differences,
-and bf16 rounding against numpy's float32 -> bfloat16 bit arithmetic spelled
-out independently in the tests.
+the trilinear hats); GELU, the forward pass (with and without bf16 rounding),
+the loss and its parameter gradient against an independent PyTorch
+construction of the same network (torch's GELU, autograd, torch's bfloat16
+conversion); the backward pass against central finite differences; Adam
+against torch.optim.Adam; bf16 rounding against bit arithmetic spelled out
+in the tests; theta as the least-squares weight (orthogonality of the
+residual it leaves, no perturbed weight does better).
 """
 from __future__ import annotations
 
@@ -110,40 +117,44 @@ def subdomain_box(topo, tets):
     return X.min(axis=0), X.max(axis=0)
 
 
-def lattice_prolongation(topo, dofs, lo, hi):
-    """P [n, 192] of the edges `dofs` on the 4x4x4 lattice of the box [lo, hi]."""
+def lattice_prolongation(topo, dofs, lo, hi, npa=NPA):
+    """P [n, 3 npa^3] of the edges `dofs` on the npa x npa x npa lattice of the
+    box [lo, hi] (npa = 4: the network's 192 coefficients)."""
     xa = topo.xyz[topo.edges[dofs, 0]]
     xb = topo.xyz[topo.edges[dofs, 1]]
     t = xb - xa
     sq, wq = np.polynomial.legendre.leggauss(3)
     sq = 0.5 * (sq + 1.0)
     wq = 0.5 * wq
-    P = np.zeros((len(dofs), NCOARSE))
-    span = (hi - lo) / (NPA - 1)
+    nnode = npa ** 3
+    P = np.zeros((len(dofs), 3 * nnode))
+    span = (hi - lo) / (npa - 1)
     for s, w in zip(sq, wq):
         x = xa + s * t
-        xi = (x - lo) / span                                   # [n, 3] in [0, 3]
-        psi = np.maximum(0.0, 1.0 - np.abs(xi[:, :, None] - np.arange(NPA)[None, None, :]))  # [n,3,4]
+        xi = (x - lo) / span                                   # [n, 3] in [0, npa - 1]
+        psi = np.maximum(0.0, 1.0 - np.abs(xi[:, :, None] - np.arange(npa)[None, None, :]))  # [n,3,npa]
         phi = (psi[:, 0, :, None, None] * psi[:, 1, None, :, None] * psi[:, 2, None, None, :])  # [n,a,b,c]
-        phi = phi.transpose(0, 3, 2, 1).reshape(len(dofs), NNODE)   # node = a + 4b + 16c
-        P += w * (phi[:, :, None] * t[:, None, :]).reshape(len(dofs), NCOARSE)
+        phi = phi.transpose(0, 3, 2, 1).reshape(len(dofs), nnode)   # node = a + npa b + npa^2 c
+        P += w * (phi[:, :, None] * t[:, None, :]).reshape(len(dofs), 3 * nnode)
     return P
 
 
 class Coarse:
-    """Per-subdomain lattices, prolongations and least-squares operators."""
+    """Per-subdomain lattices, prolongations and least-squares operators
+    (npa nodes per axis; the network uses npa = 4)."""
 
-    def __init__(self, dec):
+    def __init__(self, dec, npa=NPA):
         self.dec = dec
+        self.ncoarse = 3 * npa ** 3
         topo = dec.topo
         self.P, self.G = [], []
         for i in range(dec.nsub):
             lo, hi = subdomain_box(topo, dec.tets[i])
-            P = lattice_prolongation(topo, dec.dofs[i], lo, hi)
+            P = lattice_prolongation(topo, dec.dofs[i], lo, hi, npa)
             PDP = P.T @ (dec.D[i][:, None] * P)
-            lam = 1e-6 * np.trace(PDP) / NCOARSE
+            lam = 1e-6 * np.trace(PDP) / self.ncoarse
             self.P.append(P)
-            self.G.append(np.linalg.inv(PDP + lam * np.eye(NCOARSE)))
+            self.G.append(np.linalg.inv(PDP + lam * np.eye(self.ncoarse)))
         nb = [dec.neighbours(i) for i in range(dec.nsub)]
         self.neighbours = nb
 
@@ -178,7 +189,7 @@ class Coarse:
         s = self.scale(v)
         q = np.zeros(v.shape, dtype=np.complex128)
         for i in range(self.dec.nsub):
-            ci = c[:, i, :NCOARSE] + 1j * c[:, i, NCOARSE:]            # [nrhs, 192]
+            ci = c[:, i, :self.ncoarse] + 1j * c[:, i, self.ncoarse:]  # [nrhs, ncoarse]
             q[self.dec.dofs[i]] += self.dec.D[i][:, None] * (self.P[i] @ ci.T)
         return q * s[None, :]
 
@@ -205,23 +216,35 @@ def neighbour_mean_T(g, nbrs):
     return out
 
 
+def dense(h, W, b, use_bf16=True):
+    """Pre-activation of one MLP layer: W h + b over the last axis, the
+    operands of the product rounded to bf16 when use_bf16."""
+    r = bf16 if use_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    return r(h) @ r(W).T + b
+
+
+def message_pass(h, nbrs, Ws, Wn, b, use_bf16=True):
+    """Pre-activation of one message-passing layer: Ws h_i + Wn mean_{j in N(i)} h_j + b,
+    and the neighbour mean it used."""
+    r = bf16 if use_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    m = neighbour_mean(h, nbrs)
+    return r(h) @ r(Ws).T + r(m) @ r(Wn).T + b, m
+
+
 def forward(theta, X, nbrs, use_bf16=True):
     """Network outputs [G, nsub, 384] for inputs X [G, nsub, 384], and a cache."""
     p = unflatten(theta)
-    r = bf16 if use_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     cache = {"X": X}
     h = X
     for l in (1, 2, 3, 4):
-        z = r(h) @ r(p[f"W{l}"]).T + p[f"b{l}"]
+        z = dense(h, p[f"W{l}"], p[f"b{l}"], use_bf16)
         cache[f"in{l}"], cache[f"z{l}"] = h, z
         h = gelu(z)
     cache["h4"] = h
-    m4 = neighbour_mean(h, nbrs)
-    z5 = r(h) @ r(p["Ws1"]).T + r(m4) @ r(p["Wn1"]).T + p["b5"]
+    z5, m4 = message_pass(h, nbrs, p["Ws1"], p["Wn1"], p["b5"], use_bf16)
     cache["m4"], cache["z5"] = m4, z5
     h5 = gelu(z5)
-    m5 = neighbour_mean(h5, nbrs)
-    out = r(h5) @ r(p["Ws2"]).T + r(m5) @ r(p["Wn2"]).T + p["b6"]
+    out, m5 = message_pass(h5, nbrs, p["Ws2"], p["Wn2"], p["b6"], use_bf16)
     cache["h5"], cache["m5"] = h5, m5
     return out, cache
 
@@ -264,3 +287,21 @@ def adam_step(theta, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** t)
     vh = v / (1 - b2 ** t)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# --------------------------------------------------------------------------
+# use inside FGMRES
+# --------------------------------------------------------------------------
+
+def theta_combination(A, v, z1, q):
+    """Preconditioned block z = z1 + theta_j q_j with one complex weight per
+    column j minimising ||v_j - A z_j||_2 (least squares in the one unknown
+    theta_j: theta_j = (A q_j)^H (v_j - A z1_j) / ||A q_j||^2, 0 when A q_j = 0).
+    z1 is the one-level ORAS output and q the learned correction; with the
+    weight the learned term can only lower that local residual."""
+    t = v - A @ z1
+    aq = A @ q
+    nrm2 = np.sum(np.abs(aq) ** 2, axis=0)
+    dot = np.sum(aq.conj() * t, axis=0)
+    theta = np.where(nrm2 > 0, dot / np.where(nrm2 > 0, nrm2, 1.0), 0.0)
+    return z1 + theta[None, :] * q, theta

@@ -64,7 +64,14 @@ class Port(ct.Structure):
 
 class SolveInfo(ct.Structure):
     _fields_ = [("iters", ct.c_void_p), ("relres", ct.c_void_p), ("iters_max", ct.c_int32),
-                ("cycles", ct.c_int32), ("t_iter", ct.c_double), ("fallback", ct.c_int32)]
+                ("cycles", ct.c_int32), ("t_iter", ct.c_double), ("fallback", ct.c_int32),
+                ("t_assemble", ct.c_double), ("t_setup", ct.c_double), ("t_lu", ct.c_double)]
+
+
+def _info_dict(info, iters, relres, rc):
+    return {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
+            "t_iter": info.t_iter, "converged": rc == MX_OK, "fallback": info.fallback,
+            "t_assemble": info.t_assemble, "t_setup": info.t_setup, "t_lu": info.t_lu}
 
 
 class Sizes(ct.Structure):
@@ -94,7 +101,7 @@ def lib():
         L = ct.CDLL(LIB_PATH)
         vp, i32, dbl = ct.c_void_p, ct.c_int32, ct.c_double
         sig = {
-            "mx_create": [ct.POINTER(vp), ct.c_int],
+            "mx_create": [ct.POINTER(vp), ct.c_int, vp],
             "mx_destroy": [vp],
             "mx_assemble": [vp, ct.POINTER(Mesh), vp, ct.c_int, dbl, c128],
             "mx_setup_schwarz": [vp, i32, i32, ct.POINTER(SchwarzOpts)],
@@ -173,9 +180,11 @@ def _sources(pos, mom):
 class Context:
     """One solver context on one GPU (wraps mx_create / mx_destroy)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, stream=None):
+        """stream: integer HIP stream handle (e.g. torch's Stream.cuda_stream)
+        the context runs on; None gives it a stream of its own."""
         h = ct.c_void_p()
-        _check(lib().mx_create(ct.byref(h), device))
+        _check(lib().mx_create(ct.byref(h), device, ct.c_void_p(stream) if stream else None))
         self._h = h
         self.nports = 0
         self.ne = 0
@@ -276,12 +285,11 @@ class Context:
             S = np.zeros((nrx, ntx), dtype=np.complex128)
         iters = np.zeros(ntx, dtype=np.int32)
         relres = np.zeros(ntx, dtype=np.float64)
-        info = SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        info = SolveInfo(iters.ctypes.data, relres.ctypes.data)
         rc = lib().mx_solve(self._h, ct.byref(tx), ct.byref(rxs) if rxs is not None else None, float(rtol),
                             _ptr(E), _ptr(S), ct.byref(info))
         _check(rc, allow=(MX_ENOTCONV,))
-        return E, S, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
-                      "t_iter": info.t_iter, "converged": rc == MX_OK, "fallback": info.fallback}
+        return E, S, _info_dict(info, iters, relres, rc)
 
     def set_ports(self, ports, pec=True):
         """Waveguide ports (objects with centre, normal, u, a, b, eps) and, with
@@ -306,11 +314,10 @@ class Context:
             S = np.zeros((npt, npt), dtype=np.complex128)
         iters = np.zeros(npt, dtype=np.int32)
         relres = np.zeros(npt, dtype=np.float64)
-        info = SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        info = SolveInfo(iters.ctypes.data, relres.ctypes.data)
         rc = lib().mx_solve_ports(self._h, float(rtol), _ptr(E), _ptr(S), ct.byref(info))
         _check(rc, allow=(MX_ENOTCONV,))
-        return E, S, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
-                      "t_iter": info.t_iter, "converged": rc == MX_OK, "fallback": info.fallback}
+        return E, S, _info_dict(info, iters, relres, rc)
 
     def gradient(self, S_meas, w, alpha, grad=None):
         """Cost J and complex gradient dJ/dRe eps + j dJ/dIm eps (per vertex)
@@ -322,7 +329,7 @@ class Context:
         ntx = S_meas.shape[1]
         iters = np.zeros(ntx, dtype=np.int32)
         relres = np.zeros(ntx, dtype=np.float64)
-        info = SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        info = SolveInfo(iters.ctypes.data, relres.ctypes.data)
         J = ct.c_double(0.0)
         rc = lib().mx_gradient(self._h, _ptr(S_meas), _ptr(w), float(alpha), _ptr(grad), ct.byref(J), ct.byref(info))
         _check(rc, allow=(MX_ENOTCONV,))
@@ -337,11 +344,10 @@ class Context:
             x = np.zeros((self.ne, nrhs), dtype=np.complex128)
         iters = np.zeros(nrhs, dtype=np.int32)
         relres = np.zeros(nrhs, dtype=np.float64)
-        info = SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        info = SolveInfo(iters.ctypes.data, relres.ctypes.data)
         rc = lib().mx_solve_rhs(self._h, _ptr(b), nrhs, float(rtol), _ptr(x), ct.byref(info))
         _check(rc, allow=(MX_ENOTCONV,))
-        return x, {"iters": iters, "relres": relres, "iters_max": info.iters_max, "cycles": info.cycles,
-                   "t_iter": info.t_iter, "converged": rc == MX_OK, "fallback": info.fallback}
+        return x, _info_dict(info, iters, relres, rc)
 
     def apply_operator(self, X, Y=None):
         X2 = X if _is_torch(X) else np.ascontiguousarray(X, dtype=np.complex128)

@@ -240,6 +240,9 @@ struct mx_ctx {
   int precision = MX_PREC_C128;
   bool local_ready = false, factored = false;
   int restart = 30, maxit = 2000;
+  // wall time of the last mx_assemble / mx_setup_schwarz, device time of its LU
+  double t_assemble = 0, t_setup = 0, t_lu = 0;
+  hipEvent_t ev_lu[2] = {nullptr, nullptr};
   // sources
   SourceSet tx, rx;
   DBuf<int32_t> s_edge, s_col, r_edge;
@@ -1134,6 +1137,9 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x
     info->cycles = cycles;
     info->fallback = 0;
     info->t_iter = std::chrono::duration<double>(t1 - t0).count();
+    info->t_assemble = c->t_assemble;
+    info->t_setup = c->t_setup;
+    info->t_lu = c->t_lu;
   }
   return rc;
 }
@@ -1372,6 +1378,10 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
       if (learned_first && c->coarse_off_now) break;  // hand over to block FGMRES
     }
     if (ksteps < 0) {
+      // the cycle is dropped with x unchanged; the judged steps used r as
+      // scratch (v - A z), so the true residual b - A x is formed again
+      CK(spmm(c, c->x.p, c->r.p, nrhs));
+      launch_bminus(s, blk, c->b.p, c->r.p);
       CK(true_residual());
       continue;
     }
@@ -1409,6 +1419,9 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
     info->cycles = cycles;
     info->fallback = fallback ? fallback : (block_fallback ? 4 : 0);
     info->t_iter = std::chrono::duration<double>(t1 - t0).count();
+    info->t_assemble = c->t_assemble;
+    info->t_setup = c->t_setup;
+    info->t_lu = c->t_lu;
   }
   return rc;
 }
@@ -1737,7 +1750,7 @@ extern "C" {
 
 const char* mx_last_error(void) { return g_err.c_str(); }
 
-int mx_create(mx_ctx** out, int device) {
+int mx_create(mx_ctx** out, int device, void* hip_stream) {
   if (!out) return set_err(MX_EINVAL, "out is NULL");
   *out = nullptr;
   int ndev = 0;
@@ -1747,9 +1760,14 @@ int mx_create(mx_ctx** out, int device) {
   c->device = device;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
-  c->stream = c->own_stream;
+  if (e == hipSuccess) e = hipEventCreate(&c->ev_lu[0]);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev_lu[1]);
+  c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
   c->prof.stream = &c->stream;
   if (e != hipSuccess) {
+    for (hipEvent_t ev : c->ev_lu)
+      if (ev) (void)hipEventDestroy(ev);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
     return hip_fail(e, "hipStreamCreate", __FILE__, __LINE__);
   }
@@ -1767,6 +1785,8 @@ int mx_destroy(mx_ctx* c) {
   if (c->hb) (void)hipHostFree(c->hb);
   c->drop_graphs();
   c->prof.reset();
+  for (hipEvent_t ev : c->ev_lu)
+    if (ev) (void)hipEventDestroy(ev);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
   return MX_OK;
@@ -1839,6 +1859,7 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
   if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return set_err(MX_EINVAL, "frequency must be positive");
   if (!std::isfinite(eps_b.re) || !std::isfinite(eps_b.im)) return set_err(MX_EINVAL, "non-finite eps_b");
   CK(use_device(c));
+  const auto t_start = std::chrono::steady_clock::now();
   if (mesh) {
     Topology T;
     std::string err = build_topology(mesh->nv, mesh->nt, mesh->xyz, mesh->tet, T);
@@ -1897,6 +1918,7 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
   c->assembled = true;
   c->local_ready = c->factored = false;
   c->have_forward = false;
+  c->t_assemble = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return MX_OK;
 }
 
@@ -1907,6 +1929,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
   if (opts) o = *opts;
   if (o.precision != MX_PREC_C128 && o.precision != MX_PREC_C64) return set_err(MX_EINVAL, "bad precision");
   CK(use_device(c));
+  const auto t_start = std::chrono::steady_clock::now();
   c->restart = o.restart > 0 ? o.restart : 30;
   c->maxit = o.maxit > 0 ? o.maxit : 2000;
   if (!c->have_dec || c->dec.nsub != nsub || c->dec.overlap != overlap) {
@@ -1999,6 +2022,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
   if (o.factor) {
     hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((D.nsub + 255) / 256)), dim3(256), 0, c->stream, D.nsub,
                        c->status.p);
+    MX_HIP_CHECK(hipEventRecord(c->ev_lu[0], c->stream));
     if (o.precision == MX_PREC_C64)
       launch_lu<float>(c->stream, (float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, &c->prof);
@@ -2009,6 +2033,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     launch_perm(c->stream, D.nsub, c->Npad.p, c->vec_off.p, c->dof_ptr.p, c->dofs.p, c->piv.p, c->perm.p,
                 c->rowsrc.p);
     c->prof.end(K_LU_INV);
+    MX_HIP_CHECK(hipEventRecord(c->ev_lu[1], c->stream));
     MX_HIP_CHECK(hipGetLastError());
     std::vector<int32_t> st(D.nsub);
     MX_HIP_CHECK(hipMemcpyAsync(st.data(), c->status.p, D.nsub * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
@@ -2017,11 +2042,17 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
       if (st[i] != 0)
         return set_err(MX_EPIVOT, "zero pivot in subdomain " + std::to_string(i) + " at column " +
                                       std::to_string(st[i] - 1));
+    float lu_ms = 0;
+    MX_HIP_CHECK(hipEventElapsedTime(&lu_ms, c->ev_lu[0], c->ev_lu[1]));
+    c->t_lu = 1e-3 * lu_ms;
     c->factored = true;
+  } else {
+    c->t_lu = 0;
   }
   c->coarse_use = o.coarse != 0;
   if (c->coarse_use && !c->coarse_geom) CK(coarse_prepare(c));
   CK(sync(c));
+  c->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return MX_OK;
 }
 

@@ -95,3 +95,85 @@ def test_limits_are_errors():
         assert e.value.code == mx.MX_EINVAL
     finally:
         ctx.close()
+
+
+def test_mesh_errors_and_orientation():
+    """A zero-volume tetrahedron and a frequency that is not positive are
+    MX_EINVAL; a tetrahedron given with the opposite orientation (two vertex
+    ids swapped) yields bitwise the same operator values."""
+    print("[case] edges: degenerate / inverted tetrahedra, k0 = 0", flush=True)
+    xyz, tet = workload.kuhn_cube(3, 0.1)
+    eps = np.full(len(tet), workload.eps_r(44.0, 0.6, 1e9))
+    ctx = mx.Context(0)
+    try:
+        ctx.assemble(xyz, tet, eps, 0, 1e9, eps[0])
+        v_ref = ctx.matrix_values()
+        flipped = tet.copy()
+        flipped[::2, [0, 1]] = flipped[::2, [1, 0]]          # every other tet inverted
+        ctx.assemble(xyz, flipped, eps, 0, 1e9, eps[0])
+        assert np.array_equal(ctx.matrix_values(), v_ref)
+        bad = tet.copy()
+        bad[5] = [bad[5][0], bad[5][1], bad[5][2], bad[5][2]]  # repeated vertex
+        with pytest.raises(mx.MxError) as e:
+            ctx.assemble(xyz, bad, eps, 0, 1e9, eps[0])
+        assert e.value.code == mx.MX_EINVAL
+        flat = xyz.copy()
+        flat[:, 2] = 0.0                                      # every tetrahedron has zero volume
+        with pytest.raises(mx.MxError) as e:
+            ctx.assemble(flat, tet, eps, 0, 1e9, eps[0])
+        assert e.value.code == mx.MX_EINVAL
+        for f in (0.0, -1e9, float("nan")):
+            with pytest.raises(mx.MxError) as e:
+                ctx.assemble(xyz, tet, eps, 0, f, eps[0])
+            assert e.value.code == mx.MX_EINVAL
+    finally:
+        ctx.close()
+
+
+def test_pivot_error_and_timings():
+    """Complex64 factors of a permittivity whose mass term exceeds the
+    complex64 range: the first pivot is infinite, the elimination turns the
+    next column into non-finite values and the factorisation reports
+    MX_EPIVOT; a solve afterwards is MX_ESTATE. A normal set-up then reports
+    its assembly, set-up and factorisation times in the solve diagnostics."""
+    print("[case] edges: MX_EPIVOT on complex64 overflow", flush=True)
+    xyz, tet = workload.kuhn_cube(4, 0.1)
+    ctx = mx.Context(0)
+    try:
+        huge = np.full(len(tet), 1e50 + 0j)   # k0^2 eps |T| / 120 ~ 1e43 > FLT_MAX
+        ctx.assemble(xyz, tet, huge, 0, 1e9, 44.0)
+        with pytest.raises(mx.MxError) as e:
+            ctx.setup_schwarz(8, 1, precision=mx.MX_PREC_C64)
+        assert e.value.code == mx.MX_EPIVOT
+        with pytest.raises(mx.MxError) as e:
+            ctx.solve_rhs(np.ones((ctx.ne, 1), np.complex128))
+        assert e.value.code == mx.MX_ESTATE
+        eps = np.full(len(tet), workload.eps_r(44.0, 0.6, 1e9))
+        ctx.assemble(xyz, tet, eps, 0, 1e9, eps[0])
+        ctx.setup_schwarz(8, 1, precision=mx.MX_PREC_C64)
+        _, info = ctx.solve_rhs(workload.seeded_complex((ctx.ne, 2), 3), rtol=1e-8)
+        assert info["converged"]
+        assert info["t_assemble"] > 0 and info["t_setup"] > 0 and 0 < info["t_lu"] <= info["t_setup"]
+    finally:
+        ctx.close()
+
+
+def test_context_on_caller_stream():
+    """A context created on a caller stream (torch's) runs there and gives
+    the same answer as one on its own stream."""
+    torch = pytest.importorskip("torch")
+    print("[case] edges: context on a torch stream", flush=True)
+    p = workload.cube_problem(n=5, nsub=8, overlap=1, nsrc=3)
+    st = torch.cuda.Stream()
+    outs = []
+    for stream in (None, st.cuda_stream):
+        ctx = mx.Context(0, stream=stream)
+        try:
+            ctx.assemble(p.xyz, p.tet, p.eps, p.eps_kind, p.freq, p.eps_b)
+            ctx.setup_schwarz(p.nsub, p.overlap)
+            E, S, info = ctx.solve(p.src_pos, p.src_mom, rtol=1e-10)
+            assert info["converged"]
+            outs.append(E)
+        finally:
+            ctx.close()
+    assert np.array_equal(outs[0], outs[1])

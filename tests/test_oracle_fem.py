@@ -271,3 +271,85 @@ def test_plane_wave_convergence(eps, ns):
     for e1, e2 in zip(errs, errs[1:]):
         assert e1 / e2 >= 1.8, errs
     assert errs[-1] < (0.2 if abs(eps) < 10 else 0.5)
+
+
+# -- point dipole: closed-form field in a homogeneous lossy medium ----------
+
+def _dipole_fields(x, xs, p, k, omu):
+    """E and curl E of J = p delta(x - xs) in a homogeneous medium (exp(+j w t)):
+    E = -j w mu0 (I + grad grad / k^2) g p,  g = exp(-j k r) / (4 pi r),
+    curl E = -j w mu0 grad g x p (written out from the dyadic Green's function)."""
+    d = x - xs[None]
+    r = np.linalg.norm(d, axis=1)
+    rh = d / r[:, None]
+    kr = k * r
+    g = np.exp(-1j * kr) / (4 * np.pi * r)
+    a = 1 - 1j / kr - 1 / kr ** 2
+    b = -1 + 3j / kr + 3 / kr ** 2
+    E = -1j * omu * g[:, None] * (a[:, None] * p[None] + (b * (rh @ p))[:, None] * rh)
+    gradg = (g * (-1j * k - 1 / r))[:, None] * rh
+    return E, -1j * omu * np.cross(gradg, p[None])
+
+
+def _dipole_error(n, eps=4 - 1j, freq=1e9, rmin=0.03):
+    """Relative L2 error, outside the ball |x - xs| < rmin, of the FE field
+    with the oracle's dipole right-hand side and the exact impedance data of
+    the dipole field on the cube faces; column 1 has the interior source
+    doubled (a wrong amplitude, the control)."""
+    xyz, tet = workload.kuhn_cube(n, 0.1)
+    t = fem.Topology(xyz, tet)
+    xs = np.array([0.0513, 0.0497, 0.0502])
+    p = np.array([0.3, -0.2, 1.0])
+    k = fem.wavenumber(fem.k0_of(freq), eps)
+    omu = fem.omega_mu0(freq)
+    src = fem.dipole_rhs(t, xs[None], p[None].astype(complex), freq)[:, 0]
+    bnd = np.zeros(t.ne, dtype=complex)
+    lam2, w2 = Q.tri_rule(5)
+    for f in range(len(t.bface_tet)):
+        Xt = t.xyz[t.tet_sorted[t.bface_tet[f]]]
+        lf = fem.LOCAL_FACES[t.bface_local[f]]
+        P = Xt[list(lf)]
+        nrm = np.cross(P[1] - P[0], P[2] - P[0])
+        area = 0.5 * np.linalg.norm(nrm)
+        nrm /= np.linalg.norm(nrm)
+        opp = [v for v in range(4) if v not in lf][0]
+        if (Xt[opp] - P[0]) @ nrm > 0:
+            nrm = -nrm
+        pts = lam2 @ P
+        Ev, cE = _dipole_fields(pts, xs, p, k, omu)
+        g = np.cross(cE, nrm[None]) + 1j * k * np.cross(nrm[None], np.cross(Ev, nrm[None]))
+        for j, (a, b) in enumerate(fem.FACE_EDGES):
+            N = Q.whitney(Xt, pts, lf[a], lf[b])
+            bnd[t.bface_edges[f, j]] += area * (w2 * (g * N).sum(1)).sum()
+    A = fem.assemble(t, np.full(t.nt, eps), 0, freq, eps)
+    U = fem.solve_direct(A, np.stack([src + bnd, 2 * src + bnd], axis=1))
+    lam, w = Q.tet_rule(3)
+    X = t.xyz[t.tet_sorted]
+    gr = Q.bary_grads(X)
+    vol = np.abs(np.linalg.det(X[:, 1:] - X[:, :1])) / 6
+    keep = np.linalg.norm(X.mean(1) - xs, axis=1) > rmin
+    pts = np.einsum("qk,tkd->tqd", lam, X)
+    Ex = _dipole_fields(pts.reshape(-1, 3), xs, p, k, omu)[0].reshape(pts.shape)
+    ref = np.sqrt((vol[:, None] * w[None] * (np.abs(Ex) ** 2).sum(-1))[keep].sum())
+    errs = []
+    for c in range(2):
+        Eh = np.zeros(pts.shape, dtype=complex)
+        for le, (a, b) in enumerate(fem.LOCAL_EDGES):
+            N = lam[None, :, a, None] * gr[:, None, b] - lam[None, :, b, None] * gr[:, None, a]
+            Eh += U[t.t2e[:, le], c][:, None, None] * N
+        errs.append(np.sqrt((vol[:, None] * w[None] * (np.abs(Eh - Ex) ** 2).sum(-1))[keep].sum()) / ref)
+    return errs
+
+
+def test_dipole_matches_closed_form():
+    """The dipole right-hand side -j w mu0 p.N_e(x_s) reproduces the
+    closed-form field of a point dipole: the error away from the source falls
+    with h (measured 0.75, 0.42, 0.29 at n = 8, 12, 16), while a doubled
+    amplitude (the control) stays near |1 - 2| = 1; a wrong sign, factor, or
+    phase convention would likewise leave an O(1) error."""
+    errs = [_dipole_error(n) for n in (8, 12, 16)]
+    good = [e[0] for e in errs]
+    for e1, e2 in zip(good, good[1:]):
+        assert e1 / e2 >= 1.3, good
+    assert good[-1] < 0.35, good
+    assert errs[-1][1] > 0.7, errs

@@ -96,3 +96,27 @@ def test_targets_recover_coarse_error(small):
         assert np.linalg.norm(sw * (rec - ui)) <= 1e-4 * np.linalg.norm(sw * ui)
     q = co.correction(c, r)
     assert np.linalg.norm(q[:, 0] - u[:, 0]) <= 1e-4 * np.linalg.norm(u)
+
+
+def test_theta_combination_is_the_least_squares_weight():
+    """theta_j minimises ||v_j - A(z1_j + theta q_j)||: the residual it leaves is
+    orthogonal to A q_j, never exceeds that of theta = 0, and any perturbed
+    weight does worse; a zero correction gets theta = 0."""
+    rng = np.random.default_rng(21)
+    n = 60
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 8 * np.eye(n)
+    v = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    z1 = np.linalg.solve(A + 0.3 * rng.standard_normal((n, n)), v)
+    q = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    q[:, 2] = 0
+    z, th = learned.theta_combination(A, v, z1, q)
+    assert th[2] == 0 and np.array_equal(z[:, 2], z1[:, 2])
+    res = v - A @ z
+    for j in range(2):
+        aq = A @ q[:, j]
+        assert abs(np.vdot(aq, res[:, j])) <= 1e-12 * np.linalg.norm(aq) * np.linalg.norm(res[:, j])
+        r0 = np.linalg.norm(v[:, j] - A @ z1[:, j])
+        r1 = np.linalg.norm(res[:, j])
+        assert r1 <= r0
+        for d in (1e-3, -1e-3, 1e-3j, -1e-3j):
+            assert np.linalg.norm(v[:, j] - A @ (z1[:, j] + (th[j] + d) * q[:, j])) > r1

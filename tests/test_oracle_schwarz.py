@@ -133,3 +133,35 @@ def test_givens_zeroes():
         c, s = krylov.givens(a, b)
         assert abs(-np.conj(s) * a + c * b) < 1e-15
         assert abs(c * c + abs(s) ** 2 - 1) < 1e-15
+
+
+def test_interface_faces_brute_force():
+    """Every face of an overlapping subdomain is classified by looping over
+    Python sets of vertex triples: a face met by one tetrahedron of the whole
+    mesh is outer boundary, a face met by one tetrahedron inside the subdomain
+    and one outside is artificial interface; the oracle's lists must be
+    exactly these sets (none missing, none extra, no face twice)."""
+    p = workload.chamber_problem(c=0.03, nsub=8, overlap=1, nsrc=2)
+    t = fem.Topology(p.xyz, p.tet)
+    dec = schwarz.Decomposition(t, 8, 1)
+    owners = {}
+    for k, tv in enumerate(t.tet_sorted):
+        for lf in fem.LOCAL_FACES:
+            owners.setdefault(tuple(int(tv[a]) for a in lf), []).append(k)
+    for i in range(dec.nsub):
+        inside = set(dec.tets[i].tolist())
+        want_if, want_out = set(), set()
+        for k in inside:
+            for lf in fem.LOCAL_FACES:
+                f = tuple(int(t.tet_sorted[k][a]) for a in lf)
+                own = owners[f]
+                if len(own) == 1:
+                    want_out.add((k, f))
+                elif sum(o in inside for o in own) == 1:
+                    want_if.add((k, f))
+        (it, il), (ot, ol) = dec.interface_faces(i)
+        got_if = [(int(k), tuple(int(t.tet_sorted[k][a]) for a in fem.LOCAL_FACES[l])) for k, l in zip(it, il)]
+        got_out = [(int(k), tuple(int(t.tet_sorted[k][a]) for a in fem.LOCAL_FACES[l])) for k, l in zip(ot, ol)]
+        assert len(got_if) == len(set(got_if)) and set(got_if) == want_if, i
+        assert len(got_out) == len(set(got_out)) and set(got_out) == want_out, i
+        assert len(want_if) > 0
