@@ -315,7 +315,10 @@ int mx_solve_rhs(mx_ctx* ctx, const mx_c128* b, int32_t nrhs, double rtol,
 int mx_apply_operator(mx_ctx* ctx, const mx_c128* X, mx_c128* Y, int32_t nrhs);
 
 /* Z = M^{-1} X = sum_i R_i^T D_i B_i^{-1} R_i X (one ORAS application;
- * complex64 factors round R_i X to complex64).  X, Z host or device. */
+ * complex64 factors round R_i X to complex64).  X, Z host or device.
+ * With the learned term set up (opts.coarse = 1 and weights), Z is the
+ * preconditioner FGMRES applies: Z_j = M^{-1} X_j + theta_j q_j, q the
+ * learned correction and theta_j minimising ||X_j - A Z_j||_2. */
 int mx_apply_preconditioner(mx_ctx* ctx, const mx_c128* X, mx_c128* Z, int32_t nrhs);
 
 /* Sizes of the current state (zeros for parts not yet built). */
@@ -360,6 +363,8 @@ int mx_point_functionals(mx_ctx* ctx, const mx_sources* pts, mx_c128* R);
 int64_t mx_coarse_num_params(void);
 /* Random initial weights (seeded; normal, 1/fan_in variance, output layers x0.1). */
 int mx_coarse_init(mx_ctx* ctx, uint64_t seed);
+/* Set the parameters (n = mx_coarse_num_params()) and scales; resets the
+ * Adam moments and step count. */
 int mx_coarse_set_weights(mx_ctx* ctx, const float* theta, int64_t n, double in_scale, double out_scale);
 int mx_coarse_get_weights(mx_ctx* ctx, float* theta, int64_t n, double* in_scale, double* out_scale);
 /* Pooled features X [nrhs][nsub][384] (host) of v [ne][nrhs] (host or device). */
@@ -367,8 +372,17 @@ int mx_coarse_features(mx_ctx* ctx, const mx_c128* v, int32_t nrhs, float* X);
 /* Network outputs out [ngraph][nsub][384] for inputs X [ngraph][nsub][384]
  * (host; scales not applied). */
 int mx_coarse_forward(mx_ctx* ctx, const float* X, int32_t ngraph, float* out);
+/* Network outputs as mx_coarse_forward, and the hidden activations
+ * H [5][ngraph][nsub][256] (host): the four MLP layers and the first
+ * message-passing layer, after GELU. */
+int mx_coarse_hidden(mx_ctx* ctx, const float* X, int32_t ngraph, float* H, float* out);
 /* Mean squared error against Y and its parameter gradient (host buffers). */
 int mx_coarse_loss_grad(mx_ctx* ctx, const float* X, const float* Y, int32_t ngraph, double* loss, float* grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) of the
+ * FP32 master weights with the given gradient grad [n] (host or device,
+ * n = mx_coarse_num_params()), e.g. a gradient averaged over several
+ * processes; mx_coarse_train uses the same update. */
+int mx_coarse_adam_step(mx_ctx* ctx, const float* grad, int64_t n, double lr);
 /* Training data from the plain solver on the current operator: solves the
  * transmitters to rtol_exact, then re-runs with restart length snap_every and
  * records, at every restart, the features of the residual r and the

@@ -25,7 +25,7 @@ EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_sol
            "mx_get_matrix_values", "mx_get_partition", "mx_get_local_matrix", "mx_point_functionals",
            "mx_set_stream", "mx_set_autotune", "mx_get_tuning", "mx_set_graphs", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_coarse_num_params", "mx_coarse_init",
            "mx_coarse_set_weights", "mx_coarse_get_weights", "mx_coarse_features", "mx_coarse_forward",
-           "mx_coarse_loss_grad", "mx_coarse_collect", "mx_coarse_clear", "mx_coarse_train", "mx_set_ports",
+           "mx_coarse_loss_grad", "mx_coarse_hidden", "mx_coarse_adam_step", "mx_coarse_collect", "mx_coarse_clear", "mx_coarse_train", "mx_set_ports",
            "mx_solve_ports", "mx_set_krylov", "mx_last_error"]
 
 KERNEL_CLASSES = ["lu_panel", "lu_rowpanel", "lu_update", "lu_inv", "trsm_lower", "trsm_upper", "spmm",
@@ -128,6 +128,8 @@ def lib():
             "mx_coarse_features": [vp, vp, i32, vp],
             "mx_coarse_forward": [vp, vp, i32, vp],
             "mx_coarse_loss_grad": [vp, vp, vp, i32, ct.POINTER(dbl), vp],
+            "mx_coarse_hidden": [vp, vp, i32, vp, vp],
+            "mx_coarse_adam_step": [vp, vp, ct.c_int64, dbl],
             "mx_coarse_collect": [vp, ct.POINTER(Sources), i32, i32, dbl, ct.POINTER(i32)],
             "mx_coarse_clear": [vp],
             "mx_coarse_train": [vp, i32, i32, dbl, ct.c_uint64, vp],
@@ -427,6 +429,19 @@ class Context:
         out = np.zeros_like(X)
         _check(lib().mx_coarse_forward(self._h, _ptr(X), X.shape[0], _ptr(out)))
         return out
+
+    def coarse_hidden(self, X):
+        """(H [5, G, nsub, 256], out [G, nsub, 384]): hidden activations of the
+        four MLP layers and the first message-passing layer, and the outputs."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        H = np.zeros((5,) + X.shape[:2] + (256,), np.float32)
+        out = np.zeros_like(X)
+        _check(lib().mx_coarse_hidden(self._h, _ptr(X), X.shape[0], _ptr(H), _ptr(out)))
+        return H, out
+
+    def coarse_adam_step(self, grad, lr):
+        g = grad if _is_torch(grad) else np.ascontiguousarray(grad, dtype=np.float32)
+        _check(lib().mx_coarse_adam_step(self._h, _ptr(g), int(np.prod(g.shape)), float(lr)))
 
     def coarse_loss_grad(self, X, Y):
         X = np.ascontiguousarray(X, dtype=np.float32)

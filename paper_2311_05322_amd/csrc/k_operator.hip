@@ -248,14 +248,21 @@ __global__ void k_gather_dense(int64_t n, const int64_t* __restrict__ dest, cons
 }
 
 template <typename C>
+__device__ inline C zero_value() {
+  C z;
+  z.x = 0;
+  z.y = 0;
+  return z;
+}
+template <>
+__device__ inline float zero_value<float>() {
+  return 0.f;
+}
+
+template <typename C>
 __global__ void k_fill_zero(int64_t n, C* __restrict__ out) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += stride) {
-    C z;
-    z.x = 0;
-    z.y = 0;
-    out[k] = z;
-  }
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += stride) out[k] = zero_value<C>();
 }
 
 // identity on the padded diagonal part of each dense subdomain matrix
@@ -538,6 +545,7 @@ void launch_fill_zero(hipStream_t s, int64_t n, C* out) {
 }
 template void launch_fill_zero<float2>(hipStream_t, int64_t, float2*);
 template void launch_fill_zero<double2>(hipStream_t, int64_t, double2*);
+template void launch_fill_zero<float>(hipStream_t, int64_t, float*);
 template <typename C>
 void launch_pad_identity(hipStream_t s, int32_t nsub, const int64_t* dof_ptr, const int32_t* Npad,
                          const int64_t* mat_off, C* A) {

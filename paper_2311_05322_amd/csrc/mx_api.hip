@@ -262,7 +262,7 @@ struct mx_ctx {
   bool coarse_off_now = false;   // disabled for the rest of the current solve (fallback)
   int coarse_fallbacks = 0;
   double sx = 1.0, sy = 1.0;     // input / output scales of the network
-  DBuf<double2> qv, aq, thdot;
+  DBuf<double2> qv, aq, tv, thdot;
   DBuf<double> thnrm, thtn;
   DBuf<char> xloc2;
   DBuf<float> cP, theta, gtheta, adam_m, adam_v, nbuf, gwork, dsX, dsY;
@@ -602,6 +602,45 @@ int spmm(mx_ctx* c, const double2* X, double2* Y, int nrhs) {
   c->prof.begin(K_SPMM);
   launch_spmm(c->stream, c->topo.ne, c->row_ptr.p, c->col.p, c->val.p, X, Y, nrhs, c->tune_spmm);
   c->prof.end(K_SPMM);
+  MX_HIP_CHECK(hipGetLastError());
+  return MX_OK;
+}
+
+bool learned_ready(const mx_ctx* c) { return c->coarse_use && c->coarse_geom && c->coarse_weights; }
+
+// buffers of precond_learned for nrhs columns
+int ensure_learned_ws(mx_ctx* c, int nrhs) {
+  const size_t blk = (size_t)c->topo.ne * nrhs;
+  CK(c->qv.alloc(blk));
+  CK(c->aq.alloc(blk));
+  CK(c->tv.alloc(blk));
+  CK(c->thdot.alloc(nrhs));
+  CK(c->thnrm.alloc(nrhs));
+  CK(c->thtn.alloc(nrhs));
+  CK(c->xloc2.alloc((size_t)c->dec.vec_off[c->dec.nsub] * nrhs * elem_bytes(c->precision)));
+  CK(c->xloc.alloc((size_t)c->dec.vec_off[c->dec.nsub] * nrhs * elem_bytes(c->precision)));
+  CK(c->dotpart.alloc((size_t)dot_blocks(c->topo.ne) * 8 * nrhs));
+  CK(c->normpart.alloc((size_t)dot_blocks(c->topo.ne) * nrhs));
+  return MX_OK;
+}
+
+// The preconditioner with the learned term as FGMRES uses it:
+// z = M^{-1} v + theta_j q_j, one weight per column minimising ||v_j - A z_j||
+// (theta_j = (A q_j)^H t_j / ||A q_j||^2 with t = v - A M^{-1} v), and
+// w = A z. Scratch: qv (q), aq (A q), tv (t); thdot / thnrm / thtn keep
+// (A q)^H t, ||A q|| and ||t|| per column for the judge.
+int precond_learned(mx_ctx* c, const double2* v, double2* z, double2* w, int nrhs) {
+  hipStream_t s = c->stream;
+  const int64_t ne = c->topo.ne;
+  const int64_t blk = ne * (int64_t)nrhs;
+  CK(apply_precond(c, v, z, nrhs, c->qv.p));
+  CK(spmm(c, z, w, nrhs));
+  CK(spmm(c, c->qv.p, c->aq.p, nrhs));
+  launch_sub(s, blk, v, w, c->tv.p);
+  launch_dot(s, ne, nrhs, c->aq.p, blk, 1, c->tv.p, c->dotpart.p, c->thdot.p);
+  launch_norm(s, ne, nrhs, c->aq.p, c->normpart.p, c->thnrm.p);
+  launch_norm(s, ne, nrhs, c->tv.p, c->normpart.p, c->thtn.p);
+  launch_theta_axpy(s, blk, nrhs, c->thdot.p, c->thnrm.p, c->qv.p, c->aq.p, z, w);
   MX_HIP_CHECK(hipGetLastError());
   return MX_OK;
 }
@@ -1188,18 +1227,13 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
   const bool coarse_on = c->coarse_use && c->coarse_geom && c->coarse_weights;
   if (coarse_on) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, 1, c->cflag.p);
-    CK(c->qv.alloc(blk));
-    CK(c->aq.alloc(blk));
-    CK(c->thdot.alloc(nrhs));
-    CK(c->thnrm.alloc(nrhs));
-    CK(c->xloc2.alloc((size_t)c->dec.vec_off[c->dec.nsub] * nrhs * elem_bytes(c->precision)));
+    CK(ensure_learned_ws(c, nrhs));
   }
   int fallback = 0;
   int judge_steps = 0;
   double judge_sum = 0;
   std::vector<double2> hj_dot(nrhs);
   std::vector<double> hj_aq(nrhs), hj_t(nrhs);
-  if (coarse_on) CK(c->thtn.alloc(nrhs));
   // Gram-Schmidt (twice), normalisation and the Givens update of step k
   auto arnoldi_tail = [&](int k) -> int {
     double2* w = c->V.p + (k + 1) * blk;
@@ -1317,14 +1351,7 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
       if (coarse_on && !c->coarse_off_now) {
         // plain ORAS judges the learned term: z = M^{-1} v + theta q with the
         // per-transmitter theta minimising ||v - A z||
-        CK(apply_precond(c, vk, zk, nrhs, c->qv.p));
-        CK(spmm(c, zk, w, nrhs));
-        CK(spmm(c, c->qv.p, c->aq.p, nrhs));
-        launch_sub(s, blk, vk, w, c->r.p);
-        launch_dot(s, ne, nrhs, c->aq.p, blk, 1, c->r.p, c->dotpart.p, c->thdot.p);
-        launch_norm(s, ne, nrhs, c->aq.p, c->normpart.p, c->thnrm.p);
-        launch_norm(s, ne, nrhs, c->r.p, c->normpart.p, c->thtn.p);
-        launch_theta_axpy(s, blk, nrhs, c->thdot.p, c->thnrm.p, c->qv.p, c->aq.p, zk, w);
+        CK(precond_learned(c, vk, zk, w, nrhs));
         judged = true;
         c->prof.begin(K_CGS);
         CK(arnoldi_tail(k));
@@ -1378,10 +1405,7 @@ int fgmres(mx_ctx* c, int nrhs, double rtol, mx_solve_info* info, const std::fun
       if (learned_first && c->coarse_off_now) break;  // hand over to block FGMRES
     }
     if (ksteps < 0) {
-      // the cycle is dropped with x unchanged; the judged steps used r as
-      // scratch (v - A z), so the true residual b - A x is formed again
-      CK(spmm(c, c->x.p, c->r.p, nrhs));
-      launch_bminus(s, blk, c->b.p, c->r.p);
+      // the cycle is dropped with x unchanged (r still holds b - A x)
       CK(true_residual());
       continue;
     }
@@ -2339,7 +2363,15 @@ int mx_apply_preconditioner(mx_ctx* c, const mx_c128* X, mx_c128* Zo, int32_t nr
   CK(zout.alloc((size_t)c->topo.ne * nrhs));
   CK(c->xloc.alloc((size_t)c->dec.vec_off[c->dec.nsub] * nrhs * elem_bytes(c->precision)));
   CK(copy_in(c, xin.p, X, bytes));
-  CK(apply_precond(c, xin.p, zout.p, nrhs));
+  if (learned_ready(c)) {
+    DBuf<double2> w;
+    CK(w.alloc((size_t)c->topo.ne * nrhs));
+    CK(ensure_learned_ws(c, nrhs));
+    c->coarse_off_now = false;
+    CK(precond_learned(c, xin.p, zout.p, w.p, nrhs));
+  } else {
+    CK(apply_precond(c, xin.p, zout.p, nrhs));
+  }
   CK(copy_out(c, Zo, zout.p, bytes));
   CK(sync(c));
   return MX_OK;
@@ -2457,8 +2489,24 @@ int mx_coarse_set_weights(mx_ctx* c, const float* theta, int64_t n, double in_sc
   CK(use_device(c));
   if (!c->coarse_weights) CK(mx_coarse_init(c, 0));
   MX_HIP_CHECK(hipMemcpyAsync(c->theta.p, theta, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  launch_fill_zero<float>(c->stream, NL.total, c->adam_m.p);
+  launch_fill_zero<float>(c->stream, NL.total, c->adam_v.p);
+  c->adam_t = 0;
   c->sx = in_scale;
   c->sy = out_scale;
+  MX_HIP_CHECK(hipGetLastError());
+  return sync(c);
+}
+int mx_coarse_adam_step(mx_ctx* c, const float* grad, int64_t n, double lr) {
+  if (!c || !grad) return set_err(MX_EINVAL, "NULL argument");
+  if (n != NL.total) return set_err(MX_EINVAL, "expected " + std::to_string(NL.total) + " gradient values");
+  if (!(lr > 0) || !std::isfinite(lr)) return set_err(MX_EINVAL, "lr must be positive");
+  if (!c->coarse_weights) return set_err(MX_ESTATE, "call mx_coarse_init or mx_coarse_set_weights first");
+  CK(use_device(c));
+  CK(copy_in(c, c->gtheta.p, grad, n * sizeof(float)));
+  launch_adam(c->stream, NL.total, c->theta.p, c->gtheta.p, c->adam_m.p, c->adam_v.p, (float)lr, 0.9f, 0.999f, 1e-8f,
+              ++c->adam_t);
+  MX_HIP_CHECK(hipGetLastError());
   return sync(c);
 }
 
@@ -2492,6 +2540,22 @@ int mx_coarse_features(mx_ctx* c, const mx_c128* v, int32_t nrhs, float* X) {
   return sync(c);
 }
 
+int mx_coarse_hidden(mx_ctx* c, const float* X, int32_t ngraph, float* H, float* out) {
+  if (!c || !X || !H || !out || ngraph <= 0) return set_err(MX_EINVAL, "bad arguments");
+  if (!c->have_dec || !c->coarse_geom || !c->coarse_weights) return set_err(MX_ESTATE, "needs coarse set-up and weights");
+  CK(use_device(c));
+  const int64_t rows = (int64_t)ngraph * c->dec.nsub;
+  NetBufs B;
+  CK(net_bufs(c, rows, B));
+  MX_HIP_CHECK(hipMemcpyAsync(B.X, X, rows * NIN * 4, hipMemcpyHostToDevice, c->stream));
+  net_forward(c, ngraph, B);
+  MX_HIP_CHECK(hipGetLastError());
+  const float* hs[5] = {B.H[0], B.H[1], B.H[2], B.H[3], B.H5};
+  for (int l = 0; l < 5; ++l)
+    MX_HIP_CHECK(hipMemcpyAsync(H + (size_t)l * rows * NW, hs[l], rows * NW * 4, hipMemcpyDeviceToHost, c->stream));
+  MX_HIP_CHECK(hipMemcpyAsync(out, B.OUT, rows * NIN * 4, hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
 int mx_coarse_forward(mx_ctx* c, const float* X, int32_t ngraph, float* out) {
   if (!c || !X || !out || ngraph <= 0) return set_err(MX_EINVAL, "bad arguments");
   if (!c->have_dec || !c->coarse_geom || !c->coarse_weights) return set_err(MX_ESTATE, "needs coarse set-up and weights");

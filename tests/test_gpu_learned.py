@@ -64,6 +64,97 @@ def test_network_forward_and_gradient(setup):
     assert np.linalg.norm(out - ref32) <= 0.05 * np.linalg.norm(ref32)
 
 
+def test_each_layer_matches_oracle(setup):
+    """Every layer of the GPU network against the oracle's layer applied to
+    the GPU's own input of that layer: both round the same operands to bf16,
+    the bf16 x bf16 products are exact in FP32, so the difference is the FP32
+    against FP64 accumulation of <= 512 terms (~1e-6). In the message-passing
+    layers the neighbour mean is formed in FP32 on the GPU and in FP64 in the
+    oracle before its bf16 rounding, so an element at a rounding boundary
+    can round the other way (probability ~2^-16 per element, effect one
+    operand ulp): there the max-norm bound is that of one flipped term."""
+    p, t, dec, ctx = setup
+    nb = [dec.neighbours(i) for i in range(dec.nsub)]
+    theta, _, _ = ctx.coarse_weights()
+    P = learned.unflatten(theta.astype(np.float64))
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((3, dec.nsub, 384)).astype(np.float32)
+    H, out = ctx.coarse_hidden(X)
+    H = H.astype(np.float64)
+    inp = X.astype(np.float64)
+    for l in range(4):
+        ref = learned.gelu(learned.dense(inp, P[f"W{l + 1}"], P[f"b{l + 1}"]))
+        assert np.abs(H[l] - ref).max() <= 1e-5 * np.abs(ref).max(), l
+        inp = H[l]
+    z5, _ = learned.message_pass(H[3], nb, P["Ws1"], P["Wn1"], P["b5"])
+    ref5 = learned.gelu(z5)
+    assert np.linalg.norm(H[4] - ref5) <= 1e-5 * np.linalg.norm(ref5)
+    assert np.abs(H[4] - ref5).max() <= 2e-3 * np.abs(ref5).max()
+    ref6, _ = learned.message_pass(H[4], nb, P["Ws2"], P["Wn2"], P["b6"])
+    assert np.linalg.norm(out - ref6) <= 1e-5 * np.linalg.norm(ref6)
+    assert np.abs(out - ref6).max() <= 2e-3 * np.abs(ref6).max()
+
+
+def test_learned_preconditioner_matches_oracle(setup):
+    """One application of the preconditioner with the learned term, element by
+    element: z = M^{-1} v + theta q, q = s sum_i R_i^T D_i P_i c_i, theta per
+    column from the oracle's least-squares weight, against oracle ORAS
+    (complex128 factors), the oracle's lattice prolongation and the same
+    network output c (computed by the GPU network on the GPU's features, which
+    is bitwise what the preconditioner computes inside). GPU P and c are FP32:
+    tolerance 1e-6 relative per column."""
+    p, t, dec, ctx = setup
+    theta, sx0, sy0 = ctx.coarse_weights()
+    sx, sy = 0.7, 1.3
+    ctx.coarse_set_weights(theta, sx, sy)
+    try:
+        ctx.setup_schwarz(16, 1, precision=mx.MX_PREC_C128, coarse=True)
+        v = workload.seeded_complex((t.ne, 5), 31)
+        z = ctx.apply_preconditioner(v)
+        X = ctx.coarse_features(v)
+        c = ctx.coarse_forward(X * np.float32(1.0 / sx)).astype(np.float64) * sy
+    finally:
+        ctx.coarse_set_weights(theta, sx0, sy0)
+        ctx.setup_schwarz(16, 1, precision=mx.MX_PREC_C64, coarse=True)
+    A = fem.assemble(t, p.eps, p.eps_kind, p.freq, p.eps_b).tocsr()
+    M = schwarz.ORAS(dec, p.eps, p.eps_kind, p.freq, p.eps_b)
+    co = learned.Coarse(dec)
+    z1 = M.apply(v)
+    q = co.correction(c, v)
+    zref, th = learned.theta_combination(A, v, z1, q)
+    assert np.all(np.abs(th) > 0)
+    err = np.linalg.norm(z - zref, axis=0) / np.linalg.norm(zref, axis=0)
+    assert err.max() <= 1e-6, err
+    # the learned part is really there: without it the difference is large
+    assert (np.linalg.norm(z - z1, axis=0) / np.linalg.norm(zref, axis=0)).min() > 1e-4
+
+
+def test_adam_step_matches_oracle(setup):
+    """Two Adam steps of the GPU's FP32 master weights against the oracle's
+    FP64 adam_step from the same weights and gradients."""
+    p, t, dec, ctx = setup
+    theta, sx, sy = ctx.coarse_weights()
+    rng = np.random.default_rng(8)
+    g1 = (rng.standard_normal(theta.size) * 1e-2).astype(np.float32)
+    g2 = (rng.standard_normal(theta.size) * 1e-3).astype(np.float32)
+    lr = 1e-3
+    try:
+        ctx.coarse_set_weights(theta, sx, sy)   # resets the moments
+        ctx.coarse_adam_step(g1, lr)
+        ctx.coarse_adam_step(g2, lr)
+        got, _, _ = ctx.coarse_weights()
+    finally:
+        ctx.coarse_set_weights(theta, sx, sy)
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    vv = np.zeros_like(th)
+    for k, g in enumerate((g1, g2)):
+        th, m, vv = learned.adam_step(th, g.astype(np.float64), m, vv, k + 1, lr=lr)
+    tol = 1e-4 * lr + 2.5e-7 * np.abs(theta)
+    assert np.all(np.abs(got - th) <= tol)
+    assert np.abs(got - theta).max() > 0.5 * lr
+
+
 def test_train_and_solve(setup):
     p, t, dec, ctx = setup
     q = workload.chamber_problem(c=0.02, nsub=16, overlap=1, nsrc=8, tear_seed=1001)
