@@ -321,6 +321,24 @@ int mx_apply_operator(mx_ctx* ctx, const mx_c128* X, mx_c128* Y, int32_t nrhs);
  * learned correction and theta_j minimising ||X_j - A Z_j||_2. */
 int mx_apply_preconditioner(mx_ctx* ctx, const mx_c128* X, mx_c128* Z, int32_t nrhs);
 
+/* Allocation-free variant of mx_apply_preconditioner, for callers that cannot
+ * allocate device memory (tight serving loops, code that must not call
+ * hipMalloc). Z = M^{-1} X with the one-level preconditioner only (the
+ * learned term needs allocated buffers: MX_ESTATE when it is set up).
+ *   X, Z  device pointers [ne][nrhs] on the context's GPU, owned by the
+ *         caller (X == Z allowed).
+ * The restricted vectors live in a fixed device array of 64 MiB (each GPU
+ * the library runs on holds its own until the process ends); a call needs
+ * sum_i N_i * nrhs * (16 bytes complex128 / 8 bytes complex64) of it and
+ * returns MX_EINVAL beyond that (e.g. the 1.02M-edge chamber with 512
+ * subdomains: 21 MB per right-hand side with complex64 factors, so at most
+ * 3 per call). The call allocates nothing and does not synchronise: the work
+ * is enqueued on the context's stream and Z is ready when the stream has
+ * executed it. All contexts on one GPU share the array, so calls whose work
+ * overlaps on one GPU (two streams, two threads) race; calls in one stream
+ * are ordered. Errors: MX_EINVAL (sizes, host pointers), MX_ESTATE. */
+int mx_apply_preconditioner_noalloc(mx_ctx* ctx, const mx_c128* X, mx_c128* Z, int32_t nrhs);
+
 /* Sizes of the current state (zeros for parts not yet built). */
 int mx_get_sizes(mx_ctx* ctx, mx_sizes* out);
 

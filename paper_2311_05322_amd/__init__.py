@@ -21,7 +21,7 @@ MX_PREC_C128, MX_PREC_C64 = 0, 1
 MX_KRYLOV_PSEUDO_BLOCK, MX_KRYLOV_BLOCK, MX_KRYLOV_BLOCK_CGS2 = 0, 1, 2
 
 EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_solve", "mx_solve_rhs",
-           "mx_apply_operator", "mx_apply_preconditioner", "mx_get_sizes", "mx_get_topology",
+           "mx_apply_operator", "mx_apply_preconditioner", "mx_apply_preconditioner_noalloc", "mx_get_sizes", "mx_get_topology",
            "mx_get_matrix_values", "mx_get_partition", "mx_get_local_matrix", "mx_point_functionals",
            "mx_set_stream", "mx_set_autotune", "mx_get_tuning", "mx_set_graphs", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_coarse_num_params", "mx_coarse_init",
            "mx_coarse_set_weights", "mx_coarse_get_weights", "mx_coarse_features", "mx_coarse_forward",
@@ -109,6 +109,7 @@ def lib():
             "mx_solve_rhs": [vp, vp, i32, dbl, vp, ct.POINTER(SolveInfo)],
             "mx_apply_operator": [vp, vp, vp, i32],
             "mx_apply_preconditioner": [vp, vp, vp, i32],
+            "mx_apply_preconditioner_noalloc": [vp, vp, vp, i32],
             "mx_get_sizes": [vp, ct.POINTER(Sizes)],
             "mx_get_topology": [vp, vp, vp, vp, vp],
             "mx_get_matrix_values": [vp, vp],
@@ -363,6 +364,15 @@ class Context:
         if Z is None:
             Z = np.zeros_like(X2) if not _is_torch(X2) else X2.clone()
         _check(lib().mx_apply_preconditioner(self._h, _ptr(X2), _ptr(Z), X2.shape[1]))
+        return Z
+
+    def apply_preconditioner_noalloc(self, X, Z):
+        """Z = M^{-1} X (one-level) for device tensors X, Z [ne][nrhs]
+        complex128, with no device allocation; enqueued on the context's
+        stream without synchronising."""
+        if not (_is_torch(X) and _is_torch(Z)):
+            raise ValueError("X and Z must be device tensors")
+        _check(lib().mx_apply_preconditioner_noalloc(self._h, _ptr(X), _ptr(Z), X.shape[1]))
         return Z
 
     # -- inspection ------------------------------------------------------------

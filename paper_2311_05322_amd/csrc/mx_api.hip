@@ -4,6 +4,7 @@
 #include <chrono>
 #include <complex>
 #include <functional>
+#include <mutex>
 #include <random>
 #include <cmath>
 #include <cstring>
@@ -74,6 +75,33 @@ bool is_device_ptr(const void* ptr) {
     return false;
   }
   return a.type == hipMemoryTypeDevice;
+}
+
+// Fixed device buffer of mx_apply_preconditioner_noalloc: the restricted
+// vectors of one preconditioner application live here instead of in memory
+// the context allocates. Each GPU the library runs on holds its own copy.
+// In host code `scratch` is only a handle for hipGetSymbolAddress; the
+// device address is looked up once per device (scratch_address) and only
+// that address is ever passed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device; nullptr until looked up
+
+// device address of `scratch` on the current device `dev`
+int scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+    if (!p) return set_err(MX_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MX_OK;
 }
 
 const double C0 = 299792458.0;
@@ -243,6 +271,7 @@ struct mx_ctx {
   // wall time of the last mx_assemble / mx_setup_schwarz, device time of its LU
   double t_assemble = 0, t_setup = 0, t_lu = 0;
   hipEvent_t ev_lu[2] = {nullptr, nullptr};
+  void* scratch_dev = nullptr;   // this device's address of the fixed scratch array
   // sources
   SourceSet tx, rx;
   DBuf<int32_t> s_edge, s_col, r_edge;
@@ -553,18 +582,22 @@ void coarse_correct(mx_ctx* c, const double2* v, C* xl, int nrhs) {
 
 // z = M^{-1} v; with the learned term active it is added to z, or, when q is
 // given, returned separately in q (z then holds plain ORAS)
+// local: the restricted-vector buffer ([sum N_i][nrhs] in the factor
+// precision); NULL uses the context's own, any other buffer runs the same
+// kernels without the profiler (no event is created or recorded)
 template <typename R>
-void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr) {
+void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr, void* local = nullptr) {
   typedef C_t<R> C;
   const Decomposition& D = c->dec;
   const int64_t nrows = D.vec_off[D.nsub];
-  C* xl = (C*)c->xloc.p;
-  c->prof.begin(K_RESTRICT);
+  C* xl = local ? (C*)local : (C*)c->xloc.p;
+  KTimer* tm = local ? nullptr : &c->prof;
+  if (tm) tm->begin(K_RESTRICT);
   launch_restrict<C>(c->stream, nrows, c->rowsrc.p, v, xl, nrhs);
-  c->prof.end(K_RESTRICT);
+  if (tm) tm->end(K_RESTRICT);
   launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p,
-                 c->tune_trsm_paired ? c->trsm_order.p : c->order.p, xl, D.nsub, nrhs, &c->prof);
-  const bool coarse = c->coarse_use && !c->coarse_off_now && c->coarse_geom && c->coarse_weights;
+                 c->tune_trsm_paired ? c->trsm_order.p : c->order.p, xl, D.nsub, nrhs, tm);
+  const bool coarse = !local && c->coarse_use && !c->coarse_off_now && c->coarse_geom && c->coarse_weights;
   C* xq = nullptr;
   if (coarse) {
     c->prof.begin(K_COARSE);
@@ -578,7 +611,7 @@ void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2*
     }
     c->prof.end(K_COARSE);
   }
-  c->prof.begin(K_PROLONG);
+  if (tm) tm->begin(K_PROLONG);
   launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, z);
   if (xq) launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, q);
   for (int col = 0; col < D.ncolour; ++col) {
@@ -586,14 +619,14 @@ void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2*
     launch_prolong<C>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xl, z, nrhs);
     if (xq) launch_prolong<C>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xq, q, nrhs);
   }
-  c->prof.end(K_PROLONG);
+  if (tm) tm->end(K_PROLONG);
 }
 
-int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr) {
+int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr, void* local = nullptr) {
   if (c->precision == MX_PREC_C64)
-    apply_precond_t<float>(c, v, z, nrhs, q);
+    apply_precond_t<float>(c, v, z, nrhs, q, local);
   else
-    apply_precond_t<double>(c, v, z, nrhs, q);
+    apply_precond_t<double>(c, v, z, nrhs, q, local);
   MX_HIP_CHECK(hipGetLastError());
   return MX_OK;
 }
@@ -1788,6 +1821,16 @@ int mx_create(mx_ctx** out, int device, void* hip_stream) {
   if (e == hipSuccess) e = hipEventCreate(&c->ev_lu[1]);
   c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
   c->prof.stream = &c->stream;
+  if (e == hipSuccess) {
+    const int rc = scratch_address(device, &c->scratch_dev);
+    if (rc != MX_OK) {
+      for (hipEvent_t ev : c->ev_lu)
+        if (ev) (void)hipEventDestroy(ev);
+      if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+      delete c;
+      return rc;
+    }
+  }
   if (e != hipSuccess) {
     for (hipEvent_t ev : c->ev_lu)
       if (ev) (void)hipEventDestroy(ev);
@@ -2374,6 +2417,23 @@ int mx_apply_preconditioner(mx_ctx* c, const mx_c128* X, mx_c128* Zo, int32_t nr
   }
   CK(copy_out(c, Zo, zout.p, bytes));
   CK(sync(c));
+  return MX_OK;
+}
+
+int mx_apply_preconditioner_noalloc(mx_ctx* c, const mx_c128* X, mx_c128* Zo, int32_t nrhs) {
+  if (!c || !X || !Zo || nrhs <= 0) return set_err(MX_EINVAL, "bad arguments");
+  if (nrhs > 256) return set_err(MX_EINVAL, "at most 256 right-hand sides");
+  if (!c->factored) return set_err(MX_ESTATE, "mx_setup_schwarz (with factor=1) must come first");
+  if (learned_ready(c))
+    return set_err(MX_ESTATE, "the learned term needs allocated buffers: use mx_apply_preconditioner");
+  if (!c->scratch_dev) return set_err(MX_ESTATE, "no scratch address for this device");
+  const size_t need = (size_t)c->dec.vec_off[c->dec.nsub] * nrhs * elem_bytes(c->precision);
+  if (need > kScratchBytes)
+    return set_err(MX_EINVAL, "needs " + std::to_string(need) + " bytes of scratch, the fixed buffer holds " +
+                                  std::to_string(kScratchBytes) + ": use fewer right-hand sides per call");
+  CK(use_device(c));
+  if (!is_device_ptr(X) || !is_device_ptr(Zo)) return set_err(MX_EINVAL, "X and Z must be device pointers");
+  CK(apply_precond(c, (const double2*)X, (double2*)Zo, nrhs, nullptr, c->scratch_dev));
   return MX_OK;
 }
 
