@@ -3,11 +3,14 @@
 
 One step = one all-transmitter solve for one permittivity map: operator
 values (topology cached), dense ORAS subdomain matrices + batched LU, and
-block FGMRES of every transmitter to relative residual 1e-8 (true residual
-checked).  The headline variant uses complex64 subdomain factors on the
-matrix cores under an FP64 outer iteration; the plain FP64 one-level Schwarz
-solver is timed in the same run as the reference, and so is block FGMRES (one
-Krylov space for all transmitters, variant c64_block).
+FGMRES of every transmitter to relative residual 1e-8 (true residual
+checked; a step that does not reach it fails the run).  The headline variant
+uses complex64 subdomain factors on the matrix cores under an FP64 outer
+iteration; the plain FP64 one-level Schwarz solver is timed in the same run
+as the reference, in both Krylov modes (pseudo-block: one FGMRES per
+transmitter; block: one Krylov space for all transmitters), so the gain of
+the precision and of the Krylov mode can be told apart. solves/s = 1 / median
+step time; every variant's fields are compared with the FP64 solve.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload chamber1m|cube8]
 Prints one JSON line on stdout (progress goes to stderr).
@@ -55,23 +58,22 @@ def make_problem(name):
     return workload.chamber_problem(**w)
 
 
-def algorithmic_work(kind, n_i, nnz, ne, nrhs, elem_bytes, kt):
-    """Algorithmic flops and bytes of one launch of a kernel class, from the
-    problem sizes (real subdomain sizes n_i, not the padded ones)."""
-    n = n_i.astype(np.float64)
+def algorithmic_work(kind, sz, nrhs, elem_bytes, kt):
+    """Algorithmic flops and bytes of one launch of a kernel class. The
+    subdomain unknowns are in reverse Cuthill-McKee order and the
+    factorisation and solves visit only the 64x64 tiles inside the band of
+    each matrix; their work is what those tiles hold (tile counts from the
+    library: sz.lu_tiles 64x64x64 complex tile products per factorisation,
+    sz.trsm_tiles_lower / _upper 64x64 factor tiles per solve)."""
     if kind == "lu_update":
-        # A22 -= L21 U12 for every 64-column panel: 8 * 64 * (n - 64(p+1))^2
-        tot = 0.0
-        for ni in n_i:
-            m = np.arange(64, int(ni), 64, dtype=np.float64)
-            tot += 8.0 * 64.0 * ((ni - m) ** 2).sum()
+        tot = 8.0 * 64.0 ** 3 * sz.lu_tiles
         nfact = max(1, kt["lu_inv"][1] // 2)          # two timed intervals per factorisation
-        per = tot / max(1.0, kt["lu_update"][1] / nfact)
-        return per, None
+        return tot / max(1.0, kt["lu_update"][1] / nfact), None
     if kind in ("trsm_lower", "trsm_upper"):
-        return 4.0 * (n * n).sum() * nrhs, 0.5 * (n * n).sum() * elem_bytes
+        tiles = sz.trsm_tiles_lower if kind == "trsm_lower" else sz.trsm_tiles_upper
+        return 8.0 * 64.0 * 64.0 * nrhs * tiles, 64.0 * 64.0 * elem_bytes * tiles
     if kind == "spmm":
-        return 8.0 * nnz * nrhs, 20.0 * nnz + 8.0 * (ne + 1) + 32.0 * ne * nrhs
+        return 8.0 * sz.nnz * nrhs, 20.0 * sz.nnz + 8.0 * (sz.ne + 1) + 32.0 * sz.ne * nrhs
     return None, None
 
 
@@ -97,6 +99,10 @@ def measured_traffic(kernel, workload_name):
 
 def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=True, coarse=False, block=False,
                 two_pass=False):
+    """Times `steps` all-transmitter solves (after `warmup` untimed ones), each
+    bracketed by device synchronisation; returns the per-step wall times, the
+    solve diagnostics, the per-kernel split of one more (profiled) step and S.
+    Raises if a timed step does not reach the tolerance."""
     import torch
     import paper_2311_05322_amd as mx
     S = np.zeros((len(p.src_pos), len(p.src_pos)), np.complex128)
@@ -112,15 +118,20 @@ def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=Tr
         info = step()
         log(f"  warmup {w}: iters {info['iters_max']} converged {info['converged']}")
     # timed steps: no per-kernel events, plain Arnoldi steps replayed from HIP graphs
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
+    times, infos = [], []
     for k in range(steps):
-        infos.append(step())
-        log(f"  step {k}: iters {infos[-1]['iters_max']} relres {infos[-1]['relres'].max():.2e} "
-            f"fallback {infos[-1]['fallback']}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        infos.append(info)
+        log(f"  step {k}: {times[-1]:.3f} s iters {info['iters_max']} relres {info['relres'].max():.2e} "
+            f"fallback {info['fallback']} (assemble {info['t_assemble']:.3f} s, set-up {info['t_setup']:.3f} s "
+            f"of which LU {info['t_lu']:.3f} s, iterations {info['t_iter']:.3f} s)")
+        if not info["converged"] or not np.all(info["relres"] <= p.rtol):
+            raise RuntimeError(f"timed step {k} did not reach rtol {p.rtol}: converged {info['converged']}, "
+                               f"max relres {info['relres'].max():.3e}")
     kt = None
     if profile:
         # one more step, outside the timed region, with HIP events around every
@@ -132,72 +143,120 @@ def run_variant(ctx, p, eps_dev, E_dev, prec, steps, warmup, restart, profile=Tr
         ctx.set_profiling(False)
         log(f"  profiled step: iters {info['iters_max']}")
     ctx.set_krylov(False)
-    return (t1 - t0) / steps, infos, kt, S
+    return times, infos, kt, S
 
 
-def cpu_baseline(p, iters, budget_s=25.0):
-    """The oracle's CPU ORAS-FGMRES cost per all-transmitter solve, from a
-    bounded sample of the same workload: per-subdomain set-up (local matrix +
-    sparse LU) and local solves on a sample of subdomains, one operator product
-    with all right-hand sides, element blocks on a sample of tetrahedra;
-    scaled to the full workload with the iteration count of the GPU run."""
-    from oracle import fem, schwarz
-    t0 = time.perf_counter()
-    T = fem.Topology(p.xyz, p.tet)
-    dec = schwarz.Decomposition(T, p.nsub, p.overlap)
-    t_prep = time.perf_counter() - t0
-    nrhs = len(p.src_pos)
-    # element blocks on a 1/16 sample of the tetrahedra
-    k0 = fem.k0_of(p.freq)
+_CPU = {}
+
+
+def _cpu_worker_init():
+    from threadpoolctl import threadpool_limits
+    _CPU["limits"] = threadpool_limits(1)
+
+
+def _cpu_subdomain(i):
+    """Oracle set-up (local ORAS matrix + sparse LU) and one solve with all
+    right-hand sides for subdomain i, in a worker process."""
+    from oracle import fem
+    p, dec, X = _CPU["p"], _CPU["dec"], _CPU["X"]
+    t = time.perf_counter()
+    B = dec.local_matrix(int(i), p.eps, p.eps_kind, p.freq, p.eps_b)
+    lu = fem.sparse_lu(B)
+    t1 = time.perf_counter()
+    lu.solve(np.ascontiguousarray(X[dec.dofs[i]]))
+    return t1 - t, time.perf_counter() - t1
+
+
+def _cpu_rows(k):
+    """The oracle's operator product on row block k of all right-hand sides."""
+    Ak, X = _CPU["Ablocks"][k], _CPU["X"]
+    t = time.perf_counter()
+    Ak @ X
+    return time.perf_counter() - t
+
+
+def _cpu_elements(k):
+    from oracle import fem
+    T, p, ch = _CPU["T"], _CPU["p"], _CPU["tchunks"]
     sub = fem.Topology.__new__(fem.Topology)
     sub.xyz = T.xyz
-    sub.tet_sorted = T.tet_sorted[::16]
+    sub.tet_sorted = T.tet_sorted[ch[k]:ch[k + 1]]
     t = time.perf_counter()
-    fem.element_operator(sub, p.eps[::16], 0, k0)
-    t_elem = (time.perf_counter() - t) * 16
-    # operator product with all right-hand sides (operator values from the oracle, untimed)
-    A = fem.assemble(T, p.eps, p.eps_kind, p.freq, p.eps_b)
+    fem.element_operator(sub, p.eps[ch[k]:ch[k + 1]], 0, fem.k0_of(p.freq))
+    return time.perf_counter() - t
+
+
+def cpu_sample(p, budget_s=20.0, cores=None):
+    """The oracle's CPU ORAS-FGMRES on a bounded sample of the same workload,
+    in `cores` worker processes over subdomains (all host cores, at most 16):
+    per-subdomain set-up (local matrix + sparse LU) and one all-transmitter
+    local solve on a random sample of subdomains, the operator product with
+    all right-hand sides and the element blocks split in row / tetrahedron
+    chunks over the workers. Runs before the GPU is touched (the workers are
+    forked)."""
+    import multiprocessing as mp
+    from oracle import fem, schwarz
+    cores = cores or max(1, min(16, os.cpu_count() or 1))
+    T = fem.Topology(p.xyz, p.tet)
+    dec = schwarz.Decomposition(T, p.nsub, p.overlap)
+    A = fem.assemble(T, p.eps, p.eps_kind, p.freq, p.eps_b).tocsr()
+    nrhs = len(p.src_pos)
     X = np.ones((T.ne, nrhs), np.complex128)
-    t = time.perf_counter()
-    A @ X
-    t_spmv = time.perf_counter() - t
-    # subdomain set-up and solves on a sample of subdomains within the budget
-    t_set = t_sol = 0.0
-    done = 0
-    tb = time.perf_counter()
-    order = np.random.default_rng(0).permutation(p.nsub)
-    for i in order:
+    ch = np.linspace(0, T.ne, cores + 1).astype(np.int64)
+    _CPU.update(p=p, dec=dec, X=X, T=T, Ablocks=[A[ch[k]:ch[k + 1]] for k in range(cores)],
+                tchunks=np.linspace(0, T.nt, cores + 1).astype(np.int64))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores, initializer=_cpu_worker_init) as pool:
         t = time.perf_counter()
-        B = dec.local_matrix(int(i), p.eps, p.eps_kind, p.freq, p.eps_b)
-        lu = fem.sparse_lu(B)
-        t1 = time.perf_counter()
-        lu.solve(np.ascontiguousarray(X[dec.dofs[i]]))
-        t_set += t1 - t
-        t_sol += time.perf_counter() - t1
-        done += 1
-        if time.perf_counter() - tb > budget_s and done >= 4:
-            break
+        pool.map(_cpu_elements, range(cores))
+        t_elem = time.perf_counter() - t
+        t = time.perf_counter()
+        pool.map(_cpu_rows, range(cores))
+        t_spmm = time.perf_counter() - t
+        order = np.random.default_rng(0).permutation(p.nsub)
+        per = []
+        t0 = time.perf_counter()
+        for b in range(0, p.nsub, cores):
+            per += pool.map(_cpu_subdomain, order[b:b + cores])
+            if time.perf_counter() - t0 > budget_s:
+                break
+        t_sub = time.perf_counter() - t0
+    done = len(per)
+    set_sum = sum(x[0] for x in per)
+    sol_sum = sum(x[1] for x in per)
+    # wall time of the sampled batches, split between set-up and solves in
+    # proportion to their summed per-subdomain times, scaled to all subdomains
     scale = p.nsub / done
-    t_total = t_elem + scale * t_set + iters * (t_spmv + scale * t_sol)
-    return {"value": 1.0 / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle ORAS-FGMRES (numpy/SuperLU, single thread) on the same workload: "
-                       f"set-up and {nrhs}-RHS local solves of {done}/{p.nsub} subdomains, element blocks "
-                       f"of 1/16 of the tetrahedra, one {nrhs}-RHS operator product; scaled by "
-                       f"{scale:.1f} and by {iters} iterations; {t_total:.0f} s per solve"),
-            "seconds_per_solve": t_total, "prep_s": t_prep}
+    t_set = scale * t_sub * set_sum / (set_sum + sol_sum)
+    t_sol = scale * t_sub * sol_sum / (set_sum + sol_sum)
+    return {"cores": cores, "nrhs": nrhs, "done": done, "nsub": p.nsub, "t_elem": t_elem, "t_spmm": t_spmm,
+            "t_set": t_set, "t_sol": t_sol}
+
+
+def cpu_baseline(smp, iters):
+    t_total = smp["t_elem"] + smp["t_set"] + iters * (smp["t_spmm"] + smp["t_sol"])
+    return {"value": 1.0 / t_total, "unit": "solves/s", "cores": smp["cores"], "kind": "oracle",
+            "sample": (f"oracle ORAS-FGMRES (numpy/SuperLU) in {smp['cores']} worker processes over subdomains "
+                       f"on the same workload: local matrices, sparse LU and {smp['nrhs']}-RHS local solves of "
+                       f"{smp['done']}/{smp['nsub']} subdomains (wall time scaled by {smp['nsub'] / smp['done']:.1f}), "
+                       f"the element blocks and one {smp['nrhs']}-RHS operator product in {smp['cores']} chunks; "
+                       f"{iters} iterations (those of the headline GPU run); {t_total:.0f} s per solve"),
+            "seconds_per_solve": t_total}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--ref-steps", type=int, default=5,
+                    help="timed steps of the variants other than the headline (at most --steps)")
     ap.add_argument("--workload", default="chamber1m", choices=sorted(WORKLOADS))
     ap.add_argument("--restart", type=int, default=30)
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference variant")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference variants")
     ap.add_argument("--no-learned", action="store_true", help="headline without the learned coarse term")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-block", action="store_true", help="skip the block FGMRES variant")
+    ap.add_argument("--no-block", action="store_true", help="skip the block FGMRES variants")
     ap.add_argument("--block-cgs2", action="store_true", help="also time block FGMRES with two Gram-Schmidt passes")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -221,14 +280,21 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
                           "dispatches": 3}))
         return
-    import paper_2311_05322_amd as mx
 
     p = make_problem(args.workload)
+    smp = None
+    if not args.no_cpu:
+        # the oracle's sample runs first, in forked workers, before the GPU is touched
+        log("cpu baseline sample (oracle, all host cores)")
+        t = time.perf_counter()
+        smp = cpu_sample(p, args.cpu_budget)
+        log(f"  {smp['done']} subdomains in {time.perf_counter() - t:.1f} s on {smp['cores']} cores")
+
+    import paper_2311_05322_amd as mx
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.set_stream(stream)
-    ctx = mx.Context(0)
-    ctx.set_stream(stream.cuda_stream)
+    ctx = mx.Context(0, stream=stream.cuda_stream)
     t = time.perf_counter()
     ctx.assemble(p.xyz, p.tet, p.eps, p.eps_kind, p.freq, p.eps_b)
     ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, factor=False)
@@ -247,7 +313,7 @@ def main():
         from paper_2311_05322_amd.train_coarse import load_weights
         ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, factor=False, coarse=True)
         load_weights(ctx, wfile)
-    variants = {}
+    # (name, precision, learned term, block Krylov, two-pass)
     # the learned variant runs in block mode: judged learned steps first, then
     # block FGMRES from that iterate once plain ORAS has switched the term off
     order = ([("c64_learned", mx.MX_PREC_C64, True, True, False)] if learned else []) + \
@@ -257,33 +323,64 @@ def main():
         if args.block_cgs2:
             order.append(("c64_block_cgs2", mx.MX_PREC_C64, False, True, True))
     if not args.no_fp64:
+        if not args.no_block:
+            order.append(("c128_block", mx.MX_PREC_C128, False, True, False))
         order.append(("c128_plain", mx.MX_PREC_C128, False, False, False))
+    head = order[0][0]
+    variants, fields = {}, {}
     for name, prec, co, blk, two in order:
         log(f"variant {name}")
-        ms, infos, kt, S = run_variant(ctx, p, eps_dev, E_dev, prec, args.steps, args.warmup, args.restart,
-                                       coarse=co, block=blk, two_pass=two)
-        variants[name] = {"ms": ms, "infos": infos, "kt": kt, "S": S, "tuning": ctx.tuning()}
-        log(f"  autotuner: {variants[name]['tuning']}")
+        steps = args.steps if name == head else max(1, min(args.steps, args.ref_steps))
+        warm = args.warmup if name == head else min(args.warmup, 1)
+        times, infos, kt, S = run_variant(ctx, p, eps_dev, E_dev, prec, steps, warm, args.restart,
+                                          coarse=co, block=blk, two_pass=two)
+        variants[name] = {"times": times, "infos": infos, "kt": kt, "S": S, "tuning": ctx.tuning(),
+                          "sizes": ctx.sizes()}
+        fields[name] = E_dev.clone()
+        log(f"  median {np.median(times):.3f} s, autotuner: {variants[name]['tuning']}")
     ctx.close()
-    head = "c64_learned" if learned else "c64_plain"
-    ms_mix, infos_mix, kt_mix, S_mix = (variants[head][k] for k in ("ms", "infos", "kt", "S"))
+
+    def field_err(name, ref):
+        d = torch.linalg.vector_norm(fields[name] - fields[ref], dim=0)
+        r = torch.linalg.vector_norm(fields[ref], dim=0)
+        return float((d / r).max())
+
+    fp64 = "c128_plain" if "c128_plain" in fields else None
+    others = {}
+    for k, v in variants.items():
+        last = v["infos"][-1]
+        others[k] = {"solves_per_s": 1.0 / float(np.median(v["times"])),
+                     "s_per_solve_median": float(np.median(v["times"])),
+                     "s_per_solve_mean": float(np.mean(v["times"])), "steps": len(v["times"]),
+                     "iters": int(last["iters_max"]), "fallback": int(last["fallback"]),
+                     "max_true_relres": float(max(i["relres"].max() for i in v["infos"])),
+                     "phases_s": {"assemble": last["t_assemble"], "setup": last["t_setup"], "lu": last["t_lu"],
+                                  "iterations": last["t_iter"]},
+                     "field_rel_err_vs_fp64": field_err(k, fp64) if fp64 else None,
+                     "autotune": v["tuning"],
+                     "band_tiles": {"lu": int(v["sizes"].lu_tiles), "trsm_lower": int(v["sizes"].trsm_tiles_lower),
+                                    "trsm_upper": int(v["sizes"].trsm_tiles_upper)},
+                     "kernel_ms_per_step": {kk: x[0] for kk, x in v["kt"].items() if x[1]}}
+    ms_mix = float(np.median(variants[head]["times"]))
+    kt_mix = variants[head]["kt"]
+    infos_mix = variants[head]["infos"]
+
+    def ratio(a, b):
+        return others[a]["solves_per_s"] / others[b]["solves_per_s"] if a in others and b in others else None
+
     ref = None
-    if "c128_plain" in variants:
-        v = variants["c128_plain"]
-        ref = {"solves_per_s": 1.0 / v["ms"], "ms_per_step": v["ms"] * 1e3,
-               "iters": int(v["infos"][-1]["iters_max"]),
-               "kernel_ms_per_step": {k: x[0] for k, x in v["kt"].items() if x[1]},
-               "S_rel_diff_vs_headline": float(np.abs(S_mix - v["S"]).max() / np.abs(v["S"]).max())}
-    others = {k: {"solves_per_s": 1.0 / v["ms"], "iters": int(v["infos"][-1]["iters_max"]),
-                  "fallback": int(v["infos"][-1]["fallback"]), "autotune": v["tuning"],
-                  "kernel_ms_per_step": {kk: x[0] for kk, x in v["kt"].items() if x[1]}}
-              for k, v in variants.items()}
+    if fp64:
+        v = others[fp64]
+        ref = {"solves_per_s": v["solves_per_s"], "ms_per_step": v["s_per_solve_median"] * 1e3,
+               "iters": v["iters"], "kernel_ms_per_step": v["kernel_ms_per_step"],
+               "S_rel_diff_vs_headline": float(np.abs(variants[head]["S"] - variants[fp64]["S"]).max()
+                                               / np.abs(variants[fp64]["S"]).max())}
 
     # dominant kernel of the headline variant and its roofline
     kt = kt_mix
     dom = max((k for k in kt if kt[k][1] > 0 and k in ("lu_update", "trsm_lower", "trsm_upper", "spmm")),
               key=lambda k: kt[k][0])
-    flops, byts = algorithmic_work(dom, n_i, sz.nnz, sz.ne, nrhs, 8, kt)
+    flops, byts = algorithmic_work(dom, variants[head]["sizes"], nrhs, 8, kt)
     avg_s = kt[dom][0] / kt[dom][1] / 1e3
     if dom == "spmm":
         roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
@@ -299,7 +396,7 @@ def main():
     for k in ("lu_update", "trsm_lower", "trsm_upper", "spmm"):
         if k not in kt or kt[k][1] == 0:
             continue
-        f, b = algorithmic_work(k, n_i, sz.nnz, sz.ne, nrhs, 8, kt)
+        f, b = algorithmic_work(k, variants[head]["sizes"], nrhs, 8, kt)
         a_s = kt[k][0] / kt[k][1] / 1e3
         if k == "spmm":
             roof_all[k] = {"bound": "hbm", "achieved": b / a_s / 1e9, "unit": "GB/s",
@@ -308,13 +405,15 @@ def main():
             roof_all[k] = {"bound": "mfma", "achieved": f / a_s / 1e12, "unit": "TFLOP/s",
                            "frac": f / a_s / 1e12 / MFMA_PEAK_TFLOPS["fp32"], "avg_launch_ms": a_s * 1e3}
 
-    cpu = None
     iters = int(infos_mix[-1]["iters_max"])
-    if not args.no_cpu:
-        log("cpu baseline (oracle, bounded sample)")
-        cpu = cpu_baseline(p, iters, args.cpu_budget)
+    cpu = cpu_baseline(smp, iters) if smp else None
 
     value = 1.0 / ms_mix
+    learned_note = None
+    if head == "c64_learned" and "c64_block" in others:
+        learned_note = {"iters_with": others["c64_learned"]["iters"], "iters_block_without": others["c64_block"]["iters"],
+                        "fallback_code": others["c64_learned"]["fallback"],
+                        "solves_per_s_ratio_vs_block": ratio("c64_learned", "c64_block")}
     out = {
         "metric": "all-transmitter Maxwell solves/s @1e-8 residual: learned+FP32-LU vs FP64 Schwarz",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -325,14 +424,19 @@ def main():
                    "restart": args.restart, "coarse": "learned" if head == "c64_learned" else "none",
                    "krylov": ("judged learned steps, then block FGMRES" if head == "c64_learned"
                               else "pseudo-block FGMRES"),
-                   "precision": "complex64 LU + FP64 FGMRES"},
+                   "precision": "complex64 LU + FP64 FGMRES", "timing": "median of the timed steps"},
         "variants": others,
         "iters": iters,
-        "speedup_vs_fp64_gpu": (value / ref["solves_per_s"]) if ref else None,
+        "field_rel_err_vs_fp64": others[head]["field_rel_err_vs_fp64"],
+        "speedup_vs_fp64_gpu": ratio(head, fp64) if fp64 else None,
+        "speedup_matched_krylov": {"c64_block_vs_c128_block": ratio("c64_block", "c128_block"),
+                                   "c64_plain_vs_c128_plain": ratio("c64_plain", "c128_plain"),
+                                   "headline_vs_c128_block": ratio(head, "c128_block")},
+        "learned_term": learned_note,
         "fastest_variant": (lambda k: {"name": k, "solves_per_s": others[k]["solves_per_s"],
                                        "iters": others[k]["iters"],
-                                       "speedup_vs_fp64_gpu": (others[k]["solves_per_s"] / ref["solves_per_s"])
-                                       if ref else None})(max(others, key=lambda k: others[k]["solves_per_s"])),
+                                       "speedup_vs_fp64_gpu": ratio(k, fp64) if fp64 else None})(
+            max(others, key=lambda k: others[k]["solves_per_s"])),
         "fp64_reference": ref,
         "kernel_ms_per_step": {k: v[0] for k, v in kt_mix.items() if v[1]},
         "roofline": roof,

@@ -130,6 +130,13 @@ typedef struct {
   int64_t sum_ni;      /* sum of subdomain DOF counts n_i */
   int64_t sum_Ni2;     /* sum of padded dense sizes N_i^2 (factor entries) */
   int32_t nb;          /* dense block size; N_i = n_i rounded up to nb */
+  /* Work of the banded factorisation and solves (0 before a factorisation):
+   * the subdomain unknowns are kept in reverse Cuthill-McKee order, so the
+   * dense local matrices are banded and only 64x64 tiles inside the band are
+   * visited. */
+  int64_t lu_tiles;          /* 64x64x64 complex tile products of the trailing updates */
+  int64_t trsm_tiles_lower;  /* 64x64 factor tiles read by one forward solve (all subdomains) */
+  int64_t trsm_tiles_upper;  /* 64x64 factor tiles read by one backward solve */
 } mx_sizes;
 
 /* Kernel classes timed by mx_set_profiling / mx_get_kernel_times. */

@@ -3,7 +3,10 @@
 Argument marshalling only: every step of the solve runs in the library's HIP
 kernels.  Arrays may be numpy arrays (host) or torch tensors on the GPU
 (device pointers are passed straight through).  The C ABI is declared in
-include/mx.h; the names here mirror it.
+include/mx.h; the names here mirror it.  A process that uses torch on the GPU
+as well imports torch before the first call into the library: torch ships
+its own HIP runtime under the same soname, the first one loaded serves both,
+and torch finds no device when it is not its own.
 """
 from __future__ import annotations
 
@@ -77,7 +80,8 @@ def _info_dict(info, iters, relres, rc):
 class Sizes(ct.Structure):
     _fields_ = [("nv", ct.c_int64), ("nt", ct.c_int64), ("ne", ct.c_int64), ("nnz", ct.c_int64),
                 ("nbface", ct.c_int64), ("nsub", ct.c_int32), ("overlap", ct.c_int32), ("ncolour", ct.c_int32),
-                ("sum_ni", ct.c_int64), ("sum_Ni2", ct.c_int64), ("nb", ct.c_int32)]
+                ("sum_ni", ct.c_int64), ("sum_Ni2", ct.c_int64), ("nb", ct.c_int32), ("lu_tiles", ct.c_int64),
+                ("trsm_tiles_lower", ct.c_int64), ("trsm_tiles_upper", ct.c_int64)]
 
 
 class Tuning(ct.Structure):

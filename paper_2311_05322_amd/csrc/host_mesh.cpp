@@ -233,6 +233,84 @@ void rcb_split(const std::vector<double>& cen, std::vector<int32_t>& ids, size_t
 
 }  // namespace
 
+// Reverse Cuthill-McKee order of a graph given as CSR (ptr, adj) on n nodes
+// (Cuthill & McKee 1969, reversed as proposed by George 1971): breadth-first
+// from a pseudo-peripheral start node (the end of repeated breadth-first
+// sweeps from a node of minimum degree), neighbours visited by increasing
+// degree then index; every connected component in turn. Returns order[k] =
+// node placed at position k.
+static std::vector<int32_t> rcm_order(int32_t n, const std::vector<int64_t>& ptr, const std::vector<int32_t>& adj) {
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<int32_t> level(n, -1);
+  std::vector<char> placed(n, 0);
+  auto deg = [&](int32_t v) { return (int32_t)(ptr[v + 1] - ptr[v]); };
+  // breadth-first levels from r over the unplaced nodes; returns the last node
+  // of the deepest level with minimum degree, and the depth
+  std::vector<int32_t> q, comp;
+  auto bfs = [&](int32_t r, int32_t& depth) {
+    for (int32_t v : comp) level[v] = -1;
+    comp.clear();
+    q.clear();
+    q.push_back(r);
+    level[r] = 0;
+    comp.push_back(r);
+    for (size_t h = 0; h < q.size(); ++h) {
+      const int32_t v = q[h];
+      for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e) {
+        const int32_t u = adj[e];
+        if (placed[u] || level[u] >= 0) continue;
+        level[u] = level[v] + 1;
+        q.push_back(u);
+        comp.push_back(u);
+      }
+    }
+    depth = level[q.back()];
+    int32_t best = q.back();
+    for (int32_t v : q)
+      if (level[v] == depth && (deg(v) < deg(best) || (deg(v) == deg(best) && v < best))) best = v;
+    return best;
+  };
+  for (int32_t seed = 0; seed < n; ++seed) {
+    if (placed[seed]) continue;
+    // node of minimum degree in seed's component, then pseudo-peripheral
+    int32_t depth = 0;
+    bfs(seed, depth);
+    int32_t r = seed;
+    for (int32_t v : comp)
+      if (deg(v) < deg(r) || (deg(v) == deg(r) && v < r)) r = v;
+    int32_t d0 = -1;
+    for (int it = 0; it < 8; ++it) {
+      int32_t d = 0;
+      const int32_t far = bfs(r, d);
+      if (d <= d0) break;
+      d0 = d;
+      r = far;
+    }
+    for (int32_t v : comp) level[v] = -1;
+    comp.clear();
+    // Cuthill-McKee from r
+    const size_t start = order.size();
+    order.push_back(r);
+    placed[r] = 1;
+    std::vector<int32_t> nb;
+    for (size_t h = start; h < order.size(); ++h) {
+      const int32_t v = order[h];
+      nb.clear();
+      for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e)
+        if (!placed[adj[e]]) nb.push_back(adj[e]);
+      std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg(a) < deg(b) || (deg(a) == deg(b) && a < b); });
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+      for (int32_t u : nb) {
+        placed[u] = 1;
+        order.push_back(u);
+      }
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
 std::string build_decomposition(const Topology& T, int32_t nsub, int32_t overlap, int32_t nb,
                                 Decomposition& Dc) {
   if (nsub < 1 || (nsub & (nsub - 1))) return "nsub must be a power of two";
@@ -386,6 +464,40 @@ std::string build_decomposition(const Topology& T, int32_t nsub, int32_t overlap
     Dc.mat_off[i + 1] = Dc.mat_off[i] + N * N;
     Dc.vec_off[i + 1] = Dc.vec_off[i] + N;
   }
+  // ---- dense order of each subdomain's DOFs: reverse Cuthill-McKee on the
+  // graph of DOFs that share a tetrahedron of the subdomain
+  Dc.lpos.assign(Dc.dof_ptr[nsub], 0);
+  Dc.dense_edge.assign(Dc.vec_off[nsub], -1);
+#pragma omp parallel
+  {
+    std::vector<int32_t> loc(T.ne, -1);
+    std::vector<std::pair<int32_t, int32_t>> pairs;
+#pragma omp for schedule(dynamic, 1)
+    for (int32_t i = 0; i < nsub; ++i) {
+      const int32_t n = (int32_t)(Dc.dof_ptr[i + 1] - Dc.dof_ptr[i]);
+      for (int64_t k = Dc.dof_ptr[i]; k < Dc.dof_ptr[i + 1]; ++k) loc[Dc.dofs[k]] = (int32_t)(k - Dc.dof_ptr[i]);
+      pairs.clear();
+      for (int64_t k = Dc.tet_ptr[i]; k < Dc.tet_ptr[i + 1]; ++k) {
+        const int32_t* te = &T.t2e[6 * (size_t)Dc.tets[k]];
+        for (int a = 0; a < 6; ++a)
+          for (int b = 0; b < 6; ++b)
+            if (a != b) pairs.push_back({loc[te[a]], loc[te[b]]});
+      }
+      std::sort(pairs.begin(), pairs.end());
+      pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+      std::vector<int64_t> ptr(n + 1, 0);
+      std::vector<int32_t> adj(pairs.size());
+      for (auto& pr : pairs) ptr[pr.first + 1]++;
+      for (int32_t v = 0; v < n; ++v) ptr[v + 1] += ptr[v];
+      for (size_t e = 0; e < pairs.size(); ++e) adj[e] = pairs[e].second;
+      const std::vector<int32_t> ord = rcm_order(n, ptr, adj);
+      for (int32_t r = 0; r < n; ++r) {
+        Dc.lpos[Dc.dof_ptr[i] + ord[r]] = r;
+        Dc.dense_edge[Dc.vec_off[i] + r] = Dc.dofs[Dc.dof_ptr[i] + ord[r]];
+      }
+      for (int64_t k = Dc.dof_ptr[i]; k < Dc.dof_ptr[i + 1]; ++k) loc[Dc.dofs[k]] = -1;
+    }
+  }
   // ---- interface faces
   {
     std::vector<int64_t> keys;
@@ -423,8 +535,7 @@ std::string build_decomposition(const Topology& T, int32_t nsub, int32_t overlap
 #pragma omp for schedule(dynamic, 1)
     for (int32_t i = 0; i < nsub; ++i) {
       const int64_t N = Dc.Npad[i];
-      for (int64_t k = Dc.dof_ptr[i]; k < Dc.dof_ptr[i + 1]; ++k)
-        loc[Dc.dofs[k]] = (int32_t)(k - Dc.dof_ptr[i]);
+      for (int64_t k = Dc.dof_ptr[i]; k < Dc.dof_ptr[i + 1]; ++k) loc[Dc.dofs[k]] = Dc.lpos[k];  // dense row
       for (int64_t k = Dc.tet_ptr[i]; k < Dc.tet_ptr[i + 1]; ++k) inT[Dc.tets[k]] = 1;
       items.clear();
       for (int64_t k = Dc.tet_ptr[i]; k < Dc.tet_ptr[i + 1]; ++k) {
@@ -506,7 +617,7 @@ std::string build_decomposition(const Topology& T, int32_t nsub, int32_t overlap
       for (int64_t k = Dc.dof_ptr[i]; k < Dc.dof_ptr[i + 1]; ++k) {
         if (Dc.w[k] == 0) continue;
         Dc.p_edge.push_back(Dc.dofs[k]);
-        Dc.p_row.push_back(Dc.vec_off[i] + (k - Dc.dof_ptr[i]));
+        Dc.p_row.push_back(Dc.vec_off[i] + Dc.lpos[k]);
         Dc.p_w.push_back(Dc.D[k]);
       }
     }

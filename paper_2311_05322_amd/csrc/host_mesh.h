@@ -61,6 +61,12 @@ struct Decomposition {
   std::vector<int32_t> tets;
   std::vector<int64_t> nbr_ptr;       // [nsub+1] adjacent subdomains
   std::vector<int32_t> nbrs;
+  // dense row of each local DOF: a reverse Cuthill-McKee order of the
+  // subdomain's DOF graph (DOFs sharing a tetrahedron of the subdomain), so
+  // that the dense local matrix is banded; dense_edge is the inverse map
+  // (global edge of each dense row, -1 on the padding rows)
+  std::vector<int32_t> lpos;          // [sum n_i]
+  std::vector<int32_t> dense_edge;    // [sum N_i]
   // padded dense sizes and offsets of the local matrices
   std::vector<int32_t> Npad;          // [nsub]
   std::vector<int64_t> mat_off;       // [nsub+1] offsets in entries
@@ -72,7 +78,7 @@ struct Decomposition {
   std::vector<int64_t> ldest, lptr;
   std::vector<int32_t> lsrc;
   // prolongation entries grouped by colour: destination edge, source padded
-  // row (vec_off[i] + local index), weight
+  // row (vec_off[i] + lpos), weight
   std::vector<int64_t> pcol_ptr;      // [ncolour+1]
   std::vector<int32_t> p_edge;
   std::vector<int64_t> p_row;

@@ -428,21 +428,14 @@ __global__ void __launch_bounds__(256) k_lu_rowswap(C_t<R>* __restrict__ pool, c
 // --------------------------------------------------------------------------
 constexpr int KCH = 32;
 
+// One 64x64 tile of A22 -= L21 U12: rows i0.., columns j0.. of the matrix A
+// (order N), the kd-deep product over columns kl.. of L21 and rows kl.. of
+// U12. As / Bs: the workgroup's LDS staging.
 template <typename R>
-__global__ void __launch_bounds__(256, 2) k_lu_update(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
-                                                   const int32_t* __restrict__ Npad,
-                                                   const int32_t* __restrict__ order, int kl, int kd, int r0,
-                                                   int c0) {
+__device__ __forceinline__ void lu_update_tile(C_t<R>* __restrict__ A, int N, int i0, int j0, int kl, int kd,
+                                               C_t<R> (&As)[NB][KCH + 1], C_t<R> (&Bs)[KCH][NB + 1]) {
   typedef C_t<R> C;
   typedef Acc_t<R> Acc;
-  const int s = order[blockIdx.z];
-  const int N = Npad[s];
-  const int i0 = r0 + blockIdx.y * NB;
-  const int j0 = c0 + blockIdx.x * NB;
-  if (i0 >= N || j0 >= N) return;
-  C* A = pool + mat_off[s];
-  __shared__ C As[NB][KCH + 1];
-  __shared__ C Bs[KCH][NB + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
@@ -498,7 +491,7 @@ __global__ void __launch_bounds__(256, 2) k_lu_update(C_t<R>* __restrict__ pool,
     };
     gload(0);
     for (int kc = 0; kc < kd; kc += KCH) {
-      if (kc) __syncthreads();
+      __syncthreads();
 #pragma unroll
       for (int q = 0; q < NB * KCH / 256; ++q) {
         const int e = tid + 256 * q;
@@ -513,7 +506,7 @@ __global__ void __launch_bounds__(256, 2) k_lu_update(C_t<R>* __restrict__ pool,
   } else {
     // complex128: staged directly (the register budget holds no second chunk)
     for (int kc = 0; kc < kd; kc += KCH) {
-      if (kc) __syncthreads();
+      __syncthreads();
       for (int e = tid; e < NB * KCH; e += 256) {
         As[e / KCH][e % KCH] = A[(int64_t)(i0 + e / KCH) * N + kl + kc + e % KCH];
         Bs[e / NB][e % NB] = A[(int64_t)(kl + kc + e / NB) * N + j0 + e % NB];
@@ -534,6 +527,192 @@ __global__ void __launch_bounds__(256, 2) k_lu_update(C_t<R>* __restrict__ pool,
         v.y -= t3[it][jt][r] - t1[it][jt][r] - t2[it][jt][r];
         A[(int64_t)(i0 + wr + 16 * it + acc_row<R>(lane, r)) * N + j0 + wc + 16 * jt + (lane & 15)] = v;
       }
+}
+
+// --------------------------------------------------------------------------
+// Band bookkeeping. A subdomain matrix in reverse Cuthill-McKee order is
+// banded, and elimination keeps its non-zeros near the diagonal; only 64x64
+// tiles that the trailing updates can change are visited. After a panel is
+// factored its L part is scanned for the last row tile holding a non-zero
+// (ext_l), after its U part is formed that for the last column tile (ext_u);
+// a trailing update then visits row tiles up to the largest ext_l and column
+// tiles up to the largest ext_u of the panels it applies (everything beyond
+// is a product with an exact zero). The row interchanges of a panel move
+// values of earlier L columns between its pivot rows: an earlier panel whose
+// L part reaches the current panel's rows gets its extent raised to the
+// lowest pivot row. The extents are exact data (not a structural estimate),
+// so they hold under any pivoting.
+// --------------------------------------------------------------------------
+__global__ void k_band_init(int nsub, const int32_t* __restrict__ Npad, int np, int32_t* __restrict__ ext_l,
+                            int32_t* __restrict__ ext_u, int64_t* __restrict__ work) {
+  const int s = blockIdx.x;
+  if (s == 0 && threadIdx.x == 0) work[0] = 0;
+  const int nt = Npad[s] / NB;
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    ext_l[(int64_t)s * np + p] = p < nt ? p : -1;
+    ext_u[(int64_t)s * np + p] = p < nt ? p : -1;
+  }
+}
+
+// wave-wide "any non-zero" over a 64-wide row segment (one value per lane)
+template <typename C>
+__device__ inline bool wave_any_nonzero(C v) {
+  return __ballot(v.x != 0 || v.y != 0) != 0;
+}
+
+// ext_l of the panel at column k (scan of rows k+64 .. N-1, bottom up, one
+// row per wave and step) and the pivot rule for the earlier panels
+template <typename R>
+__global__ void __launch_bounds__(256) k_band_l(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                                const int32_t* __restrict__ Npad, const int32_t* __restrict__ order,
+                                                const int32_t* __restrict__ piv, const int64_t* __restrict__ vec_off,
+                                                int np, int32_t* __restrict__ ext_l, int k) {
+  const int s = order[blockIdx.x];
+  const int N = Npad[s];
+  if (k >= N) return;
+  const C_t<R>* A = pool + mat_off[s];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ int last[4];
+  int found = -1;
+  for (int r = N - 1 - w; r >= k + NB; r -= 4) {
+    if (wave_any_nonzero(A[(int64_t)r * N + k + lane])) {
+      found = r;
+      break;
+    }
+  }
+  if (lane == 0) last[w] = found;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int p = k / NB;
+    int rmax = max(max(last[0], last[1]), max(last[2], last[3]));
+    int32_t* e = ext_l + (int64_t)s * np;
+    e[p] = rmax >= 0 ? max(p, rmax / NB) : p;
+    int pmax = k;
+    for (int c = 0; c < NB; ++c) pmax = max(pmax, piv[vec_off[s] + k + c]);
+    const int tm = pmax / NB;
+    for (int q = 0; q < p; ++q)
+      if (e[q] >= p && e[q] < tm) e[q] = tm;
+  }
+}
+
+// ext_u of the panel at row k (scan of column tiles right of the panel,
+// right to left, one tile per wave and step)
+template <typename R>
+__global__ void __launch_bounds__(256) k_band_u(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                                const int32_t* __restrict__ Npad, const int32_t* __restrict__ order,
+                                                int np, int32_t* __restrict__ ext_u, int k) {
+  const int s = order[blockIdx.x];
+  const int N = Npad[s];
+  if (k >= N) return;
+  const C_t<R>* A = pool + mat_off[s];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ int last[4];
+  const int p = k / NB;
+  int found = -1;
+  for (int ct = N / NB - 1 - w; ct > p && found < 0; ct -= 4) {
+    for (int r = 0; r < NB; ++r)
+      if (wave_any_nonzero(A[(int64_t)(k + r) * N + NB * ct + lane])) {
+        found = ct;
+        break;
+      }
+  }
+  if (lane == 0) last[w] = found;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int cmax = max(max(last[0], last[1]), max(last[2], last[3]));
+    ext_u[(int64_t)s * np + p] = cmax >= 0 ? cmax : p;
+  }
+}
+
+// Tile list of one trailing update A22 -= L U over the panels [pa, pb):
+// mode 0 (the group's update) rows rt0 .. max ext_l, columns ct0 .. max ext_u;
+// mode 1 (one panel's column block) rows rt0 .. max ext_l, column ct0 (if any
+// U part reaches it); mode 2 (one panel's row block) row rt0 (if any L part
+// reaches it), columns ct0 .. max ext_u. tptr = exclusive prefix of the tile
+// counts over the active subdomains, tbox[2z] = first row tile,
+// tbox[2z+1] = number of column tiles; work[0] += tiles * (kd / 64).
+__global__ void __launch_bounds__(256) k_band_tiles(int nact, const int32_t* __restrict__ Npad,
+                                                    const int32_t* __restrict__ order, int np,
+                                                    const int32_t* __restrict__ ext_l,
+                                                    const int32_t* __restrict__ ext_u, int pa, int pb, int rt0,
+                                                    int ct0, int mode, int64_t* __restrict__ tptr,
+                                                    int32_t* __restrict__ tbox, int64_t* __restrict__ work,
+                                                    int kdt) {
+  __shared__ int64_t part[256];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int z0 = 0; z0 < nact; z0 += 256) {
+    const int z = z0 + threadIdx.x;
+    int64_t cnt = 0;
+    if (z < nact) {
+      const int s = order[z];
+      const int nt = Npad[s] / NB;
+      int lmax = -1, umax = -1;
+      for (int q = pa; q < pb && q < nt; ++q) {
+        lmax = max(lmax, ext_l[(int64_t)s * np + q]);
+        umax = max(umax, ext_u[(int64_t)s * np + q]);
+      }
+      lmax = min(lmax, nt - 1);
+      umax = min(umax, nt - 1);
+      int r1, c1;
+      if (mode == 0) { r1 = lmax; c1 = umax; }
+      else if (mode == 1) { r1 = lmax; c1 = umax >= ct0 ? ct0 : ct0 - 1; }
+      else { r1 = lmax >= rt0 ? rt0 : rt0 - 1; c1 = umax; }
+      const int nr = rt0 < nt ? max(0, r1 - rt0 + 1) : 0;
+      const int nc = ct0 < nt ? max(0, c1 - ct0 + 1) : 0;
+      cnt = (int64_t)nr * nc;
+      tbox[2 * z] = rt0;
+      tbox[2 * z + 1] = nc;
+    }
+    part[threadIdx.x] = cnt;
+    __syncthreads();
+    // inclusive scan of the block (Hillis-Steele)
+    for (int o = 1; o < 256; o <<= 1) {
+      const int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+      __syncthreads();
+      part[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (z < nact) tptr[z] = carry + part[threadIdx.x] - cnt;
+    __syncthreads();
+    if (threadIdx.x == 255) carry += part[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tptr[nact] = carry;
+    work[0] += carry * kdt;
+  }
+}
+
+// The trailing update over a tile list: a fixed grid of workgroups walks the
+// list (tile t, t + gridDim.x, ...), whatever the number of tiles; uneven
+// subdomains are balanced over the whole chip.
+template <typename R>
+__global__ void __launch_bounds__(256, 2) k_lu_update_list(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                                        const int32_t* __restrict__ Npad,
+                                                        const int32_t* __restrict__ order, int nact,
+                                                        const int64_t* __restrict__ tptr,
+                                                        const int32_t* __restrict__ tbox, int ct0, int kl, int kd) {
+  typedef C_t<R> C;
+  __shared__ C As[NB][KCH + 1];
+  __shared__ C Bs[KCH][NB + 1];
+  const int64_t total = tptr[nact];
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    // subdomain of tile t: last z with tptr[z] <= t
+    int lo = 0, hi = nact - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tptr[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int z = lo;
+    const int64_t loc = t - tptr[z];
+    const int nc = tbox[2 * z + 1];
+    const int i0 = NB * (tbox[2 * z] + (int)(loc / nc));
+    const int j0 = NB * (ct0 + (int)(loc % nc));
+    const int s = order[z];
+    lu_update_tile<R>(pool + mat_off[s], Npad[s], i0, j0, kl, kd, As, Bs);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -577,7 +756,7 @@ __global__ void __launch_bounds__(64) k_inv_upper(C_t<R>* __restrict__ pool, con
 // perm = the row permutation P of P A = L U
 __global__ void __launch_bounds__(64) k_perm(int32_t nsub, const int32_t* __restrict__ Npad,
                                              const int64_t* __restrict__ vec_off,
-                                             const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ dofs,
+                                             const int32_t* __restrict__ dense_edge,
                                              const int32_t* __restrict__ piv, int32_t* __restrict__ perm_scratch,
                                              int32_t* __restrict__ rowsrc) {
   const int s = blockIdx.x;
@@ -594,11 +773,7 @@ __global__ void __launch_bounds__(64) k_perm(int32_t nsub, const int32_t* __rest
     }
   }
   __syncthreads();
-  const int64_t n = dof_ptr[s + 1] - dof_ptr[s];
-  for (int r = threadIdx.x; r < N; r += 64) {
-    int q = perm[r];
-    rowsrc[vec_off[s] + r] = q < n ? dofs[dof_ptr[s] + q] : -1;
-  }
+  for (int r = threadIdx.x; r < N; r += 64) rowsrc[vec_off[s] + r] = dense_edge[vec_off[s] + perm[r]];
 }
 
 // --------------------------------------------------------------------------
@@ -693,7 +868,7 @@ template <typename R, bool LOWER>
 __global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
     k_trsm(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off, const int32_t* __restrict__ Npad,
            const int64_t* __restrict__ vec_off, const int32_t* __restrict__ order, C_t<R>* __restrict__ xloc,
-           int nrhs) {
+           int nrhs, const int32_t* __restrict__ trs_lo, const int32_t* __restrict__ trs_hi, int np) {
   typedef C_t<R> C;
   typedef Acc_t<R> Acc;
   constexpr int TRT = TrsmShape<R>::RT, TNW = trsm_waves<R>();
@@ -717,9 +892,13 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
       for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) { cre[rt][ct] = zacc<R>(); cim[rt][ct] = zacc<R>(); }
-      // off-diagonal part over K = [kbeg, kbeg + KC * nch)
-      const int kbeg = LOWER ? 0 : b0 + nd * NB;
-      const int nch = ((LOWER ? b0 : N) - kbeg) / KC;
+      // off-diagonal part over K = [kbeg, kbeg + KC * nch): the band of this
+      // wave's row tile (L: from its first non-zero column tile up to the
+      // super-block; U: from the super-block's end up to its last one)
+      const int tw = (b0 + 16 * TRT * w) / NB;
+      const int kbeg = LOWER ? NB * trs_lo[(int64_t)s * np + tw] : b0 + nd * NB;
+      const int kend = LOWER ? b0 : min(N, NB * (trs_hi[(int64_t)s * np + tw] + 1));
+      const int nch = max(0, (kend - kbeg) / KC);
       if (nch > 0) {
         Acc t3[TRT][2];
 #pragma unroll
@@ -869,10 +1048,14 @@ static void launch_panel(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, c
 // Batched LU with partial pivoting of all subdomain matrices (largest first,
 // a subdomain drops out of a launch once its order is passed), then the
 // inverses of the 64x64 diagonal blocks of U used by the triangular solves.
+// Every trailing update visits only the tiles its band bookkeeping leaves
+// (k_band_*), through a tile list walked by a fixed grid.
+constexpr int UPDATE_GRID = 1024;   // workgroups of a tile-list update (2 per CU resident)
+
 template <typename R>
 void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
                int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
-               const std::vector<int32_t>& Nsorted, KTimer* tm) {
+               const std::vector<int32_t>& Nsorted, const LuBand& band, KTimer* tm) {
   if (Nsorted.empty()) return;
   const int Nmax = Nsorted[0];
   const int nsub = (int)Nsorted.size();
@@ -882,6 +1065,17 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
     return a;
   };
   const unsigned ctiles = ceil_div(Nmax, NB);
+  const int np = band.np;
+  hipLaunchKernelGGL(k_band_init, dim3(nsub), dim3(64), 0, st, nsub, Npad, np, band.ext_l, band.ext_u, band.work);
+  // trailing update of the panels [pa, pb) over the tile box (rt0, ct0, mode)
+  auto update = [&](int nact, int pa, int pb, int rt0, int ct0, int mode, int kl, int kd) {
+    MX_TB(K_LU_UPDATE);
+    hipLaunchKernelGGL(k_band_tiles, dim3(1), dim3(256), 0, st, nact, Npad, order, np, band.ext_l, band.ext_u, pa, pb,
+                       rt0, ct0, mode, band.tptr, band.tbox, band.work, kd / NB);
+    hipLaunchKernelGGL((k_lu_update_list<R>), dim3(UPDATE_GRID), dim3(256), 0, st, pool, mat_off, Npad, order, nact,
+                       band.tptr, band.tbox, ct0, kl, kd);
+    MX_TE(K_LU_UPDATE);
+  };
   // Panels are taken in groups of LU_GROUP: the trailing matrix gets one
   // LU_GROUP*64-deep pass per group. Inside a group, panel i (i > 0) first
   // receives the group's earlier panels' update of its own column block
@@ -889,18 +1083,17 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
   // earlier panels' update of its own row block right of it, and then forms
   // its U12.
   for (int g0 = 0; g0 < Nmax; g0 += LU_GROUP * NB) {
+    const int pa = g0 / NB;
     for (int i = 0; i < LU_GROUP; ++i) {
       const int ki = g0 + i * NB;
       if (ki >= Nmax) break;
       const int nact = active(ki);
-      if (i > 0) {
-        MX_TB(K_LU_UPDATE);
-        hipLaunchKernelGGL((k_lu_update<R>), dim3(1, (Nmax - ki) / NB, nact), dim3(256), 0, st, pool, mat_off, Npad,
-                           order, g0, i * NB, ki, ki);
-        MX_TE(K_LU_UPDATE);
-      }
+      const int pk = ki / NB;
+      if (i > 0) update(nact, pa, pk, pk, pk, 1, g0, i * NB);
       MX_TB(K_LU_PANEL);
       launch_panel<R>(st, pool, mat_off, Npad, order, piv, vec_off, status, pswap, Nmax, nact, ki);
+      hipLaunchKernelGGL((k_band_l<R>), dim3(nact), dim3(256), 0, st, pool, mat_off, Npad, order, piv, vec_off, np,
+                         band.ext_l, ki);
       MX_TE(K_LU_PANEL);
       MX_TB(K_LU_ROWPANEL);
       if (i > 0 && sizeof(R) == 4)  // complex64: the moved values fit in registers
@@ -911,23 +1104,21 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
                            order, pswap, ki, i == 0 ? 0 : 1);
       MX_TE(K_LU_ROWPANEL);
       const int kn = ki + NB;
-      if (i == 0 || kn >= Nmax) continue;
-      MX_TB(K_LU_UPDATE);
-      hipLaunchKernelGGL((k_lu_update<R>), dim3((Nmax - kn) / NB, 1, nact), dim3(256), 0, st, pool, mat_off, Npad,
-                         order, g0, i * NB, ki, kn);
-      MX_TE(K_LU_UPDATE);
+      if (kn >= Nmax) continue;
+      if (i > 0) {
+        update(nact, pa, pk, pk, kn / NB, 2, g0, i * NB);
+        MX_TB(K_LU_ROWPANEL);
+        hipLaunchKernelGGL((k_lu_rowpanel<R, NB>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad, order,
+                           pswap, ki, 2);
+        MX_TE(K_LU_ROWPANEL);
+      }
       MX_TB(K_LU_ROWPANEL);
-      hipLaunchKernelGGL((k_lu_rowpanel<R, NB>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad, order,
-                         pswap, ki, 2);
+      hipLaunchKernelGGL((k_band_u<R>), dim3(nact), dim3(256), 0, st, pool, mat_off, Npad, order, np, band.ext_u, ki);
       MX_TE(K_LU_ROWPANEL);
     }
     const int ke = g0 + LU_GROUP * NB;
     if (ke >= Nmax) break;
-    const int nt = (Nmax - ke) / NB;
-    MX_TB(K_LU_UPDATE);
-    hipLaunchKernelGGL((k_lu_update<R>), dim3(nt, nt, active(ke)), dim3(256), 0, st, pool, mat_off, Npad, order, g0,
-                       LU_GROUP * NB, ke, ke);
-    MX_TE(K_LU_UPDATE);
+    update(active(ke), pa, pa + LU_GROUP, ke / NB, ke / NB, 0, g0, LU_GROUP * NB);
   }
   MX_TB(K_LU_INV);
   hipLaunchKernelGGL((k_inv_upper<R>), dim3(ceil_div(Nmax, NB), (unsigned)Nsorted.size()), dim3(64), 0, st, pool,
@@ -935,33 +1126,38 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
   MX_TE(K_LU_INV);
 }
 template void launch_lu<float>(hipStream_t, float2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
-                               const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, KTimer*);
+                               const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, const LuBand&,
+                               KTimer*);
 template void launch_lu<double>(hipStream_t, double2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
-                                const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, KTimer*);
+                                const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, const LuBand&,
+                                KTimer*);
 
-void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int64_t* dof_ptr,
-                 const int32_t* dofs, const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc) {
+void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int32_t* dense_edge,
+                 const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc) {
   if (nsub > 0)
-    hipLaunchKernelGGL(k_perm, dim3(nsub), dim3(64), 0, st, nsub, Npad, vec_off, dof_ptr, dofs, piv, perm_scratch,
+    hipLaunchKernelGGL(k_perm, dim3(nsub), dim3(64), 0, st, nsub, Npad, vec_off, dense_edge, piv, perm_scratch,
                        rowsrc);
 }
 
 template <typename R>
 void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
-                 const int64_t* vec_off, const int32_t* order, C_t<R>* xloc, int nsub, int nrhs, KTimer* tm) {
+                 const int64_t* vec_off, const int32_t* order, C_t<R>* xloc, int nsub, int nrhs,
+                 const int32_t* trs_lo, const int32_t* trs_hi, int np, KTimer* tm) {
   if (nsub <= 0 || nrhs <= 0) return;
   dim3 grid(nsub, ceil_div(nrhs, RC));
   MX_TB(K_TRSM_LOWER);
-  hipLaunchKernelGGL((k_trsm<R, true>), grid, dim3(64 * trsm_waves<R>()), 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs);
+  hipLaunchKernelGGL((k_trsm<R, true>), grid, dim3(64 * trsm_waves<R>()), 0, st, pool, mat_off, Npad, vec_off, order,
+                     xloc, nrhs, trs_lo, trs_hi, np);
   MX_TE(K_TRSM_LOWER);
   MX_TB(K_TRSM_UPPER);
-  hipLaunchKernelGGL((k_trsm<R, false>), grid, dim3(64 * trsm_waves<R>()), 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs);
+  hipLaunchKernelGGL((k_trsm<R, false>), grid, dim3(64 * trsm_waves<R>()), 0, st, pool, mat_off, Npad, vec_off, order,
+                     xloc, nrhs, trs_lo, trs_hi, np);
   MX_TE(K_TRSM_UPPER);
 }
 template void launch_trsm<float>(hipStream_t, const float2*, const int64_t*, const int32_t*, const int64_t*,
-                                 const int32_t*, float2*, int, int, KTimer*);
+                                 const int32_t*, float2*, int, int, const int32_t*, const int32_t*, int, KTimer*);
 template void launch_trsm<double>(hipStream_t, const double2*, const int64_t*, const int32_t*, const int64_t*,
-                                  const int32_t*, double2*, int, int, KTimer*);
+                                  const int32_t*, double2*, int, int, const int32_t*, const int32_t*, int, KTimer*);
 
 int lu_max_swap_rows() { return MAXSW; }
 

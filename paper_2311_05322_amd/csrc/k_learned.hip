@@ -4,7 +4,7 @@
 //
 // Network arithmetic: the operands of every matrix product are rounded to
 // bfloat16 (round to nearest even) as they are staged into LDS and multiplied
-// on the 16x16x4 FP32 matrix cores with FP32 accumulation; biases, GELU, the
+// on the 16x16x32 bf16 matrix cores with FP32 accumulation; biases, GELU, the
 // loss and the Adam update run in FP32 on FP32 master weights.
 #include "mx_device.h"
 #include "mx_kernels.h"
@@ -17,13 +17,6 @@ constexpr int NCO = 192;   // complex lattice coefficients (64 nodes x 3 compone
 constexpr int NIN = 384;   // real channels [Re | Im]
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-
-__device__ inline float bf16r(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return x;  // inf / nan unchanged
-  u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
-  return __uint_as_float(u);
-}
 
 __device__ inline float gelu_f(float z) {
   const float a = 0.7978845608028654f;
@@ -139,9 +132,11 @@ __global__ void __launch_bounds__(256) k_pool(int nsub, const int64_t* __restric
   }
 }
 
-// xloc[vec_off[i] + l][j] += alpha * s_j * sum_k P[l][k] (c_re[k] + j c_im[k])
+// xloc[vec_off[i] + lpos[l]][j] += alpha * s_j * sum_k P[l][k] (c_re[k] + j c_im[k])
+// (lpos: dense row of the subdomain DOF row l)
 template <typename C>
-__global__ void __launch_bounds__(256) k_coarse_apply(const int64_t* __restrict__ dof_ptr,
+__global__ void __launch_bounds__(256) k_coarse_apply(const int32_t* __restrict__ lpos,
+                                                      const int64_t* __restrict__ dof_ptr,
                                                       const int64_t* __restrict__ vec_off, const float* __restrict__ P,
                                                       const float* __restrict__ Cn, int nsub, int nrhs, int j0, int nj,
                                                       const double* __restrict__ scale, float alpha,
@@ -176,7 +171,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply(const int64_t* __restrict_
       re += p.x * c0.x + p.y * c1.x + p.z * c2.x + p.w * c3.x;
       im += p.x * c0.y + p.y * c1.y + p.z * c2.y + p.w * c3.y;
     }
-    const int64_t o = (vec_off[i] + (row - r0)) * nrhs + j0 + j;
+    const int64_t o = (vec_off[i] + lpos[row]) * nrhs + j0 + j;
     C x = xloc[o];
     x.x += f * re;
     x.y += f * im;
@@ -212,20 +207,38 @@ __global__ void __launch_bounds__(192) k_pdp(const int64_t* __restrict__ dof_ptr
 // ---------------------------------------------------------------------------
 // GEMM: C[m][n] (= or +=) sum_k a(m,k) b(k,n) (+ bias[n]), optional GELU with
 // the pre-activation kept in Z; a(m,k) = TA ? A[k*lda+m] : A[m*lda+k],
-// b(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n].  64x64 tiles, 16-deep K steps staged
-// in LDS (rounded to bf16 when rnd), 4 waves x (2x2) 16x16x4 MFMA tiles.
-// gridDim.z > 1 splits K; each split writes its own slice C + z*M*ldc.
+// b(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n].  Operands rounded to bfloat16
+// (round to nearest even) as they are staged into LDS, products on the bf16
+// matrix cores (16x16x32, FP32 accumulation: a bf16 x bf16 product is exact
+// in FP32, so the result differs from FP32 arithmetic on the rounded operands
+// only in the order of the additions). 64x64 tiles, 32-deep K chunks, both
+// operands stored k-contiguous in LDS so that a lane's eight k values are
+// one 16-byte read; 4 waves x (2x2) MFMA tiles. gridDim.z > 1 splits K; each
+// split writes its own slice C + z*M*ldc.
 // ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ inline unsigned short bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u)  // inf stays inf, a NaN stays a NaN
+    return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+constexpr int GK = 32;       // K chunk
+constexpr int GKP = GK + 8;  // LDS row pitch (bf16 values): 80 bytes
+
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
                                               const float* __restrict__ B, int ldb, float* __restrict__ Cm, int ldc,
                                               int beta, const float* __restrict__ bias, int act,
-                                              float* __restrict__ Z, int rnd) {
-  __shared__ float As[64][17];
-  __shared__ float Bs[16][65];
+                                              float* __restrict__ Z) {
+  __shared__ __attribute__((aligned(16))) unsigned short As[64][GKP];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[64][GKP];
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int nsplit = gridDim.z;
-  const int kchunk = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
+  const int kchunk = ((K + nsplit - 1) / nsplit + GK - 1) / GK * GK;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
@@ -234,32 +247,34 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* 
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-    for (int e = tid; e < 64 * 16; e += 256) {
-      int mm = e / 16, kk = e % 16;
-      int gm = m0 + mm, gk = k0 + kk;
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+#pragma unroll
+    for (int q = 0; q < 64 * GK / 256; ++q) {
+      const int e = tid + 256 * q;
+      // thread -> element maps that read consecutive addresses
+      const int mm = TA ? e % 64 : e / GK, ka = TA ? e / 64 : e % GK;
+      const int gm = m0 + mm, gka = k0 + ka;
       float va = 0.f;
-      if (gm < M && gk < ke) va = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-      As[mm][kk] = rnd ? bf16r(va) : va;
-      int kk2 = e / 64, nn = e % 64;
-      int gk2 = k0 + kk2, gn = n0 + nn;
+      if (gm < M && gka < ke) va = TA ? A[(int64_t)gka * lda + gm] : A[(int64_t)gm * lda + gka];
+      As[mm][ka] = bf16_bits(va);
+      const int nn = TB ? e / GK : e % 64, kb2 = TB ? e % GK : e / 64;
+      const int gn = n0 + nn, gkb = k0 + kb2;
       float vb = 0.f;
-      if (gn < N && gk2 < ke) vb = TB ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
-      Bs[kk2][nn] = rnd ? bf16r(vb) : vb;
+      if (gn < N && gkb < ke) vb = TB ? B[(int64_t)gn * ldb + gkb] : B[(int64_t)gkb * ldb + gn];
+      Bs[nn][kb2] = bf16_bits(vb);
     }
     __syncthreads();
+    bf16x8_t av[2], bv[2];
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
-      float av[2], bv[2];
+    for (int a = 0; a < 2; ++a)
+      av[a] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(&As[wr + 16 * a + (lane & 15)][8 * (lane >> 4)]));
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[wr + 16 * a + (lane & 15)][kk + (lane >> 4)];
+    for (int b = 0; b < 2; ++b)
+      bv[b] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(&Bs[wc + 16 * b + (lane & 15)][8 * (lane >> 4)]));
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wc + 16 * b + (lane & 15)];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma(av[a], bv[b], acc[a][b]);
-    }
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
     __syncthreads();
   }
   float* Cz = Cm + (int64_t)blockIdx.z * M * ldc;
@@ -412,15 +427,14 @@ void launch_pool(hipStream_t s, int nsub, const int64_t* dof_ptr, const int32_t*
 }
 
 template <typename C>
-void launch_coarse_apply(hipStream_t s, int64_t nrows, const int32_t* row_sub, const int64_t* dof_ptr,
+void launch_coarse_apply(hipStream_t s, int64_t nrows, const int32_t* lpos, const int64_t* dof_ptr,
                          const int64_t* vec_off, const float* P, const float* Cn, int nsub, int nrhs,
                          const double* scale, float alpha, C* xloc) {
-  (void)row_sub;
   if (nrows <= 0 || nsub <= 0) return;
   for (int j0 = 0; j0 < nrhs; j0 += 32) {
     const int nj = nrhs - j0 < 32 ? nrhs - j0 : 32;
-    hipLaunchKernelGGL(k_coarse_apply<C>, dim3(nsub, 8), dim3(256), 0, s, dof_ptr, vec_off, P, Cn, nsub, nrhs, j0,
-                       nj, scale, alpha, xloc);
+    hipLaunchKernelGGL(k_coarse_apply<C>, dim3(nsub, 8), dim3(256), 0, s, lpos, dof_ptr, vec_off, P, Cn, nsub, nrhs,
+                       j0, nj, scale, alpha, xloc);
   }
 }
 template void launch_coarse_apply<float2>(hipStream_t, int64_t, const int32_t*, const int64_t*, const int64_t*,
@@ -447,9 +461,10 @@ void launch_gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, const flo
     out = work;
     b = 0;
   }
+  (void)rnd;  // operands are always rounded to bf16 (the network's arithmetic)
 #define MXG(TA_, TB_) \
   hipLaunchKernelGGL((k_gemm<TA_, TB_>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, ldc, b, \
-                     nsplit > 1 ? nullptr : bias, nsplit > 1 ? 0 : act, Z, rnd)
+                     nsplit > 1 ? nullptr : bias, nsplit > 1 ? 0 : act, Z)
   if (!ta && !tb) MXG(false, false);
   else if (!ta && tb) MXG(false, true);
   else if (ta && !tb) MXG(true, false);

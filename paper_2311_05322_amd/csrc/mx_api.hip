@@ -260,8 +260,16 @@ struct mx_ctx {
   // decomposition
   Decomposition dec;
   bool have_dec = false;
-  DBuf<int32_t> dofs, Npad, order, trsm_order, if_tet, if_lf, lsrc, p_edge, piv, status, pswap, perm, rowsrc;
+  DBuf<int32_t> dofs, Npad, order, trsm_order, if_tet, if_lf, lsrc, p_edge, piv, status, pswap, perm, rowsrc, lpos,
+      dense_edge;
   DBuf<int64_t> dof_ptr, mat_off, vec_off, ldest, lptr, p_row;
+  // band bookkeeping of the factorisation (LuBand) and the triangular-solve
+  // ranges derived from it; lu_tiles / trsm_tiles: 64x64 tile products of the
+  // last factorisation and of one lower + upper solve per right-hand side
+  DBuf<int32_t> ext_l, ext_u, tbox, trs_lo, trs_hi;
+  DBuf<int64_t> tptr, band_work;
+  int band_np = 0;
+  int64_t lu_tiles = 0, trsm_tiles_l = 0, trsm_tiles_u = 0;
   DBuf<double> p_w;
   std::vector<int32_t> Nsorted;
   DBuf<char> factors;
@@ -576,7 +584,7 @@ void coarse_correct(mx_ctx* c, const double2* v, C* xl, int nrhs) {
   launch_scale_f(s, (int64_t)nrhs * D.nsub * NIN, B.X, (float)(1.0 / c->sx));
   net_forward(c, nrhs, B);
   launch_nonfinite(s, (int64_t)nrhs * D.nsub * NIN, B.OUT, c->cflag.p);
-  launch_coarse_apply<C>(s, D.dof_ptr[D.nsub], c->row_sub.p, c->dof_ptr.p, c->vec_off.p, c->cP.p, B.OUT, D.nsub,
+  launch_coarse_apply<C>(s, D.dof_ptr[D.nsub], c->lpos.p, c->dof_ptr.p, c->vec_off.p, c->cP.p, B.OUT, D.nsub,
                          nrhs, c->cscale.p, (float)c->sy, xl);
 }
 
@@ -596,7 +604,8 @@ void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2*
   launch_restrict<C>(c->stream, nrows, c->rowsrc.p, v, xl, nrhs);
   if (tm) tm->end(K_RESTRICT);
   launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p,
-                 c->tune_trsm_paired ? c->trsm_order.p : c->order.p, xl, D.nsub, nrhs, tm);
+                 c->tune_trsm_paired ? c->trsm_order.p : c->order.p, xl, D.nsub, nrhs, c->trs_lo.p, c->trs_hi.p,
+                 c->band_np, tm);
   const bool coarse = !local && c->coarse_use && !c->coarse_off_now && c->coarse_geom && c->coarse_weights;
   C* xq = nullptr;
   if (coarse) {
@@ -695,10 +704,10 @@ int autotune_trsm(mx_ctx* c, int nrhs, hipEvent_t e0, hipEvent_t e1) {
   for (int v = 0; v < 2; ++v) {
     const int32_t* ord = v ? c->trsm_order.p : c->order.p;
     launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, ord, xl, D.nsub, nrhs,
-                   nullptr);
+                   c->trs_lo.p, c->trs_hi.p, c->band_np, nullptr);
     MX_HIP_CHECK(hipEventRecord(e0, c->stream));
     launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, ord, xl, D.nsub, nrhs,
-                   nullptr);
+                   c->trs_lo.p, c->trs_hi.p, c->band_np, nullptr);
     MX_HIP_CHECK(hipEventRecord(e1, c->stream));
     MX_HIP_CHECK(hipEventSynchronize(e1));
     float ms = 0;
@@ -760,7 +769,8 @@ uint64_t step_signature(const mx_ctx* c, int nrhs, int m, double rtol) {
   const void* ptrs[] = {c->V.p, c->Z.p, c->xloc.p, c->factors.p, c->val.p, c->row_ptr.p, c->col.p,
                         c->rowsrc.p, c->trsm_order.p, c->mat_off.p, c->Npad.p, c->vec_off.p, c->p_edge.p,
                         c->p_row.p, c->p_w.p, c->dotpart.p, c->normpart.p, c->h1.p, c->h2.p, c->hn.p, c->H.p,
-                        c->cs.p, c->sn.p, c->g.p, c->bnorm.p, c->conv.p, c->kdone.p, c->res.p};
+                        c->cs.p, c->sn.p, c->g.p, c->bnorm.p, c->conv.p, c->kdone.p, c->res.p, c->trs_lo.p,
+                        c->trs_hi.p};
   mix(ptrs, sizeof(ptrs));
   val(c->topo.ne);
   val(c->dec.nsub);
@@ -1518,6 +1528,44 @@ bool spd_inverse(std::vector<double>& A, int n) {
 }
 
 // lattices, prolongations and least-squares operators of the current decomposition
+// Ranges of the triangular solves from the band bookkeeping of the
+// factorisation: row tile t of L has non-zeros in the column tiles
+// [lo_t, t), lo_t = first panel whose L part reaches t; row tile t of U in
+// (t, ext_u[t]]. Also the tile counts of the factorisation and of one
+// lower + upper solve per right-hand side.
+int triangular_ranges(mx_ctx* c) {
+  const Decomposition& D = c->dec;
+  const int np = c->band_np;
+  const size_t n = (size_t)D.nsub * np;
+  std::vector<int32_t> el(n), eu(n), lo(n, 0);
+  int64_t work = 0;
+  MX_HIP_CHECK(hipMemcpyAsync(el.data(), c->ext_l.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  MX_HIP_CHECK(hipMemcpyAsync(eu.data(), c->ext_u.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  MX_HIP_CHECK(hipMemcpyAsync(&work, c->band_work.p, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  CK(sync(c));
+  int64_t tiles_l = 0, tiles_u = 0;
+  for (int s = 0; s < D.nsub; ++s) {
+    const int nt = D.Npad[s] / 64;
+    const int32_t* e = el.data() + (size_t)s * np;
+    int32_t* l = lo.data() + (size_t)s * np;
+    for (int t = 0; t < nt; ++t) {
+      int f = t;
+      for (int q = 0; q < t; ++q)
+        if (e[q] >= t) { f = q; break; }
+      l[t] = f;
+      // off-diagonal tiles of each solve plus the diagonal (inverse) tile
+      tiles_l += (t - f) + 1;
+      tiles_u += (std::min(eu[(size_t)s * np + t], nt - 1) - t) + 1;
+    }
+  }
+  CK(c->trs_lo.upload(lo, c->stream));
+  CK(c->trs_hi.upload(eu, c->stream));
+  c->lu_tiles = work;
+  c->trsm_tiles_l = tiles_l;
+  c->trsm_tiles_u = tiles_u;
+  return sync(c);
+}
+
 int coarse_prepare(mx_ctx* c) {
   const Topology& T = c->topo;
   const Decomposition& D = c->dec;
@@ -2021,6 +2069,8 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     CK(c->p_edge.upload(d.p_edge, c->stream));
     CK(c->p_row.upload(d.p_row, c->stream));
     CK(c->p_w.upload(d.p_w, c->stream));
+    CK(c->lpos.upload(d.lpos, c->stream));
+    CK(c->dense_edge.upload(d.dense_edge, c->stream));
     std::vector<int32_t> ord(nsub);
     for (int i = 0; i < nsub; ++i) ord[i] = i;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d.Npad[a] > d.Npad[b]; });
@@ -2033,6 +2083,14 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     CK(c->rowsrc.alloc(d.vec_off[nsub]));
     CK(c->status.alloc(nsub));
     CK(c->pswap.alloc((size_t)nsub * (2 * lu_max_swap_rows() + 1)));
+    c->band_np = c->Nsorted.empty() ? 0 : c->Nsorted[0] / 64;
+    CK(c->ext_l.alloc((size_t)nsub * c->band_np));
+    CK(c->ext_u.alloc((size_t)nsub * c->band_np));
+    CK(c->trs_lo.alloc((size_t)nsub * c->band_np));
+    CK(c->trs_hi.alloc((size_t)nsub * c->band_np));
+    CK(c->tptr.alloc((size_t)nsub + 1));
+    CK(c->tbox.alloc((size_t)2 * nsub));
+    CK(c->band_work.alloc(1));
     c->have_dec = true;
     c->pec_local_ready = false;
     c->ws_nrhs = 0;
@@ -2069,7 +2127,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
       std::vector<int32_t> idx;
       for (int sd = 0; sd < D.nsub; ++sd) {
         for (int64_t r = D.dof_ptr[sd]; r < D.dof_ptr[sd + 1]; ++r)
-          if (pec[D.dofs[r]]) idx.push_back((int32_t)(r - D.dof_ptr[sd]));
+          if (pec[D.dofs[r]]) idx.push_back(D.lpos[r]);
         ptr.push_back((int64_t)idx.size());
       }
       CK(c->pl_ptr.upload(ptr, c->stream));
@@ -2090,15 +2148,15 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((D.nsub + 255) / 256)), dim3(256), 0, c->stream, D.nsub,
                        c->status.p);
     MX_HIP_CHECK(hipEventRecord(c->ev_lu[0], c->stream));
+    const LuBand band{c->ext_l.p, c->ext_u.p, c->tptr.p, c->tbox.p, c->band_work.p, c->band_np};
     if (o.precision == MX_PREC_C64)
       launch_lu<float>(c->stream, (float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
-                       c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, &c->prof);
+                       c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, &c->prof);
     else
       launch_lu<double>(c->stream, (double2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
-                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, &c->prof);
+                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, &c->prof);
     c->prof.begin(K_LU_INV);
-    launch_perm(c->stream, D.nsub, c->Npad.p, c->vec_off.p, c->dof_ptr.p, c->dofs.p, c->piv.p, c->perm.p,
-                c->rowsrc.p);
+    launch_perm(c->stream, D.nsub, c->Npad.p, c->vec_off.p, c->dense_edge.p, c->piv.p, c->perm.p, c->rowsrc.p);
     c->prof.end(K_LU_INV);
     MX_HIP_CHECK(hipEventRecord(c->ev_lu[1], c->stream));
     MX_HIP_CHECK(hipGetLastError());
@@ -2112,6 +2170,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     float lu_ms = 0;
     MX_HIP_CHECK(hipEventElapsedTime(&lu_ms, c->ev_lu[0], c->ev_lu[1]));
     c->t_lu = 1e-3 * lu_ms;
+    CK(triangular_ranges(c));
     c->factored = true;
   } else {
     c->t_lu = 0;
@@ -2455,6 +2514,11 @@ int mx_get_sizes(mx_ctx* c, mx_sizes* o) {
     o->sum_Ni2 = c->dec.mat_off[c->dec.nsub];
     o->nb = c->dec.nb;
   }
+  if (c->factored) {
+    o->lu_tiles = c->lu_tiles;
+    o->trsm_tiles_lower = c->trsm_tiles_l;
+    o->trsm_tiles_upper = c->trsm_tiles_u;
+  }
   return MX_OK;
 }
 
@@ -2508,8 +2572,19 @@ int mx_get_local_matrix(mx_ctx* c, int32_t i, mx_c128* B) {
     hipLaunchKernelGGL(k_extract_local<double2>, dim3(g), dim3(256), 0, c->stream, n, N,
                        (const double2*)c->factors.p + D.mat_off[i], tmp.p);
   MX_HIP_CHECK(hipGetLastError());
-  MX_HIP_CHECK(hipMemcpyAsync(B, tmp.p, (size_t)n * n * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
-  return sync(c);
+  std::vector<double2> h((size_t)n * n);
+  MX_HIP_CHECK(hipMemcpyAsync(h.data(), tmp.p, h.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  CK(sync(c));
+  // dense rows are in the subdomain's reverse Cuthill-McKee order: back to
+  // the sorted DOF order of the interface
+  const int32_t* lp = D.lpos.data() + D.dof_ptr[i];
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const double2 v = h[(size_t)lp[a] * n + lp[b]];
+      B[(size_t)a * n + b].re = v.x;
+      B[(size_t)a * n + b].im = v.y;
+    }
+  return MX_OK;
 }
 
 

@@ -60,7 +60,7 @@ void launch_coarse_P(hipStream_t s, int64_t nrows, const int32_t* row_sub, const
 void launch_pool(hipStream_t s, int nsub, const int64_t* dof_ptr, const int32_t* dofs, const float* P,
                  const double* wts, const double2* v, int nrhs, const double* scale, float* X);
 template <typename C>
-void launch_coarse_apply(hipStream_t s, int64_t nrows, const int32_t* row_sub, const int64_t* dof_ptr,
+void launch_coarse_apply(hipStream_t s, int64_t nrows, const int32_t* lpos, const int64_t* dof_ptr,
                          const int64_t* vec_off, const float* P, const float* Cn, int nsub, int nrhs,
                          const double* scale, float alpha, C* xloc);
 void launch_gapply(hipStream_t s, int nsub, int nrhs, const double* G, const float* in, float* out);
@@ -93,15 +93,32 @@ void launch_prolong(hipStream_t s, int64_t n, const int32_t* edge, const int64_t
                     const C* zloc, double2* z, int nrhs);
 
 // dense subdomain factorisation and solves
+// Band bookkeeping of the factorisation (device arrays, np = N_max / 64 per
+// subdomain): ext_l[s*np + p] = last 64-row tile with a non-zero in the L
+// part of panel p, ext_u[s*np + p] = last 64-column tile with a non-zero in
+// its U part (p itself when there is none); tptr [nsub+1] / tbox [2 nsub]:
+// tile lists of one trailing update; work[0]: 64x64x64 complex tile products
+// of the factorisation.
+struct LuBand {
+  int32_t* ext_l;
+  int32_t* ext_u;
+  int64_t* tptr;
+  int32_t* tbox;
+  int64_t* work;
+  int np;
+};
 template <typename R>
 void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
                int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
-               const std::vector<int32_t>& Nsorted, KTimer* tm);
-void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int64_t* dof_ptr,
-                 const int32_t* dofs, const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc);
+               const std::vector<int32_t>& Nsorted, const LuBand& band, KTimer* tm);
+void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int32_t* dense_edge,
+                 const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc);
 template <typename R>
+// trs_lo[s*np + t]: first 64-column tile of row tile t's L part; trs_hi: last
+// column tile of its U part (from the band bookkeeping of the factorisation)
 void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
-                 const int64_t* vec_off, const int32_t* order, C_t<R>* xloc, int nsub, int nrhs, KTimer* tm);
+                 const int64_t* vec_off, const int32_t* order, C_t<R>* xloc, int nsub, int nrhs,
+                 const int32_t* trs_lo, const int32_t* trs_hi, int np, KTimer* tm);
 int lu_max_swap_rows();
 
 // Krylov
