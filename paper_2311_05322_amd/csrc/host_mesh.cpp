@@ -468,6 +468,9 @@ std::string build_decomposition(const Topology& T, int32_t nsub, int32_t overlap
   // graph of DOFs that share a tetrahedron of the subdomain
   Dc.lpos.assign(Dc.dof_ptr[nsub], 0);
   Dc.dense_edge.assign(Dc.vec_off[nsub], -1);
+  Dc.band_np = 0;
+  for (int32_t i = 0; i < nsub; ++i) Dc.band_np = std::max(Dc.band_np, Dc.Npad[i] / nb);
+  Dc.band0.assign((size_t)nsub * Dc.band_np, -1);
 #pragma omp parallel
   {
     std::vector<int32_t> loc(T.ne, -1);
@@ -494,6 +497,19 @@ std::string build_decomposition(const Topology& T, int32_t nsub, int32_t overlap
       for (int32_t r = 0; r < n; ++r) {
         Dc.lpos[Dc.dof_ptr[i] + ord[r]] = r;
         Dc.dense_edge[Dc.vec_off[i] + r] = Dc.dofs[Dc.dof_ptr[i] + ord[r]];
+      }
+      // structural band: last row of each dense column (the diagonal, the
+      // padding identity and every pair of DOFs sharing a tetrahedron)
+      const int32_t Ni = Dc.Npad[i];
+      std::vector<int32_t> colmax(Ni);
+      for (int32_t r = 0; r < Ni; ++r) colmax[r] = r;
+      for (auto& pr : pairs) {
+        const int32_t ra = Dc.lpos[Dc.dof_ptr[i] + pr.first], rb = Dc.lpos[Dc.dof_ptr[i] + pr.second];
+        colmax[rb] = std::max(colmax[rb], ra);
+      }
+      for (int32_t c = 0; c < Ni; ++c) {
+        int32_t& b = Dc.band0[(size_t)i * Dc.band_np + c / nb];
+        b = std::max(b, colmax[c] / nb);
       }
       for (int64_t k = Dc.dof_ptr[i]; k < Dc.dof_ptr[i + 1]; ++k) loc[Dc.dofs[k]] = -1;
     }

@@ -67,6 +67,12 @@ struct Decomposition {
   // (global edge of each dense row, -1 on the padding rows)
   std::vector<int32_t> lpos;          // [sum n_i]
   std::vector<int32_t> dense_edge;    // [sum N_i]
+  // band0[i * band_np + p]: last 64-row tile holding a structural non-zero
+  // of the columns of panel p of the dense matrix in that order (the matrix
+  // pattern is symmetric, so it is also the last column tile of its rows);
+  // band_np = max N_i / 64
+  int32_t band_np = 0;
+  std::vector<int32_t> band0;
   // padded dense sizes and offsets of the local matrices
   std::vector<int32_t> Npad;          // [nsub]
   std::vector<int64_t> mat_off;       // [nsub+1] offsets in entries

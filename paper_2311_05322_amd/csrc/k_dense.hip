@@ -64,12 +64,16 @@ template <typename R, int RPT>
 __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                  const int32_t* __restrict__ Npad, const int32_t* __restrict__ order,
                                                  int32_t* __restrict__ piv, const int64_t* __restrict__ vec_off,
-                                                 int32_t* __restrict__ status, int32_t* __restrict__ pswap, int k0) {
+                                                 int32_t* __restrict__ status, int32_t* __restrict__ pswap,
+                                                 const int32_t* __restrict__ lim, int k0) {
   typedef C_t<R> C;
   constexpr int W = PanelW<R>::W;
   const int s = order[blockIdx.x];
   const int N = Npad[s];
   if (k0 >= N) return;
+  // rows at and beyond Nr are zero in the panel's columns (band bookkeeping):
+  // they are neither read nor written, and never a pivot
+  const int Nr = lim[3 * s];
   C* A = pool + mat_off[s];
   int32_t* pv = piv + vec_off[s];
   const int tid = threadIdx.x;
@@ -123,7 +127,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = c0 + tid + PT * i;
-      if (r < N) {
+      if (r < Nr) {
         const C* row = A + (int64_t)r * N;
 #pragma unroll
         for (int j = 0; j < W; ++j) a[i][j] = row[c0 + j];
@@ -162,7 +166,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int r = c0 + tid + PT * i;
-        if (r < N && r >= c) {
+        if (r < Nr && r >= c) {
           R v = fabs(a[i][j].x) + fabs(a[i][j].y);
           if (v > best || (v == best && r < brow)) { best = v; brow = r; }
         }
@@ -181,7 +185,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
           if (red_v[w] > b || (red_v[w] == b && red_r[w] < br)) { b = red_v[w]; br = red_r[w]; }
         // no usable pivot (zero or non-finite column): keep the row order so
         // every later access stays inside the matrix, and report the column
-        if (!(b > 0) || br < c || br >= N) {
+        if (!(b > 0) || br < c || br >= Nr) {
           br = c;
           b = 0;
           if (status[s] == 0) status[s] = c + 1;
@@ -238,7 +242,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int r = c0 + tid + PT * i;
-        if (r < N && r > c) {
+        if (r < Nr && r > c) {
           C l = cmulT(a[i][j], inv);
           a[i][j] = l;
 #pragma unroll
@@ -251,7 +255,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = c0 + tid + PT * i;
-      if (r < N) {
+      if (r < Nr) {
 #pragma unroll
         for (int j = 0; j < W; ++j) A[(int64_t)r * N + c0 + j] = a[i][j];
       }
@@ -319,7 +323,8 @@ template <typename R, int XR>
 __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                      const int32_t* __restrict__ Npad,
                                                      const int32_t* __restrict__ order,
-                                                     const int32_t* __restrict__ pswap, int k0, int mode) {
+                                                     const int32_t* __restrict__ pswap,
+                                                     const int32_t* __restrict__ lim, int k0, int mode) {
   typedef C_t<R> C;
   typedef Acc_t<R> Acc;
   const int s = order[blockIdx.y];
@@ -327,6 +332,9 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
   const int cb = blockIdx.x * NB;
   if (cb >= N || cb == k0 || k0 >= N) return;
   if (mode == 2 && cb < k0) return;
+  // outside [lim2, lim1) every row the panel touches is zero: nothing moves
+  // and U12 is zero there
+  if (cb >= lim[3 * s + 1] || cb < lim[3 * s + 2]) return;
   C* A = pool + mat_off[s];
   const int32_t* ps = pswap + (int64_t)s * (2 * MAXSW + 1);
   const int n = mode == 2 ? NB : ps[0];
@@ -390,13 +398,15 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_lu_rowswap(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                     const int32_t* __restrict__ Npad,
                                                     const int32_t* __restrict__ order,
-                                                    const int32_t* __restrict__ pswap, int k0) {
+                                                    const int32_t* __restrict__ pswap,
+                                                    const int32_t* __restrict__ lim, int k0) {
   typedef C_t<R> C;
   constexpr int PER = MAXSW * NB / 256;
   const int s = order[blockIdx.y];
   const int N = Npad[s];
   const int cb = blockIdx.x * NB;
   if (cb >= N || cb == k0 || k0 >= N) return;  // the whole workgroup
+  if (cb >= lim[3 * s + 1] || cb < lim[3 * s + 2]) return;
   C* A = pool + mat_off[s];
   const int32_t* ps = pswap + (int64_t)s * (2 * MAXSW + 1);
   const int n = ps[0];
@@ -566,7 +576,8 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_band_l(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                 const int32_t* __restrict__ Npad, const int32_t* __restrict__ order,
                                                 const int32_t* __restrict__ piv, const int64_t* __restrict__ vec_off,
-                                                int np, int32_t* __restrict__ ext_l, int k) {
+                                                int np, int32_t* __restrict__ ext_l, const int32_t* __restrict__ lim,
+                                                int k) {
   const int s = order[blockIdx.x];
   const int N = Npad[s];
   if (k >= N) return;
@@ -574,7 +585,7 @@ __global__ void __launch_bounds__(256) k_band_l(const C_t<R>* __restrict__ pool,
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __shared__ int last[4];
   int found = -1;
-  for (int r = N - 1 - w; r >= k + NB; r -= 4) {
+  for (int r = min(N, lim[3 * s]) - 1 - w; r >= k + NB; r -= 4) {
     if (wave_any_nonzero(A[(int64_t)r * N + k + lane])) {
       found = r;
       break;
@@ -600,7 +611,8 @@ __global__ void __launch_bounds__(256) k_band_l(const C_t<R>* __restrict__ pool,
 template <typename R>
 __global__ void __launch_bounds__(256) k_band_u(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
                                                 const int32_t* __restrict__ Npad, const int32_t* __restrict__ order,
-                                                int np, int32_t* __restrict__ ext_u, int k) {
+                                                int np, int32_t* __restrict__ ext_u, const int32_t* __restrict__ lim,
+                                                int k) {
   const int s = order[blockIdx.x];
   const int N = Npad[s];
   if (k >= N) return;
@@ -609,7 +621,7 @@ __global__ void __launch_bounds__(256) k_band_u(const C_t<R>* __restrict__ pool,
   __shared__ int last[4];
   const int p = k / NB;
   int found = -1;
-  for (int ct = N / NB - 1 - w; ct > p && found < 0; ct -= 4) {
+  for (int ct = min(N, lim[3 * s + 1]) / NB - 1 - w; ct > p && found < 0; ct -= 4) {
     for (int r = 0; r < NB; ++r)
       if (wave_any_nonzero(A[(int64_t)(k + r) * N + NB * ct + lane])) {
         found = ct;
@@ -621,6 +633,43 @@ __global__ void __launch_bounds__(256) k_band_u(const C_t<R>* __restrict__ pool,
   if (threadIdx.x == 0) {
     const int cmax = max(max(last[0], last[1]), max(last[2], last[3]));
     ext_u[(int64_t)s * np + p] = cmax >= 0 ? cmax : p;
+  }
+}
+
+// Bounds of the panel at column k for every active subdomain (before it is
+// factored): rows of its columns that can hold non-zeros, [k, lim0), and
+// columns its rows can, [lim2, lim1). Non-zeros below the structural band
+// band0 come only from earlier panels q whose L part reaches the panel's
+// rows (ext_l[q] >= p): their updates (rows <= ext_l[q], columns <= ext_u[q])
+// and their row interchanges (rows <= ext_l[q]); left of the panel a row
+// holds L values of exactly those panels.
+__global__ void __launch_bounds__(256) k_band_limits(int nact, const int32_t* __restrict__ Npad,
+                                                     const int32_t* __restrict__ order, int np,
+                                                     const int32_t* __restrict__ band0,
+                                                     const int32_t* __restrict__ ext_l,
+                                                     const int32_t* __restrict__ ext_u, int32_t* __restrict__ lim,
+                                                     int k) {
+  for (int z = blockIdx.x * blockDim.x + threadIdx.x; z < nact; z += gridDim.x * blockDim.x) {
+    const int s = order[z];
+    const int N = Npad[s];
+    if (k >= N) continue;
+    const int p = k / NB, nt = N / NB;
+    const int32_t* el = ext_l + (int64_t)s * np;
+    const int32_t* eu = ext_u + (int64_t)s * np;
+    const int32_t* b0 = band0 + (int64_t)s * np;
+    int re = b0[p], ce = -1, lo = p;
+    for (int q = 0; q < p; ++q)
+      if (el[q] >= p) {
+        re = max(re, el[q]);
+        ce = max(ce, eu[q]);
+        lo = min(lo, q);
+      }
+    re = min(re, nt - 1);
+    for (int t = p; t <= re; ++t) ce = max(ce, b0[t]);
+    ce = min(max(ce, p), nt - 1);
+    lim[3 * s] = NB * (re + 1);
+    lim[3 * s + 1] = NB * (ce + 1);
+    lim[3 * s + 2] = NB * lo;
   }
 }
 
@@ -1029,20 +1078,20 @@ inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) /
 template <typename R>
 static void launch_panel(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
                          const int32_t* order, int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
-                         int Nmax, int nact, int k0) {
+                         const int32_t* lim, int Nmax, int nact, int k0) {
   const int m = Nmax - k0;
   if (m <= PT * 1)
     hipLaunchKernelGGL((k_lu_panel<R, 1>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
-                       status, pswap, k0);
+                       status, pswap, lim, k0);
   else if (m <= PT * 2)
     hipLaunchKernelGGL((k_lu_panel<R, 2>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
-                       status, pswap, k0);
+                       status, pswap, lim, k0);
   else if (m <= PT * 4)
     hipLaunchKernelGGL((k_lu_panel<R, 4>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
-                       status, pswap, k0);
+                       status, pswap, lim, k0);
   else
     hipLaunchKernelGGL((k_lu_panel<R, 8>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
-                       status, pswap, k0);
+                       status, pswap, lim, k0);
 }
 
 // Batched LU with partial pivoting of all subdomain matrices (largest first,
@@ -1091,17 +1140,19 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
       const int pk = ki / NB;
       if (i > 0) update(nact, pa, pk, pk, pk, 1, g0, i * NB);
       MX_TB(K_LU_PANEL);
-      launch_panel<R>(st, pool, mat_off, Npad, order, piv, vec_off, status, pswap, Nmax, nact, ki);
+      hipLaunchKernelGGL(k_band_limits, dim3(ceil_div(nact, 256)), dim3(256), 0, st, nact, Npad, order, np, band.band0,
+                         band.ext_l, band.ext_u, band.lim, ki);
+      launch_panel<R>(st, pool, mat_off, Npad, order, piv, vec_off, status, pswap, band.lim, Nmax, nact, ki);
       hipLaunchKernelGGL((k_band_l<R>), dim3(nact), dim3(256), 0, st, pool, mat_off, Npad, order, piv, vec_off, np,
-                         band.ext_l, ki);
+                         band.ext_l, band.lim, ki);
       MX_TE(K_LU_PANEL);
       MX_TB(K_LU_ROWPANEL);
       if (i > 0 && sizeof(R) == 4)  // complex64: the moved values fit in registers
         hipLaunchKernelGGL((k_lu_rowswap<R>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad, order, pswap,
-                           ki);
+                           band.lim, ki);
       else
         hipLaunchKernelGGL((k_lu_rowpanel<R, MAXSW>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad,
-                           order, pswap, ki, i == 0 ? 0 : 1);
+                           order, pswap, band.lim, ki, i == 0 ? 0 : 1);
       MX_TE(K_LU_ROWPANEL);
       const int kn = ki + NB;
       if (kn >= Nmax) continue;
@@ -1109,11 +1160,12 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
         update(nact, pa, pk, pk, kn / NB, 2, g0, i * NB);
         MX_TB(K_LU_ROWPANEL);
         hipLaunchKernelGGL((k_lu_rowpanel<R, NB>), dim3(ctiles, nact), dim3(256), 0, st, pool, mat_off, Npad, order,
-                           pswap, ki, 2);
+                           pswap, band.lim, ki, 2);
         MX_TE(K_LU_ROWPANEL);
       }
       MX_TB(K_LU_ROWPANEL);
-      hipLaunchKernelGGL((k_band_u<R>), dim3(nact), dim3(256), 0, st, pool, mat_off, Npad, order, np, band.ext_u, ki);
+      hipLaunchKernelGGL((k_band_u<R>), dim3(nact), dim3(256), 0, st, pool, mat_off, Npad, order, np, band.ext_u,
+                         band.lim, ki);
       MX_TE(K_LU_ROWPANEL);
     }
     const int ke = g0 + LU_GROUP * NB;

@@ -266,7 +266,7 @@ struct mx_ctx {
   // band bookkeeping of the factorisation (LuBand) and the triangular-solve
   // ranges derived from it; lu_tiles / trsm_tiles: 64x64 tile products of the
   // last factorisation and of one lower + upper solve per right-hand side
-  DBuf<int32_t> ext_l, ext_u, tbox, trs_lo, trs_hi;
+  DBuf<int32_t> ext_l, ext_u, tbox, trs_lo, trs_hi, band0, band_lim;
   DBuf<int64_t> tptr, band_work;
   int band_np = 0;
   int64_t lu_tiles = 0, trsm_tiles_l = 0, trsm_tiles_u = 0;
@@ -2083,7 +2083,9 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     CK(c->rowsrc.alloc(d.vec_off[nsub]));
     CK(c->status.alloc(nsub));
     CK(c->pswap.alloc((size_t)nsub * (2 * lu_max_swap_rows() + 1)));
-    c->band_np = c->Nsorted.empty() ? 0 : c->Nsorted[0] / 64;
+    c->band_np = d.band_np;
+    CK(c->band0.upload(d.band0, c->stream));
+    CK(c->band_lim.alloc((size_t)3 * nsub));
     CK(c->ext_l.alloc((size_t)nsub * c->band_np));
     CK(c->ext_u.alloc((size_t)nsub * c->band_np));
     CK(c->trs_lo.alloc((size_t)nsub * c->band_np));
@@ -2148,7 +2150,8 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((D.nsub + 255) / 256)), dim3(256), 0, c->stream, D.nsub,
                        c->status.p);
     MX_HIP_CHECK(hipEventRecord(c->ev_lu[0], c->stream));
-    const LuBand band{c->ext_l.p, c->ext_u.p, c->tptr.p, c->tbox.p, c->band_work.p, c->band_np};
+    const LuBand band{c->ext_l.p, c->ext_u.p, c->tptr.p, c->tbox.p, c->band_work.p, c->band0.p, c->band_lim.p,
+                      c->band_np};
     if (o.precision == MX_PREC_C64)
       launch_lu<float>(c->stream, (float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, &c->prof);

@@ -99,12 +99,17 @@ void launch_prolong(hipStream_t s, int64_t n, const int32_t* edge, const int64_t
 // its U part (p itself when there is none); tptr [nsub+1] / tbox [2 nsub]:
 // tile lists of one trailing update; work[0]: 64x64x64 complex tile products
 // of the factorisation.
+// band0[s*np + p]: last row tile with a structural non-zero in the columns
+// of panel p before elimination; lim[3s..3s+2]: rows [k, lim0) of the current
+// panel that can hold non-zeros and the columns [lim2, lim1) its rows can.
 struct LuBand {
   int32_t* ext_l;
   int32_t* ext_u;
   int64_t* tptr;
   int32_t* tbox;
   int64_t* work;
+  const int32_t* band0;
+  int32_t* lim;
   int np;
 };
 template <typename R>
