@@ -252,7 +252,7 @@ def main():
     ap.add_argument("--ref-steps", type=int, default=5,
                     help="timed steps of the variants other than the headline (at most --steps)")
     ap.add_argument("--workload", default="chamber1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=15)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference variants")
     ap.add_argument("--no-learned", action="store_true", help="headline without the learned coarse term")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -75,7 +75,7 @@ typedef struct {
 /* Options of the Schwarz preconditioner and the Krylov solver. */
 typedef struct {
   int32_t precision;   /* MX_PREC_C128 or MX_PREC_C64 */
-  int32_t restart;     /* FGMRES restart length m (default 30 when <= 0) */
+  int32_t restart;     /* FGMRES restart length m (default 15 when <= 0) */
   int32_t maxit;       /* iteration cap (default 2000 when <= 0) */
   int32_t factor;      /* 1: factor the subdomain matrices (normal use);
                           0: keep them assembled (mx_get_local_matrix only) */
@@ -180,16 +180,24 @@ int mx_set_stream(mx_ctx* ctx, void* hip_stream);
  *   SpMM: 0 = one lane per right-hand side, non-zeros read by every lane;
  *         1 = 32 lanes per row, each non-zero read once and broadcast
  *             (nrhs <= 32 only);
- *   triangular-solve workgroup order: 1 = b-th largest subdomain paired with
- *         the b-th smallest, 0 = largest first.
- * enable = 0 switches it off and restores variant 0 / paired order. */
+ *   triangular solves: workgroup order (1 = b-th largest subdomain paired
+ *         with the b-th smallest, 0 = largest first) x right-hand-side
+ *         columns per workgroup (32, or 16 with twice the workgroups and
+ *         four resident per compute unit).
+ * enable = 0 switches it off and restores variant 0 / paired order / 32. */
 typedef struct {
   int32_t spmm_variant;
   int32_t trsm_paired;
+  int32_t trsm_cols;
   double spmm_ms[2];   /* average time of one SpMM per variant (0 if not run) */
-  double trsm_ms[2];   /* one lower + upper solve: [largest first, paired]     */
+  double trsm_ms[4];   /* one lower + upper solve: [largest first / 32 columns,
+                          paired / 32, largest first / 16, paired / 16]      */
 } mx_tuning;
 int mx_set_autotune(mx_ctx* ctx, int enable);
+/* Fix the variants (switches the autotuner off): spmm_variant 0/1,
+ * trsm_paired 0/1, trsm_cols 16/32. Results do not depend on the variants
+ * beyond rounding. Errors: MX_EINVAL. */
+int mx_set_tuning(mx_ctx* ctx, int32_t spmm_variant, int32_t trsm_paired, int32_t trsm_cols);
 int mx_get_tuning(mx_ctx* ctx, mx_tuning* out);
 
 /* Krylov solver of every solve (mx_solve, mx_solve_rhs, mx_solve_ports and
@@ -276,7 +284,7 @@ int mx_assemble(mx_ctx* ctx, const mx_mesh* mesh, const mx_c128* eps, int eps_ki
  * of unity, local matrices with impedance transmission conditions, and the
  * batched dense LU of all subdomain matrices (one set of launches).  The
  * partition is cached while the mesh, nsub and overlap are unchanged.
- * opts may be NULL (complex128, restart 30, maxit 2000, factor 1).
+ * opts may be NULL (complex128, restart 15, maxit 2000, factor 1).
  * Errors: MX_EINVAL (nsub not a power of two, overlap < 1), MX_EPIVOT (a
  * subdomain matrix has a column with no usable pivot: zero or non-finite,
  * e.g. entries beyond the complex64 range; the message names the subdomain

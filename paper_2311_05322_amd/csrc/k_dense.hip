@@ -846,7 +846,6 @@ __global__ void __launch_bounds__(64) k_perm(int32_t nsub, const int32_t* __rest
 // --------------------------------------------------------------------------
 constexpr int SB = 256;
 constexpr int KC = 16;
-constexpr int RC = 32;
 template <typename R> struct TrsmShape;
 template <> struct TrsmShape<float> { static constexpr int RT = 4; };
 template <> struct TrsmShape<double> { static constexpr int RT = 2; };
@@ -868,14 +867,14 @@ __device__ inline C_t<R> diag_inv_elem(const C_t<R>* A, int N, int b0, int i, in
 // k = kc + 4*(lane/16) + s4: the factor row 16*rt + lane%16 is read as 4
 // consecutive complex values per lane, and the right-hand-side rows with the
 // same permuted k, columns 16*ct + lane%16.
-template <typename R>
+template <typename R, int NCT>
 struct trsm_ops {
   C_t<R> a[TrsmShape<R>::RT][4];
-  C_t<R> b[4][2];
+  C_t<R> b[4][NCT];
 };
 
-template <typename R>
-__device__ __forceinline__ void trsm_load(trsm_ops<R>& o, const C_t<R>* __restrict__ Arow, int N,
+template <typename R, int NCT>
+__device__ __forceinline__ void trsm_load(trsm_ops<R, NCT>& o, const C_t<R>* __restrict__ Arow, int N,
                                           const C_t<R>* __restrict__ X, int nrhs, int j0, int nc, int kc, int lane) {
 #pragma unroll
   for (int rt = 0; rt < TrsmShape<R>::RT; ++rt) {
@@ -886,25 +885,26 @@ __device__ __forceinline__ void trsm_load(trsm_ops<R>& o, const C_t<R>* __restri
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
+    for (int ct = 0; ct < NCT; ++ct) {
       const int col = 16 * ct + (lane & 15);
       o.b[s4][ct] = col < nc ? X[(int64_t)(kc + 4 * (lane >> 4) + s4) * nrhs + j0 + col] : czero<C_t<R>>();
     }
 }
 
-template <typename R>
-__device__ __forceinline__ void trsm_mul3(const trsm_ops<R>& o, Acc_t<R> (&t1)[TrsmShape<R>::RT][2],
-                                          Acc_t<R> (&t2)[TrsmShape<R>::RT][2], Acc_t<R> (&t3)[TrsmShape<R>::RT][2]) {
+template <typename R, int NCT>
+__device__ __forceinline__ void trsm_mul3(const trsm_ops<R, NCT>& o, Acc_t<R> (&t1)[TrsmShape<R>::RT][NCT],
+                                          Acc_t<R> (&t2)[TrsmShape<R>::RT][NCT],
+                                          Acc_t<R> (&t3)[TrsmShape<R>::RT][NCT]) {
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4) {
-    R bs[2];
+    R bs[NCT];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) bs[ct] = o.b[s4][ct].x + o.b[s4][ct].y;
+    for (int ct = 0; ct < NCT; ++ct) bs[ct] = o.b[s4][ct].x + o.b[s4][ct].y;
 #pragma unroll
     for (int rt = 0; rt < TrsmShape<R>::RT; ++rt) {
       const R as = o.a[rt][s4].x + o.a[rt][s4].y;
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
+      for (int ct = 0; ct < NCT; ++ct) {
         t1[rt][ct] = mfma(o.a[rt][s4].x, o.b[s4][ct].x, t1[rt][ct]);
         t2[rt][ct] = mfma(o.a[rt][s4].y, o.b[s4][ct].y, t2[rt][ct]);
         t3[rt][ct] = mfma(as, bs[ct], t3[rt][ct]);
@@ -913,14 +913,17 @@ __device__ __forceinline__ void trsm_mul3(const trsm_ops<R>& o, Acc_t<R> (&t1)[T
   }
 }
 
-template <typename R, bool LOWER>
-__global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
+// NCT: 16-column tiles of right-hand sides per workgroup (RC = 16 NCT columns);
+// one workgroup per (subdomain, RC columns)
+template <typename R, bool LOWER, int NCT>
+__global__ void __launch_bounds__(64 * trsm_waves<R>(), (NCT == 1 && sizeof(R) == 4) ? 3 : 2)
     k_trsm(const C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off, const int32_t* __restrict__ Npad,
            const int64_t* __restrict__ vec_off, const int32_t* __restrict__ order, C_t<R>* __restrict__ xloc,
            int nrhs, const int32_t* __restrict__ trs_lo, const int32_t* __restrict__ trs_hi, int np) {
   typedef C_t<R> C;
   typedef Acc_t<R> Acc;
   constexpr int TRT = TrsmShape<R>::RT, TNW = trsm_waves<R>();
+  constexpr int RC = 16 * NCT;
   const int s = order[blockIdx.x];
   const int N = Npad[s];
   const C* A = pool + mat_off[s];
@@ -936,11 +939,11 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
     const int nd = min(SB, N - b0) / NB;
     if (w < nd * (NB / (16 * TRT))) {  // this wave's rows lie in the super-block
       const C* Arow = A + (int64_t)(b0 + 16 * TRT * w) * N;
-      Acc cre[TRT][2], cim[TRT][2];
+      Acc cre[TRT][NCT], cim[TRT][NCT];
 #pragma unroll
       for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) { cre[rt][ct] = zacc<R>(); cim[rt][ct] = zacc<R>(); }
+        for (int ct = 0; ct < NCT; ++ct) { cre[rt][ct] = zacc<R>(); cim[rt][ct] = zacc<R>(); }
       // off-diagonal part over K = [kbeg, kbeg + KC * nch): the band of this
       // wave's row tile (L: from its first non-zero column tile up to the
       // super-block; U: from the super-block's end up to its last one)
@@ -949,32 +952,32 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
       const int kend = LOWER ? b0 : min(N, NB * (trs_hi[(int64_t)s * np + tw] + 1));
       const int nch = max(0, (kend - kbeg) / KC);
       if (nch > 0) {
-        Acc t3[TRT][2];
+        Acc t3[TRT][NCT];
 #pragma unroll
         for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) t3[rt][ct] = zacc<R>();
+          for (int ct = 0; ct < NCT; ++ct) t3[rt][ct] = zacc<R>();
         if constexpr (sizeof(R) == 4) {
           // complex64: two chunks of loads in flight before their products
-          trsm_ops<R> o0, o1;
+          trsm_ops<R, NCT> o0, o1;
           for (int c = 0; c < nch; c += 2) {
-            trsm_load<R>(o0, Arow, N, X, nrhs, j0, nc, kbeg + c * KC, lane);
-            if (c + 1 < nch) trsm_load<R>(o1, Arow, N, X, nrhs, j0, nc, kbeg + (c + 1) * KC, lane);
-            trsm_mul3<R>(o0, cre, cim, t3);
-            if (c + 1 < nch) trsm_mul3<R>(o1, cre, cim, t3);
+            trsm_load<R, NCT>(o0, Arow, N, X, nrhs, j0, nc, kbeg + c * KC, lane);
+            if (c + 1 < nch) trsm_load<R, NCT>(o1, Arow, N, X, nrhs, j0, nc, kbeg + (c + 1) * KC, lane);
+            trsm_mul3<R, NCT>(o0, cre, cim, t3);
+            if (c + 1 < nch) trsm_mul3<R, NCT>(o1, cre, cim, t3);
           }
         } else {
-          trsm_ops<R> o0;
+          trsm_ops<R, NCT> o0;
           for (int c = 0; c < nch; ++c) {
-            trsm_load<R>(o0, Arow, N, X, nrhs, j0, nc, kbeg + c * KC, lane);
-            trsm_mul3<R>(o0, cre, cim, t3);
+            trsm_load<R, NCT>(o0, Arow, N, X, nrhs, j0, nc, kbeg + c * KC, lane);
+            trsm_mul3<R, NCT>(o0, cre, cim, t3);
           }
         }
         // cre = sum a.re b.re, cim = sum a.im b.im, t3 = sum (a.re + a.im)(b.re + b.im)
 #pragma unroll
         for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
+          for (int ct = 0; ct < NCT; ++ct) {
             const Acc t1 = cre[rt][ct], t2 = cim[rt][ct];
             cre[rt][ct] = t1 - t2;
             cim[rt][ct] = t3[rt][ct] - t1 - t2;
@@ -983,7 +986,7 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
 #pragma unroll
       for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = 16 * TRT * w + 16 * rt + acc_row<R>(lane, r);
@@ -1000,9 +1003,9 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
     for (int dq = 0; dq < nd; ++dq) {
       const int d = LOWER ? dq : nd - 1 - dq;
       const int db = b0 + NB * d;
-      Acc yre[2], yim[2];
+      Acc yre[NCT], yim[NCT];
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) { yre[ct] = zacc<R>(); yim[ct] = zacc<R>(); }
+      for (int ct = 0; ct < NCT; ++ct) { yre[ct] = zacc<R>(); yim[ct] = zacc<R>(); }
       if (dw) {
         C dv[NB / 4];
 #pragma unroll
@@ -1011,7 +1014,7 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
 #pragma unroll
         for (int kk = 0; kk < NB / 4; ++kk)
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
+          for (int ct = 0; ct < NCT; ++ct) {
             C bv = Tb[NB * d + 4 * kk + (lane >> 4)][16 * ct + (lane & 15)];
             cmfma<R>(dv[kk], bv, yre[ct], yim[ct]);
           }
@@ -1019,7 +1022,7 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
       __syncthreads();
       if (dw) {
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = 16 * w + acc_row<R>(lane, r);
@@ -1041,18 +1044,18 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), 2)
 #pragma unroll
         for (int kk = 0; kk < NB / 4; ++kk)
           av[kk] = A[(int64_t)(b0 + NB * dd + 16 * rt + (lane & 15)) * N + db + 4 * kk + (lane >> 4)];
-        Acc ure[2], uim[2];
+        Acc ure[NCT], uim[NCT];
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) { ure[ct] = zacc<R>(); uim[ct] = zacc<R>(); }
+        for (int ct = 0; ct < NCT; ++ct) { ure[ct] = zacc<R>(); uim[ct] = zacc<R>(); }
 #pragma unroll
         for (int kk = 0; kk < NB / 4; ++kk)
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
+          for (int ct = 0; ct < NCT; ++ct) {
             C bv = Tb[NB * d + 4 * kk + (lane >> 4)][16 * ct + (lane & 15)];
             cmfma<R>(av[kk], bv, ure[ct], uim[ct]);
           }
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = NB * dd + 16 * rt + acc_row<R>(lane, r);
@@ -1194,22 +1197,37 @@ void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_
 template <typename R>
 void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
                  const int64_t* vec_off, const int32_t* order, C_t<R>* xloc, int nsub, int nrhs,
-                 const int32_t* trs_lo, const int32_t* trs_hi, int np, KTimer* tm) {
+                 const int32_t* trs_lo, const int32_t* trs_hi, int np, int cols, KTimer* tm) {
   if (nsub <= 0 || nrhs <= 0) return;
-  dim3 grid(nsub, ceil_div(nrhs, RC));
-  MX_TB(K_TRSM_LOWER);
-  hipLaunchKernelGGL((k_trsm<R, true>), grid, dim3(64 * trsm_waves<R>()), 0, st, pool, mat_off, Npad, vec_off, order,
-                     xloc, nrhs, trs_lo, trs_hi, np);
-  MX_TE(K_TRSM_LOWER);
-  MX_TB(K_TRSM_UPPER);
-  hipLaunchKernelGGL((k_trsm<R, false>), grid, dim3(64 * trsm_waves<R>()), 0, st, pool, mat_off, Npad, vec_off, order,
-                     xloc, nrhs, trs_lo, trs_hi, np);
-  MX_TE(K_TRSM_UPPER);
+  const dim3 block(64 * trsm_waves<R>());
+  if (cols == 16) {
+    const dim3 grid(nsub, ceil_div(nrhs, 16));
+    MX_TB(K_TRSM_LOWER);
+    hipLaunchKernelGGL((k_trsm<R, true, 1>), grid, block, 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs,
+                       trs_lo, trs_hi, np);
+    MX_TE(K_TRSM_LOWER);
+    MX_TB(K_TRSM_UPPER);
+    hipLaunchKernelGGL((k_trsm<R, false, 1>), grid, block, 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs,
+                       trs_lo, trs_hi, np);
+    MX_TE(K_TRSM_UPPER);
+  } else {
+    const dim3 grid(nsub, ceil_div(nrhs, 32));
+    MX_TB(K_TRSM_LOWER);
+    hipLaunchKernelGGL((k_trsm<R, true, 2>), grid, block, 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs,
+                       trs_lo, trs_hi, np);
+    MX_TE(K_TRSM_LOWER);
+    MX_TB(K_TRSM_UPPER);
+    hipLaunchKernelGGL((k_trsm<R, false, 2>), grid, block, 0, st, pool, mat_off, Npad, vec_off, order, xloc, nrhs,
+                       trs_lo, trs_hi, np);
+    MX_TE(K_TRSM_UPPER);
+  }
 }
 template void launch_trsm<float>(hipStream_t, const float2*, const int64_t*, const int32_t*, const int64_t*,
-                                 const int32_t*, float2*, int, int, const int32_t*, const int32_t*, int, KTimer*);
+                                 const int32_t*, float2*, int, int, const int32_t*, const int32_t*, int, int,
+                                 KTimer*);
 template void launch_trsm<double>(hipStream_t, const double2*, const int64_t*, const int32_t*, const int64_t*,
-                                  const int32_t*, double2*, int, int, const int32_t*, const int32_t*, int, KTimer*);
+                                  const int32_t*, double2*, int, int, const int32_t*, const int32_t*, int, int,
+                                  KTimer*);
 
 int lu_max_swap_rows() { return MAXSW; }
 

@@ -275,7 +275,7 @@ struct mx_ctx {
   DBuf<char> factors;
   int precision = MX_PREC_C128;
   bool local_ready = false, factored = false;
-  int restart = 30, maxit = 2000;
+  int restart = 15, maxit = 2000;
   // wall time of the last mx_assemble / mx_setup_schwarz, device time of its LU
   double t_assemble = 0, t_setup = 0, t_lu = 0;
   hipEvent_t ev_lu[2] = {nullptr, nullptr};
@@ -345,7 +345,8 @@ struct mx_ctx {
   uint64_t tune_key = 0;
   int tune_spmm = 0;           // 0: lanes per right-hand side, 1: broadcast entries
   int tune_trsm_paired = 1;    // 1: size-paired workgroup order, 0: largest first
-  double tune_spmm_ms[2] = {0, 0}, tune_trsm_ms[2] = {0, 0};
+  int tune_trsm_cols = 32;     // right-hand-side columns per triangular-solve workgroup
+  double tune_spmm_ms[2] = {0, 0}, tune_trsm_ms[4] = {0, 0, 0, 0};
   bool graphs_on = true;
   uint64_t g_sig = 0;         // signature of the buffers, sizes and tolerance captured
   std::vector<hipGraphExec_t> gexec;
@@ -605,7 +606,7 @@ void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2*
   if (tm) tm->end(K_RESTRICT);
   launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p,
                  c->tune_trsm_paired ? c->trsm_order.p : c->order.p, xl, D.nsub, nrhs, c->trs_lo.p, c->trs_hi.p,
-                 c->band_np, tm);
+                 c->band_np, c->tune_trsm_cols, tm);
   const bool coarse = !local && c->coarse_use && !c->coarse_off_now && c->coarse_geom && c->coarse_weights;
   C* xq = nullptr;
   if (coarse) {
@@ -695,26 +696,32 @@ int precond_learned(mx_ctx* c, const double2* v, double2* z, double2* w, int nrh
 // variant of the SpMM and of the triangular-solve workgroup order is run on
 // this problem's own data (X = b; the restricted b) and timed with HIP
 // events; the fastest is kept for the following solves.
+// triangular-solve shapes: workgroup order (largest first / size-paired) x
+// right-hand-side columns per workgroup (32 / 16)
 template <typename R>
 int autotune_trsm(mx_ctx* c, int nrhs, hipEvent_t e0, hipEvent_t e1) {
   typedef C_t<R> C;
   const Decomposition& D = c->dec;
   C* xl = (C*)c->xloc.p;
   launch_restrict<C>(c->stream, D.vec_off[D.nsub], c->rowsrc.p, c->b.p, xl, nrhs);
-  for (int v = 0; v < 2; ++v) {
-    const int32_t* ord = v ? c->trsm_order.p : c->order.p;
+  int best = 0;
+  for (int v = 0; v < 4; ++v) {
+    const int32_t* ord = (v & 1) ? c->trsm_order.p : c->order.p;
+    const int cols = v < 2 ? 32 : 16;
     launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, ord, xl, D.nsub, nrhs,
-                   c->trs_lo.p, c->trs_hi.p, c->band_np, nullptr);
+                   c->trs_lo.p, c->trs_hi.p, c->band_np, cols, nullptr);
     MX_HIP_CHECK(hipEventRecord(e0, c->stream));
     launch_trsm<R>(c->stream, (const C*)c->factors.p, c->mat_off.p, c->Npad.p, c->vec_off.p, ord, xl, D.nsub, nrhs,
-                   c->trs_lo.p, c->trs_hi.p, c->band_np, nullptr);
+                   c->trs_lo.p, c->trs_hi.p, c->band_np, cols, nullptr);
     MX_HIP_CHECK(hipEventRecord(e1, c->stream));
     MX_HIP_CHECK(hipEventSynchronize(e1));
     float ms = 0;
     MX_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
     c->tune_trsm_ms[v] = ms;
+    if (ms < c->tune_trsm_ms[best]) best = v;
   }
-  c->tune_trsm_paired = c->tune_trsm_ms[1] <= c->tune_trsm_ms[0] ? 1 : 0;
+  c->tune_trsm_paired = best & 1;
+  c->tune_trsm_cols = best < 2 ? 32 : 16;
   return MX_OK;
 }
 
@@ -778,6 +785,7 @@ uint64_t step_signature(const mx_ctx* c, int nrhs, int m, double rtol) {
   val(c->precision);
   val(c->tune_spmm);
   val(c->tune_trsm_paired);
+  val(c->tune_trsm_cols);
   val(nrhs);
   val(m);
   val(rtol);
@@ -1922,7 +1930,21 @@ int mx_set_autotune(mx_ctx* c, int enable) {
     c->tune_key = 0;
     c->tune_spmm = 0;
     c->tune_trsm_paired = 1;
+    c->tune_trsm_cols = 32;
   }
+  return MX_OK;
+}
+
+int mx_set_tuning(mx_ctx* c, int32_t spmm_variant, int32_t trsm_paired, int32_t trsm_cols) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  if ((spmm_variant != 0 && spmm_variant != 1) || (trsm_paired != 0 && trsm_paired != 1) ||
+      (trsm_cols != 16 && trsm_cols != 32))
+    return set_err(MX_EINVAL, "variants: spmm 0/1, trsm order 0/1, trsm columns 16/32");
+  c->autotune_on = false;
+  c->tune_key = 0;
+  c->tune_spmm = spmm_variant;
+  c->tune_trsm_paired = trsm_paired;
+  c->tune_trsm_cols = trsm_cols;
   return MX_OK;
 }
 
@@ -1930,10 +1952,9 @@ int mx_get_tuning(mx_ctx* c, mx_tuning* out) {
   if (!c || !out) return set_err(MX_EINVAL, "NULL argument");
   out->spmm_variant = c->tune_spmm;
   out->trsm_paired = c->tune_trsm_paired;
-  for (int i = 0; i < 2; ++i) {
-    out->spmm_ms[i] = c->tune_spmm_ms[i];
-    out->trsm_ms[i] = c->tune_trsm_ms[i];
-  }
+  out->trsm_cols = c->tune_trsm_cols;
+  for (int i = 0; i < 2; ++i) out->spmm_ms[i] = c->tune_spmm_ms[i];
+  for (int i = 0; i < 4; ++i) out->trsm_ms[i] = c->tune_trsm_ms[i];
   return MX_OK;
 }
 
@@ -2040,12 +2061,12 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
 int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_opts* opts) {
   if (!c) return set_err(MX_EINVAL, "NULL context");
   if (!c->assembled) return set_err(MX_ESTATE, "mx_assemble must come first");
-  mx_schwarz_opts o = {MX_PREC_C128, 30, 2000, 1, 0};
+  mx_schwarz_opts o = {MX_PREC_C128, 15, 2000, 1, 0};
   if (opts) o = *opts;
   if (o.precision != MX_PREC_C128 && o.precision != MX_PREC_C64) return set_err(MX_EINVAL, "bad precision");
   CK(use_device(c));
   const auto t_start = std::chrono::steady_clock::now();
-  c->restart = o.restart > 0 ? o.restart : 30;
+  c->restart = o.restart > 0 ? o.restart : 15;
   c->maxit = o.maxit > 0 ? o.maxit : 2000;
   if (!c->have_dec || c->dec.nsub != nsub || c->dec.overlap != overlap) {
     Decomposition D;

@@ -120,10 +120,11 @@ void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_
                  const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc);
 template <typename R>
 // trs_lo[s*np + t]: first 64-column tile of row tile t's L part; trs_hi: last
-// column tile of its U part (from the band bookkeeping of the factorisation)
+// column tile of its U part (from the band bookkeeping of the factorisation);
+// cols: right-hand-side columns per workgroup (16 or 32)
 void launch_trsm(hipStream_t st, const C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
                  const int64_t* vec_off, const int32_t* order, C_t<R>* xloc, int nsub, int nrhs,
-                 const int32_t* trs_lo, const int32_t* trs_hi, int np, KTimer* tm);
+                 const int32_t* trs_lo, const int32_t* trs_hi, int np, int cols, KTimer* tm);
 int lu_max_swap_rows();
 
 // Krylov

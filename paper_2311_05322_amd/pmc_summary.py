@@ -1,4 +1,6 @@
-"""Summarises rocprofv3 HBM byte counters of one kernel into a short text file.
+"""Summarises rocprofv3 output into short text files for profiles/.
+
+Mode `traffic` (default): HBM byte counters of one kernel.
 
 Input: four counter-collection CSV files written by `rocprofv3 --pmc ...
 --output-format csv`: FETCH_SIZE and WRITE_SIZE of a plain device copy of known
@@ -11,6 +13,13 @@ whether the kernel changed after the counters were taken.
 python -m paper_2311_05322_amd.pmc_summary --copy-mib 1024 \\
     --copy-fetch C_F.csv --copy-write C_W.csv --fetch K_F.csv --write K_W.csv \\
     --kernel k_lu_update --command "..." --out profiles/x.md
+
+Mode `stats`: the kernel statistics CSV of `rocprofv3 --kernel-trace --stats
+--output-format csv` as a markdown table (namespaces and argument lists
+dropped from the names), with the command and a note.
+
+python -m paper_2311_05322_amd.pmc_summary stats --csv prof/x_kernel_stats.csv \\
+    --title "..." --command "..." [--note "..."] --out profiles/y.md
 """
 from __future__ import annotations
 
@@ -21,6 +30,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = {"k_lu_update": ["csrc/k_dense.hip", "csrc/mx_device.h"],
+           "k_lu_update_list": ["csrc/k_dense.hip", "csrc/mx_device.h"],
            "k_trsm": ["csrc/k_dense.hip", "csrc/mx_device.h"],
            "k_spmm": ["csrc/k_operator.hip", "csrc/mx_device.h"],
            "k_spmm_bcast": ["csrc/k_operator.hip", "csrc/mx_device.h"]}
@@ -43,7 +53,58 @@ def _values(path, name_part):
     return out
 
 
+def short_name(name: str) -> str:
+    """'void mx::(anonymous namespace)::k_trsm<float, true, 2>(args)' -> 'k_trsm<float, true, 2>'."""
+    name = name.replace("(anonymous namespace)::", "")
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    name = name[:cut].strip()
+    if name.startswith("void "):
+        name = name[5:]
+    head = name.split("<", 1)
+    head[0] = head[0].split("::")[-1]
+    return "<".join(head)
+
+
+def stats(argv):
+    ap = argparse.ArgumentParser(prog="pmc_summary stats")
+    ap.add_argument("--csv", required=True)
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--note", action="append", default=[])
+    ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    rows = []
+    with open(a.csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((short_name(r["Name"]), int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
+                         float(r["AverageNs"]) / 1e6, float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[2])
+    lines = [f"# {a.title}", "", "Command (repository root on the MI355X box, `cd /tmp && export TMPDIR=/tmp` first):",
+             "", "```", *a.command, "```", ""]
+    for n in a.note:
+        lines += [n, ""]
+    lines += ["| kernel | calls | total ms | avg ms | % |", "|---|---:|---:|---:|---:|"]
+    for name, calls, tot, avg, pct in rows[:a.top]:
+        lines.append(f"| `{name}` | {calls} | {tot:.1f} | {avg:.4f} | {pct:.2f} |")
+    lines.append("")
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "stats":
+        return stats(sys.argv[2:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--copy-mib", type=int, required=True)
     ap.add_argument("--copy-kernel", default="neg_kernel")

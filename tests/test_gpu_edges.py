@@ -58,6 +58,33 @@ def test_zero_rhs_column(chamber):
     assert err.max() <= 1e-5
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_every_kernel_variant_same_answer(chamber, prec):
+    """Every SpMM variant, triangular-solve order and right-hand-side width
+    per workgroup gives the same solution (to the solve tolerance) and the
+    direct solution."""
+    p, t, A, ctx = chamber
+    ctx.setup_schwarz(p.nsub, p.overlap, precision=prec)
+    B = workload.seeded_complex((t.ne, 20), 19)
+    U = fem.solve_direct(A, B)
+    ref = None
+    try:
+        for spmm in (0, 1):
+            for paired in (0, 1):
+                for cols in (16, 32):
+                    print(f"[case] precision {prec} spmm {spmm} paired {paired} cols {cols}", flush=True)
+                    ctx.set_tuning(spmm, paired, cols)
+                    X, info = ctx.solve_rhs(B, rtol=1e-10)
+                    assert info["converged"]
+                    err = np.linalg.norm(X - U, axis=0) / np.linalg.norm(U, axis=0)
+                    assert err.max() <= (1e-6 if prec == 0 else 1e-5)
+                    if ref is None:
+                        ref = X
+                    assert np.linalg.norm(X - ref) <= 1e-8 * np.linalg.norm(ref)
+    finally:
+        ctx.set_autotune(True)
+
+
 def test_autotune_off_same_answer(chamber):
     p, t, A, ctx = chamber
     ctx.setup_schwarz(p.nsub, p.overlap, precision=1)
