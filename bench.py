@@ -82,7 +82,7 @@ def measured_traffic(kernel, workload_name):
     this kernel on this workload, or None when there is none or the kernel's
     source changed after the counters were taken."""
     from paper_2311_05322_amd.pmc_summary import SOURCES, source_hash
-    name = "k_" + kernel.split("_lower")[0].split("_upper")[0]
+    name = "k_" + kernel
     path = os.path.join(ROOT, "profiles", f"{name}_{workload_name}_hbm_traffic.md")
     if name not in SOURCES or not os.path.exists(path):
         return None

@@ -32,6 +32,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = {"k_lu_update": ["csrc/k_dense.hip", "csrc/mx_device.h"],
            "k_lu_update_list": ["csrc/k_dense.hip", "csrc/mx_device.h"],
            "k_trsm": ["csrc/k_dense.hip", "csrc/mx_device.h"],
+           "k_trsm_lower": ["csrc/k_dense.hip", "csrc/mx_device.h"],
+           "k_trsm_upper": ["csrc/k_dense.hip", "csrc/mx_device.h"],
            "k_spmm": ["csrc/k_operator.hip", "csrc/mx_device.h"],
            "k_spmm_bcast": ["csrc/k_operator.hip", "csrc/mx_device.h"]}
 
@@ -113,13 +115,14 @@ def main():
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--kernel", required=True, choices=sorted(SOURCES))
+    ap.add_argument("--match", default=None, help="substring of the dispatches' kernel names (default: --kernel)")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     kib = a.copy_mib * 1024.0
     cf, cw = _values(a.copy_fetch, a.copy_kernel), _values(a.copy_write, a.copy_kernel)
     sf, sw = kib / (sum(cf) / len(cf)), kib / (sum(cw) / len(cw))
-    kf, kw = _values(a.fetch, a.kernel), _values(a.write, a.kernel)
+    kf, kw = _values(a.fetch, a.match or a.kernel), _values(a.write, a.match or a.kernel)
     if not kf or len(kf) != len(kw):
         raise SystemExit("kernel dispatch counts differ or are empty")
     n = len(kf)
@@ -137,7 +140,8 @@ def main():
         f"Copy calibration ({a.copy_mib} MiB read and written per dispatch, {len(cf)} dispatches):",
         f"FETCH_SIZE {sum(cf) / len(cf):.1f} KiB -> factor {sf:.4f}; WRITE_SIZE {sum(cw) / len(cw):.1f} KiB -> factor {sw:.4f}.",
         "",
-        f"{a.kernel}: {n} dispatches; figures are per-dispatch averages.",
+        f"{a.kernel} (dispatches matching `{a.match or a.kernel}`): {n} dispatches; figures are per-dispatch "
+        "averages.",
         "",
         "| per launch | counter (KiB) | scaled bytes |",
         "|---|---:|---:|",
