@@ -287,6 +287,22 @@ def chamber_problem(c: float = 0.004, mesh_seed: int = 0, tear_seed: int | None 
                     "tear_centre": ph.tear_centre, "tear_semi": ph.tear_semi})
 
 
+def batched_specs(n: int = 8, seed: int = 0):
+    """Seeded specifications of n phantoms solved as one batch: lattice cube
+    size c ~ U(3.6, 4.77) mm (about 1.4M to 0.6M edges in the chamber), mesh
+    jitter seed and tear seed k, and the number of subdomains that keeps the
+    overlapping subdomains between about 2.5k and 5.5k unknowns (512 below
+    1.0M edges, 1024 above; the edge count is about 1.02M (4 mm / c)^3).
+    Returns a list of dicts (c, mesh_seed, tear_seed, nsub)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        c = float(rng.uniform(0.0036, 0.00477))
+        ne_est = 1.02e6 * (0.004 / c) ** 3
+        out.append({"c": c, "mesh_seed": k, "tear_seed": k, "nsub": 512 if ne_est < 1.0e6 else 1024})
+    return out
+
+
 @dataclasses.dataclass
 class PortSpec:
     """Rectangular waveguide aperture on the mesh boundary: centre, outward
