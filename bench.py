@@ -244,6 +244,43 @@ def cpu_baseline(smp, iters):
             "seconds_per_solve": t_total}
 
 
+def spmm_variants(p, reps, name, counts=(32, 16, 5)):
+    """Every SpMM variant on the assembled operator: average launch time
+    (the library's device events around each launch) at the given
+    right-hand-side counts (at most 32), the rate against the algorithmic bytes, and the largest
+    difference from variant 0."""
+    import torch
+    import paper_2311_05322_amd as mx
+    ctx = mx.Context(0)
+    ctx.assemble(p.xyz, p.tet, p.eps, p.eps_kind, p.freq, p.eps_b)
+    sz = ctx.sizes()
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.view_as_complex(torch.randn(ctx.ne, 32, 2, dtype=torch.float64, device="cuda", generator=g))
+    out = {"workload": name, "ne": int(sz.ne), "nnz": int(sz.nnz), "reps": reps,
+           "variants": {}}
+    try:
+        for nrhs in counts:
+            Xn = X[:, :nrhs].contiguous()
+            ref = None
+            for v in (0, 1, 2):
+                ctx.set_tuning(v, 1, 32)
+                Y = ctx.apply_operator(Xn)
+                ctx.set_profiling(True)
+                for _ in range(reps):
+                    ctx.apply_operator(Xn, Y)
+                ms, n = ctx.kernel_times()["spmm"]
+                ctx.set_profiling(False)
+                ref = Y.clone() if ref is None else ref
+                _, byts = algorithmic_work("spmm", sz, nrhs, 16, None)
+                out["variants"][f"{nrhs}/{v}"] = {
+                    "ms": ms / n, "GB_s": byts / (ms / n) / 1e6, "frac_hbm": byts / (ms / n) / 1e6 / HBM_PEAK_GBS,
+                    "max_rel_diff_vs_0": float((Y - ref).abs().max() / ref.abs().max())}
+                log(f"nrhs {nrhs} variant {v}: {ms / n:.4f} ms")
+    finally:
+        ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +299,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy kernel (read MIB MiB, write MIB MiB) three times, as the "
                          "reference for HBM byte counters, and exit")
+    ap.add_argument("--spmm-variants", type=int, default=0, metavar="REPS",
+                    help="only time every SpMM variant (REPS launches each, device events) at 32, 16 and 5 "
+                         "right-hand sides on the workload's operator, print one JSON line and exit")
+    ap.add_argument("--spmm-nrhs", default="32,16,5", help="right-hand-side counts of --spmm-variants")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the solver runs on a single MI355X; --gpus {args.gpus} "
@@ -282,6 +323,9 @@ def main():
         return
 
     p = make_problem(args.workload)
+    if args.spmm_variants:
+        spmm_variants(p, args.spmm_variants, args.workload, [int(x) for x in args.spmm_nrhs.split(",")])
+        return
     smp = None
     if not args.no_cpu:
         # the oracle's sample runs first, in forked workers, before the GPU is touched

@@ -180,6 +180,11 @@ int mx_set_stream(mx_ctx* ctx, void* hip_stream);
  *   SpMM: 0 = one lane per right-hand side, non-zeros read by every lane;
  *         1 = 32 lanes per row, each non-zero read once and broadcast
  *             (nrhs <= 32 only);
+ *         2 = column windows: slices of at most 32 consecutive rows whose
+ *             non-zeros touch at most 128 columns; each workgroup stages
+ *             its slice's X rows (16 right-hand sides) in LDS once and
+ *             forms the slice's rows from there (built with the mesh;
+ *             unavailable when a row has more than 128 non-zeros);
  *   triangular solves: workgroup order (1 = b-th largest subdomain paired
  *         with the b-th smallest, 0 = largest first) x right-hand-side
  *         columns per workgroup (32, or 16 with twice the workgroups and
@@ -189,12 +194,13 @@ typedef struct {
   int32_t spmm_variant;
   int32_t trsm_paired;
   int32_t trsm_cols;
-  double spmm_ms[2];   /* average time of one SpMM per variant (0 if not run) */
+  double spmm_ms[3];   /* average time of one SpMM per variant (0 if not run,
+                          1e30 if the variant does not apply)               */
   double trsm_ms[4];   /* one lower + upper solve: [largest first / 32 columns,
                           paired / 32, largest first / 16, paired / 16]      */
 } mx_tuning;
 int mx_set_autotune(mx_ctx* ctx, int enable);
-/* Fix the variants (switches the autotuner off): spmm_variant 0/1,
+/* Fix the variants (switches the autotuner off): spmm_variant 0/1/2,
  * trsm_paired 0/1, trsm_cols 16/32. Results do not depend on the variants
  * beyond rounding. Errors: MX_EINVAL. */
 int mx_set_tuning(mx_ctx* ctx, int32_t spmm_variant, int32_t trsm_paired, int32_t trsm_cols);

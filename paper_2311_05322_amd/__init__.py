@@ -86,7 +86,7 @@ class Sizes(ct.Structure):
 
 class Tuning(ct.Structure):
     _fields_ = [("spmm_variant", ct.c_int32), ("trsm_paired", ct.c_int32), ("trsm_cols", ct.c_int32),
-                ("spmm_ms", ct.c_double * 2), ("trsm_ms", ct.c_double * 4)]
+                ("spmm_ms", ct.c_double * 3), ("trsm_ms", ct.c_double * 4)]
 
 
 class KernelTimes(ct.Structure):

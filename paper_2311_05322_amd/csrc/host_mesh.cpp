@@ -729,4 +729,45 @@ bool point_functional(const Topology& T, const double x[3], const double p_re[3]
   return true;
 }
 
+bool build_col_windows(const Topology& T, int32_t cap, int32_t max_rows, ColWindows& W) {
+  W = ColWindows();
+  const int64_t n = T.ne;
+  if (n <= 0 || cap <= 0 || cap > 256 || max_rows <= 0) return false;
+  for (int64_t r = 0; r < n; ++r)
+    if (T.row_ptr[r + 1] - T.row_ptr[r] > cap) return false;
+  std::vector<int32_t> mark(n, -1);   // slice that last counted the column
+  std::vector<int32_t> cols;
+  W.cap = cap;
+  W.max_rows = max_rows;
+  W.row.push_back(0);
+  W.cptr.push_back(0);
+  W.lcol.resize(T.nnz);
+  int64_t r = 0;
+  for (int32_t s = 0; r < n; ++s) {
+    const int64_t r0 = r;
+    int32_t u = 0;
+    while (r < n && r - r0 < max_rows) {
+      int32_t fresh = 0;
+      for (int64_t k = T.row_ptr[r]; k < T.row_ptr[r + 1]; ++k) fresh += mark[T.col[k]] != s;
+      if (u + fresh > cap) break;
+      for (int64_t k = T.row_ptr[r]; k < T.row_ptr[r + 1]; ++k)
+        if (mark[T.col[k]] != s) {
+          mark[T.col[k]] = s;
+          ++u;
+        }
+      ++r;
+    }
+    cols.assign(T.col.begin() + T.row_ptr[r0], T.col.begin() + T.row_ptr[r]);
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    for (int64_t k = T.row_ptr[r0]; k < T.row_ptr[r]; ++k)
+      W.lcol[k] = (uint8_t)(std::lower_bound(cols.begin(), cols.end(), T.col[k]) - cols.begin());
+    W.ucol.insert(W.ucol.end(), cols.begin(), cols.end());
+    W.umax = std::max(W.umax, (int32_t)cols.size());
+    W.row.push_back((int32_t)r);
+    W.cptr.push_back((int32_t)W.ucol.size());
+  }
+  return true;
+}
+
 }  // namespace mx

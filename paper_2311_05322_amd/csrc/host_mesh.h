@@ -94,6 +94,21 @@ struct Decomposition {
 std::string build_decomposition(const Topology& T, int32_t nsub, int32_t overlap, int32_t nb,
                                 Decomposition& D);
 
+// Column windows of the operator's rows for the LDS-staged product: the rows
+// are cut, in order, into slices of at most max_rows consecutive rows whose
+// non-zeros touch at most cap distinct columns (cap <= 256). ucol lists each
+// slice's columns in ascending order and lcol gives, for every non-zero in
+// CSR order, the position of its column in its slice's list.
+struct ColWindows {
+  int32_t cap = 0, max_rows = 0, umax = 0;
+  std::vector<int32_t> row;     // [ns+1] first row of each slice
+  std::vector<int32_t> cptr;    // [ns+1] offsets into ucol
+  std::vector<int32_t> ucol;
+  std::vector<uint8_t> lcol;    // [nnz]
+};
+// Returns false (and an empty W) when a single row has more than cap columns.
+bool build_col_windows(const Topology& T, int32_t cap, int32_t max_rows, ColWindows& W);
+
 // Point functional r[e] = p . N_e(x), averaged over all tetrahedra whose
 // closure contains x (min barycentric >= -1e-12).  Output: sorted edges and
 // complex values (re, im interleaved).  Returns false when x is outside.

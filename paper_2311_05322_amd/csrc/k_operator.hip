@@ -327,6 +327,7 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t nrows, const int64_t* __re
 // row's column indices and values are loaded once, one entry per lane, and
 // handed to all 32 lanes with cross-lane shuffles, so that each lane issues
 // only the X loads (four in flight). Same XCD row-band mapping as k_spmm.
+template <int UNR>
 __global__ void __launch_bounds__(256) k_spmm_bcast(int64_t nrows, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ col,
                                                     const double2* __restrict__ val,
@@ -339,35 +340,161 @@ __global__ void __launch_bounds__(256) k_spmm_bcast(int64_t nrows, const int64_t
   const int half = threadIdx.x & 32;  // first lane of this row's group within the wave
   if (row >= nrows) return;
   const int64_t k0 = rp[row], k1 = rp[row + 1];
+  // lanes beyond nrhs read a copy of the last column; entries beyond the row's
+  // end read the row's own X row with value zero (no per-entry branches)
+  const uint32_t jc = (uint32_t)min(lane, nrhs - 1);
   double re = 0, im = 0;
   for (int64_t kb = k0; kb < k1; kb += 32) {
     const int cnt = (int)min((int64_t)32, k1 - kb);
-    int c = 0;
+    int c = (int)row;
     double2 a = make_double2(0.0, 0.0);
     if (lane < cnt) {
       c = col[kb + lane];
       a = val[kb + lane];
     }
-    for (int q = 0; q < cnt; q += 4) {
-      double2 x[4], aa[4];
+    for (int q = 0; q < cnt; q += UNR) {
+      double2 x[UNR], aa[UNR];
+      uint32_t off[UNR];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < UNR; ++u) {
         const int src = half + q + u;
-        const int cc = __shfl(c, src, 64);
+        off[u] = (uint32_t)__shfl(c, src, 64) * (uint32_t)nrhs + jc;
         aa[u].x = __shfl(a.x, src, 64);
         aa[u].y = __shfl(a.y, src, 64);
-        x[u] = (q + u < cnt && lane < nrhs) ? X[(int64_t)cc * nrhs + lane] : make_double2(0.0, 0.0);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (q + u < cnt) {
-          re += aa[u].x * x[u].x - aa[u].y * x[u].y;
-          im += aa[u].x * x[u].y + aa[u].y * x[u].x;
-        }
+      for (int u = 0; u < UNR; ++u) x[u] = X[off[u]];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        re = fma(aa[u].x, x[u].x, re);
+        re = fma(-aa[u].y, x[u].y, re);
+        im = fma(aa[u].x, x[u].y, im);
+        im = fma(aa[u].y, x[u].x, im);
       }
     }
   }
   if (lane < nrhs) Y[row * nrhs + lane] = make_double2(re, im);
+}
+
+// Y = A X for nrhs <= 64 / NS, one wavefront per row: lane s * W + j
+// (W = 64 / NS) takes right-hand side j and entry stream s (entries k0 + s,
+// k0 + s + NS, ...). The row index is wave-uniform, so the column indices and
+// values come through scalar loads and reach the lanes as SGPR operands (a
+// select between the NS streams' values); no cross-lane shuffles except the
+// NS-way sum at the end of the row. Four rows per workgroup, XCD bands as in
+// k_spmm.
+// One chunk of a row held one entry per lane of the row's WD-lane group
+// (window position lc, value a): the entries are broadcast by shuffles and the
+// X values read from the LDS window, four in flight. Slots beyond cnt take
+// the value zero (their lanes hold zero) and read the X row of the chunk's
+// last entry, a column the row has.
+template <int WD>
+__device__ inline void win_chunk(int cnt, int lc, double2 a, const double2* win, int lane, double& re,
+                                 double& im) {
+  for (int q = 0; q < cnt; q += 4) {
+    double2 x[4], aa[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int l = __shfl(lc, min(q + u, cnt - 1), WD);
+      aa[u].x = __shfl(a.x, q + u, WD);
+      aa[u].y = __shfl(a.y, q + u, WD);
+      x[u] = win[l * WD + lane];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      re = fma(aa[u].x, x[u].x, re);
+      re = fma(-aa[u].y, x[u].y, re);
+      im = fma(aa[u].x, x[u].y, im);
+      im = fma(aa[u].y, x[u].x, im);
+    }
+  }
+}
+
+// Y = A X with X staged in LDS per slice of rows (column windows). The rows
+// are cut into slices of at most 32 consecutive rows whose non-zeros touch at
+// most 128 distinct columns. Workgroup (slice, h) copies those X rows,
+// right-hand sides WD h .. WD h + WD - 1, into LDS once (16 WD bytes per row;
+// launched with WD = 16: 32 KB per workgroup, five per compute unit; WD = 32
+// needs 64 KB, two per compute unit, and measured slower), then forms the
+// slice's rows from LDS: WD lanes per row (lane j: right-hand side WD h + j),
+// 32 / G rows per WD-lane group (G = 256 / WD groups), the first 32 entries
+// of each row loaded before the barrier together with the window. Workgroups
+// are dealt to the XCDs in contiguous bands as in k_spmm; the nh
+// right-hand-side blocks of a slice are adjacent.
+template <int WD>
+__global__ void __launch_bounds__(256) k_spmm_win(int32_t nsl, int nh, const int32_t* __restrict__ srow,
+                                                  const int32_t* __restrict__ scp, const int32_t* __restrict__ ucol,
+                                                  const int64_t* __restrict__ rp, const uint8_t* __restrict__ lcol,
+                                                  const double2* __restrict__ val, const double2* __restrict__ X,
+                                                  double2* __restrict__ Y, int nrhs) {
+  constexpr int G = 256 / WD, CAP = kSpmmWinCap, PASSES = CAP / G, RPG = kSpmmWinRows / G, CH = 32 / WD;
+  __shared__ double2 win[CAP * WD];
+  const int64_t per = gridDim.x / 8;
+  const int64_t b = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t s = b / nh;
+  if (s >= nsl) return;
+  const int h = (int)(b % nh);
+  const int g = threadIdx.x / WD, lane = threadIdx.x % WD;
+  const int j = h * WD + lane;
+  const int jc = min(j, nrhs - 1);  // lanes beyond nrhs carry a copy of the last column
+  const int c0 = scp[s], U = scp[s + 1] - c0;
+  const int row0 = srow[s], nr = srow[s + 1] - row0;
+  double2 t[PASSES];
+#pragma unroll
+  for (int u = 0; u < PASSES; ++u) {
+    const int r = g + G * u;
+    t[u] = make_double2(0.0, 0.0);
+    if (r < U) t[u] = X[(int64_t)ucol[c0 + r] * nrhs + jc];
+  }
+  // rows g, g + G, ... of the slice: entries lane, WD + lane, ... (first 32)
+  int64_t k0[RPG], k1[RPG];
+  int lc[RPG][CH];
+  double2 a[RPG][CH];
+#pragma unroll
+  for (int w = 0; w < RPG; ++w) {
+    const int rr = g + G * w;
+    k0[w] = k1[w] = 0;
+    if (rr < nr) {
+      k0[w] = rp[row0 + rr];
+      k1[w] = rp[row0 + rr + 1];
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int64_t k = k0[w] + WD * c + lane;
+      lc[w][c] = 0;
+      a[w][c] = make_double2(0.0, 0.0);
+      if (k < k1[w]) {
+        lc[w][c] = lcol[k];
+        a[w][c] = val[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PASSES; ++u) {
+    const int r = g + G * u;
+    if (r < U) win[r * WD + lane] = t[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < RPG; ++w) {
+    const int rr = g + G * w;
+    if (rr >= nr) break;
+    const int64_t n = k1[w] - k0[w];
+    double re = 0, im = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      if (n > WD * c) win_chunk<WD>((int)min(n - WD * c, (int64_t)WD), lc[w][c], a[w][c], win, lane, re, im);
+    for (int64_t kb = k0[w] + 32; kb < k1[w]; kb += WD) {  // rows with more than 32 entries
+      int l = 0;
+      double2 v = make_double2(0.0, 0.0);
+      if (kb + lane < k1[w]) {
+        l = lcol[kb + lane];
+        v = val[kb + lane];
+      }
+      win_chunk<WD>((int)min(k1[w] - kb, (int64_t)WD), l, v, win, lane, re, im);
+    }
+    if (j < nrhs) Y[(int64_t)(row0 + rr) * nrhs + j] = make_double2(re, im);
+  }
 }
 
 // xloc[R][j] = v[rowsrc[R]][j] (0 for padded rows), cast to C
@@ -558,10 +685,14 @@ template void launch_pad_identity<double2>(hipStream_t, int32_t, const int64_t*,
 static inline unsigned nblk8(int64_t n, int64_t per) { return (unsigned)((nblk(n, per) + 7) / 8 * 8); }
 
 void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t* col, const double2* val,
-                 const double2* X, double2* Y, int nrhs, int variant) {
+                 const double2* X, double2* Y, int nrhs, int variant, const SpmmWindows* win) {
   if (nrows <= 0) return;
-  if (variant == 1 && nrhs <= 32)
-    hipLaunchKernelGGL(k_spmm_bcast, dim3(nblk8(nrows, 8)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
+  if (variant == 2 && win && win->nsl > 0) {
+    const int nh = (nrhs + 15) / 16;
+    hipLaunchKernelGGL(k_spmm_win<16>, dim3(nblk8((int64_t)win->nsl * nh, 1)), dim3(256), 0, s, win->nsl, nh,
+                       win->srow, win->scp, win->ucol, rp, win->lcol, val, X, Y, nrhs);
+  } else if (variant == 1 && nrhs <= 32)
+    hipLaunchKernelGGL(k_spmm_bcast<4>, dim3(nblk8(nrows, 8)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
   else if (nrhs <= 8)
     hipLaunchKernelGGL(k_spmm<8>, dim3(nblk8(nrows, 32)), dim3(256), 0, s, nrows, rp, col, val, X, Y, nrhs);
   else if (nrhs <= 16)

@@ -250,6 +250,12 @@ struct mx_ctx {
   DBuf<double> xyz;
   DBuf<int32_t> ts, col, csrc, bf_tet, bf_lf;
   DBuf<int64_t> row_ptr, cptr;
+  // column windows of the operator's rows (SpMM variant 2; win_ok false when
+  // some row has more columns than a window holds)
+  ColWindows win;
+  bool win_ok = false;
+  DBuf<int32_t> win_row, win_cp, win_ucol;
+  DBuf<uint8_t> win_lcol;
   // operator
   bool assembled = false;
   int eps_kind = 0;
@@ -343,10 +349,10 @@ struct mx_ctx {
   // autotuner: kernel variants picked by timing them on this problem
   bool autotune_on = true;
   uint64_t tune_key = 0;
-  int tune_spmm = 0;           // 0: lanes per right-hand side, 1: broadcast entries
+  int tune_spmm = 0;           // 0: lanes per right-hand side, 1: broadcast entries, 2: LDS windows
   int tune_trsm_paired = 1;    // 1: size-paired workgroup order, 0: largest first
   int tune_trsm_cols = 32;     // right-hand-side columns per triangular-solve workgroup
-  double tune_spmm_ms[2] = {0, 0}, tune_trsm_ms[4] = {0, 0, 0, 0};
+  double tune_spmm_ms[3] = {0, 0, 0}, tune_trsm_ms[4] = {0, 0, 0, 0};
   bool graphs_on = true;
   uint64_t g_sig = 0;         // signature of the buffers, sizes and tolerance captured
   std::vector<hipGraphExec_t> gexec;
@@ -641,9 +647,15 @@ int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q 
   return MX_OK;
 }
 
+SpmmWindows windows(const mx_ctx* c) {
+  if (!c->win_ok) return SpmmWindows{0, nullptr, nullptr, nullptr, nullptr};
+  return SpmmWindows{(int32_t)(c->win.row.size() - 1), c->win_row.p, c->win_cp.p, c->win_ucol.p, c->win_lcol.p};
+}
+
 int spmm(mx_ctx* c, const double2* X, double2* Y, int nrhs) {
   c->prof.begin(K_SPMM);
-  launch_spmm(c->stream, c->topo.ne, c->row_ptr.p, c->col.p, c->val.p, X, Y, nrhs, c->tune_spmm);
+  const SpmmWindows w = windows(c);
+  launch_spmm(c->stream, c->topo.ne, c->row_ptr.p, c->col.p, c->val.p, X, Y, nrhs, c->tune_spmm, &w);
   c->prof.end(K_SPMM);
   MX_HIP_CHECK(hipGetLastError());
   return MX_OK;
@@ -741,14 +753,16 @@ int autotune(mx_ctx* c, int nrhs) {
   MX_HIP_CHECK(hipEventCreate(&e1));
   const int64_t ne = c->topo.ne;
   int rc = MX_OK;
-  for (int v = 0; v < 2 && rc == MX_OK; ++v) {
-    if (v == 1 && nrhs > 32) {
+  const SpmmWindows w = windows(c);
+  for (int v = 0; v < 3 && rc == MX_OK; ++v) {
+    if ((v == 1 && nrhs > 32) || (v == 2 && !c->win_ok)) {
       c->tune_spmm_ms[v] = 1e30;
       continue;
     }
-    launch_spmm(c->stream, ne, c->row_ptr.p, c->col.p, c->val.p, c->b.p, c->r.p, nrhs, v);
+    launch_spmm(c->stream, ne, c->row_ptr.p, c->col.p, c->val.p, c->b.p, c->r.p, nrhs, v, &w);
     hipError_t e = hipEventRecord(e0, c->stream);
-    for (int it = 0; it < 3; ++it) launch_spmm(c->stream, ne, c->row_ptr.p, c->col.p, c->val.p, c->b.p, c->r.p, nrhs, v);
+    for (int it = 0; it < 3; ++it)
+      launch_spmm(c->stream, ne, c->row_ptr.p, c->col.p, c->val.p, c->b.p, c->r.p, nrhs, v, &w);
     if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0;
@@ -756,7 +770,11 @@ int autotune(mx_ctx* c, int nrhs) {
     if (e != hipSuccess) rc = hip_fail(e, "autotune spmm", __FILE__, __LINE__);
     c->tune_spmm_ms[v] = ms / 3;
   }
-  if (rc == MX_OK) c->tune_spmm = c->tune_spmm_ms[1] < c->tune_spmm_ms[0] ? 1 : 0;
+  if (rc == MX_OK) {
+    c->tune_spmm = 0;
+    for (int v = 1; v < 3; ++v)
+      if (c->tune_spmm_ms[v] < c->tune_spmm_ms[c->tune_spmm]) c->tune_spmm = v;
+  }
   if (rc == MX_OK && c->factored)
     rc = c->precision == MX_PREC_C64 ? autotune_trsm<float>(c, nrhs, e0, e1) : autotune_trsm<double>(c, nrhs, e0, e1);
   (void)hipEventDestroy(e0);
@@ -777,9 +795,11 @@ uint64_t step_signature(const mx_ctx* c, int nrhs, int m, double rtol) {
                         c->rowsrc.p, c->trsm_order.p, c->mat_off.p, c->Npad.p, c->vec_off.p, c->p_edge.p,
                         c->p_row.p, c->p_w.p, c->dotpart.p, c->normpart.p, c->h1.p, c->h2.p, c->hn.p, c->H.p,
                         c->cs.p, c->sn.p, c->g.p, c->bnorm.p, c->conv.p, c->kdone.p, c->res.p, c->trs_lo.p,
-                        c->trs_hi.p};
+                        c->trs_hi.p, c->win_row.p, c->win_cp.p, c->win_ucol.p, c->win_lcol.p};
   mix(ptrs, sizeof(ptrs));
   val(c->topo.ne);
+  val(c->win_ok);
+  val(c->win.row.size());
   val(c->dec.nsub);
   val(c->dec.ncolour);
   val(c->precision);
@@ -1937,9 +1957,11 @@ int mx_set_autotune(mx_ctx* c, int enable) {
 
 int mx_set_tuning(mx_ctx* c, int32_t spmm_variant, int32_t trsm_paired, int32_t trsm_cols) {
   if (!c) return set_err(MX_EINVAL, "NULL context");
-  if ((spmm_variant != 0 && spmm_variant != 1) || (trsm_paired != 0 && trsm_paired != 1) ||
+  if (spmm_variant < 0 || spmm_variant > 2 || (trsm_paired != 0 && trsm_paired != 1) ||
       (trsm_cols != 16 && trsm_cols != 32))
-    return set_err(MX_EINVAL, "variants: spmm 0/1, trsm order 0/1, trsm columns 16/32");
+    return set_err(MX_EINVAL, "variants: spmm 0/1/2, trsm order 0/1, trsm columns 16/32");
+  if (spmm_variant == 2 && !c->win_ok)
+    return set_err(MX_EINVAL, "spmm variant 2 needs an assembled mesh whose rows fit a column window");
   c->autotune_on = false;
   c->tune_key = 0;
   c->tune_spmm = spmm_variant;
@@ -1953,7 +1975,7 @@ int mx_get_tuning(mx_ctx* c, mx_tuning* out) {
   out->spmm_variant = c->tune_spmm;
   out->trsm_paired = c->tune_trsm_paired;
   out->trsm_cols = c->tune_trsm_cols;
-  for (int i = 0; i < 2; ++i) out->spmm_ms[i] = c->tune_spmm_ms[i];
+  for (int i = 0; i < 3; ++i) out->spmm_ms[i] = c->tune_spmm_ms[i];
   for (int i = 0; i < 4; ++i) out->trsm_ms[i] = c->tune_trsm_ms[i];
   return MX_OK;
 }
@@ -2019,6 +2041,13 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
     CK(c->col.upload(t.col, c->stream));
     CK(c->row_ptr.upload(t.row_ptr, c->stream));
     CK(c->cptr.upload(t.cptr, c->stream));
+    c->win_ok = build_col_windows(t, kSpmmWinCap, kSpmmWinRows, c->win);
+    if (c->win_ok) {
+      CK(c->win_row.upload(c->win.row, c->stream));
+      CK(c->win_cp.upload(c->win.cptr, c->stream));
+      CK(c->win_ucol.upload(c->win.ucol, c->stream));
+      CK(c->win_lcol.upload(c->win.lcol, c->stream));
+    }
     CK(c->csrc.upload(t.csrc, c->stream));
     CK(c->bf_tet.upload(t.bf_tet, c->stream));
     CK(c->bf_lf.upload(t.bf_lf, c->stream));

@@ -84,8 +84,22 @@ void launch_scale_f(hipStream_t s, int64_t n, float* x, float f);
 void launch_nonfinite(hipStream_t s, int64_t n, const float* x, int32_t* flag);
 
 // operator application and Schwarz transfer
+// Column windows of the rows for SpMM variant 2 (slices of at most
+// kSpmmWinRows consecutive rows touching at most kSpmmWinCap columns):
+// srow/scp [nsl+1] first row and ucol offset of each slice, ucol the slice's
+// columns, lcol [nnz] position of each non-zero's column in its slice's list.
+constexpr int kSpmmWinCap = 128, kSpmmWinRows = 32;
+struct SpmmWindows {
+  int32_t nsl;
+  const int32_t* srow;
+  const int32_t* scp;
+  const int32_t* ucol;
+  const uint8_t* lcol;
+};
+// variant 0: one lane per right-hand side; 1: 32 lanes per row, entries
+// broadcast (nrhs <= 32); 2: column windows staged in LDS (needs win)
 void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t* col, const double2* val,
-                 const double2* X, double2* Y, int nrhs, int variant = 0);
+                 const double2* X, double2* Y, int nrhs, int variant = 0, const SpmmWindows* win = nullptr);
 template <typename C>
 void launch_restrict(hipStream_t s, int64_t nrows, const int32_t* rowsrc, const double2* v, C* xloc, int nrhs);
 template <typename C>

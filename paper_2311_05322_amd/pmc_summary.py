@@ -20,6 +20,12 @@ dropped from the names), with the command and a note.
 
 python -m paper_2311_05322_amd.pmc_summary stats --csv prof/x_kernel_stats.csv \\
     --title "..." --command "..." [--note "..."] --out profiles/y.md
+
+Mode `counters`: any counters of `rocprofv3 --pmc` runs (one or more
+counter-collection CSV files), averaged per kernel, as one markdown table.
+
+python -m paper_2311_05322_amd.pmc_summary counters --csv a.csv --csv b.csv \\
+    --title "..." --command "..." --out profiles/z.md
 """
 from __future__ import annotations
 
@@ -35,7 +41,8 @@ SOURCES = {"k_lu_update": ["csrc/k_dense.hip", "csrc/mx_device.h"],
            "k_trsm_lower": ["csrc/k_dense.hip", "csrc/mx_device.h"],
            "k_trsm_upper": ["csrc/k_dense.hip", "csrc/mx_device.h"],
            "k_spmm": ["csrc/k_operator.hip", "csrc/mx_device.h"],
-           "k_spmm_bcast": ["csrc/k_operator.hip", "csrc/mx_device.h"]}
+           "k_spmm_bcast": ["csrc/k_operator.hip", "csrc/mx_device.h"],
+           "k_spmm_win": ["csrc/k_operator.hip", "csrc/mx_device.h"]}
 
 
 def source_hash(kernel: str) -> str:
@@ -96,7 +103,43 @@ def stats(argv):
         lines += [n, ""]
     lines += ["| kernel | calls | total ms | avg ms | % |", "|---|---:|---:|---:|---:|"]
     for name, calls, tot, avg, pct in rows[:a.top]:
+        name = name if len(name) <= 72 else name[:69] + "..."
         lines.append(f"| `{name}` | {calls} | {tot:.1f} | {avg:.4f} | {pct:.2f} |")
+    lines.append("")
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def counters(argv):
+    ap = argparse.ArgumentParser(prog="pmc_summary counters")
+    ap.add_argument("--csv", action="append", required=True, help="counter-collection CSV (repeatable)")
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--note", action="append", default=[])
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    vals: dict = {}
+    for path in a.csv:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k = short_name(r["Kernel_Name"])
+                vals.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    kernels = sorted(vals)
+    names = sorted({c for k in kernels for c in vals[k]})
+    lines = [f"# {a.title}", "", "Commands (repository root on the MI355X box, `cd /tmp && export TMPDIR=/tmp` "
+             "first):", "", "```", *a.command, "```", ""]
+    for n in a.note:
+        lines += [n, ""]
+    lines += ["Per-dispatch averages over all dispatches of each kernel.", "",
+              "| counter | " + " | ".join(f"`{k}`" for k in kernels) + " |",
+              "|---|" + "---:|" * len(kernels)]
+    for c in names:
+        cells = []
+        for k in kernels:
+            v = vals[k].get(c)
+            cells.append(f"{sum(v) / len(v):.4g}" if v else "")
+        lines.append(f"| {c} | " + " | ".join(cells) + " |")
     lines.append("")
     with open(a.out, "w") as f:
         f.write("\n".join(lines))
@@ -107,6 +150,8 @@ def main():
     import sys
     if len(sys.argv) > 1 and sys.argv[1] == "stats":
         return stats(sys.argv[2:])
+    if len(sys.argv) > 1 and sys.argv[1] == "counters":
+        return counters(sys.argv[2:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--copy-mib", type=int, required=True)
     ap.add_argument("--copy-kernel", default="neg_kernel")

@@ -39,9 +39,9 @@ def test_ragged_rhs_counts(chamber, nrhs, prec, tol):
         err = np.linalg.norm(X - U, axis=0) / np.linalg.norm(U, axis=0)
         assert err.max() <= tol, (nrhs, rep, err.max())
     tun = ctx.tuning()
-    assert tun["spmm_variant"] in (0, 1)
+    assert tun["spmm_variant"] in (0, 1, 2)
     if nrhs > 32:
-        assert tun["spmm_variant"] == 0
+        assert tun["spmm_variant"] != 1
 
 
 def test_zero_rhs_column(chamber):
@@ -69,7 +69,7 @@ def test_every_kernel_variant_same_answer(chamber, prec):
     U = fem.solve_direct(A, B)
     ref = None
     try:
-        for spmm in (0, 1):
+        for spmm in (0, 1, 2):
             for paired in (0, 1):
                 for cols in (16, 32):
                     print(f"[case] precision {prec} spmm {spmm} paired {paired} cols {cols}", flush=True)
@@ -120,6 +120,46 @@ def test_limits_are_errors():
         with pytest.raises(mx.MxError) as e:
             ctx.solve(np.zeros((0, 3)), np.zeros((0, 3)), rtol=1e-8)
         assert e.value.code == mx.MX_EINVAL
+    finally:
+        ctx.close()
+
+
+def _fan(k):
+    """k tetrahedra around one axis edge: that edge's row of the operator has
+    3k + 1 non-zeros (axis, 2k spokes, k rim edges)."""
+    ang = 2 * np.pi * np.arange(k) / k
+    xyz = np.concatenate([[[0.0, 0.0, -0.05], [0.0, 0.0, 0.05]],
+                          np.stack([0.04 * np.cos(ang), 0.04 * np.sin(ang), np.zeros(k)], 1)])
+    tet = np.array([[0, 1, 2 + i, 2 + (i + 1) % k] for i in range(k)], np.int32)
+    return xyz, tet
+
+
+@pytest.mark.parametrize("k", [16, 50])
+def test_spmm_long_rows(k):
+    """A row longer than two 16-entry chunks (49 non-zeros) goes through the
+    column-window SpMM's tail loop; a row longer than a window (151 > 128
+    columns) leaves that variant unavailable (MX_EINVAL when asked for) and
+    every other variant still matches A @ X."""
+    print(f"[case] spmm fan of {k} tetrahedra", flush=True)
+    xyz, tet = _fan(k)
+    eps = np.full(len(tet), workload.eps_r(44.0, 0.6, 1e9))
+    t = fem.Topology(xyz, tet)
+    assert np.diff(t.row_ptr).max() == 3 * k + 1
+    A = fem.assemble(t, eps, 0, 1e9, eps[0])
+    X = workload.seeded_complex((t.ne, 20), 3)
+    ref = A @ X
+    ctx = mx.Context(0)
+    try:
+        ctx.assemble(xyz, tet, eps, 0, 1e9, eps[0])
+        variants = (0, 1, 2) if 3 * k + 1 <= 128 else (0, 1)
+        if 3 * k + 1 > 128:
+            with pytest.raises(mx.MxError) as e:
+                ctx.set_tuning(2, 1, 32)
+            assert e.value.code == mx.MX_EINVAL
+        for v in variants:
+            ctx.set_tuning(v, 1, 32)
+            Y = ctx.apply_operator(X)
+            assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max(), v
     finally:
         ctx.close()
 

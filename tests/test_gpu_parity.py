@@ -55,15 +55,20 @@ def test_operator_values(case):
     assert np.abs(v - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-def test_spmm(case):
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_spmm(case, variant):
+    """Every SpMM variant against A @ X: 32 right-hand sides, a ragged count
+    (5) and 20 (the column-window variant's second block half full)."""
     X = workload.seeded_complex((case.t.ne, 32), 7)
-    Y = case.ctx.apply_operator(X)
     ref = case.A @ X
-    assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max()
-    # ragged right-hand-side count
-    X5 = np.ascontiguousarray(X[:, :5])
-    Y5 = case.ctx.apply_operator(X5)
-    assert np.abs(Y5 - case.A @ X5).max() <= 1e-13 * np.abs(ref).max()
+    case.ctx.set_tuning(variant, 1, 32)
+    try:
+        for n in (32, 5, 20):
+            Xn = np.ascontiguousarray(X[:, :n])
+            Yn = case.ctx.apply_operator(Xn)
+            assert np.abs(Yn - ref[:, :n]).max() <= 1e-13 * np.abs(ref).max(), n
+    finally:
+        case.ctx.set_autotune(True)
 
 
 @pytest.mark.parametrize("overlap", [1, 2])
