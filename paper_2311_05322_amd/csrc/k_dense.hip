@@ -834,8 +834,8 @@ __global__ void __launch_bounds__(64) k_perm(int32_t nsub, const int32_t* __rest
 // complex64: four waves; RT = 2 for complex128: eight waves) and accumulates
 // A[rows, K] X[K] on its own, with no workgroup barrier: it streams its
 // factor rows and the matching right-hand-side rows straight into MFMA
-// operand registers (complex64: one 16-column chunk ahead of the chunk being
-// multiplied); the right-hand-side rows are shared by the waves and come from
+// operand registers (complex64: the next 16-column chunk in flight while a
+// chunk is multiplied); the right-hand-side rows are shared by the waves and come from
 // L1/L2. Two workgroups share a compute unit for complex64; for complex128
 // the workgroup's LDS admits one per compute unit, and its eight waves keep
 // two on each SIMD so that one wave's loads are covered by the other's
@@ -882,12 +882,15 @@ __device__ __forceinline__ void trsm_load(trsm_ops<R, NCT>& o, const C_t<R>* __r
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) o.a[rt][s4] = ap[s4];
   }
+  // columns beyond nc read a copy of the last column: the products of an
+  // MFMA column depend on that column alone, and those columns are never
+  // stored, so no branch (and no conservative wait) is needed here
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
-      const int col = 16 * ct + (lane & 15);
-      o.b[s4][ct] = col < nc ? X[(int64_t)(kc + 4 * (lane >> 4) + s4) * nrhs + j0 + col] : czero<C_t<R>>();
+      const int col = min(16 * ct + (lane & 15), nc - 1);
+      o.b[s4][ct] = X[(int64_t)(kc + 4 * (lane >> 4) + s4) * nrhs + j0 + col];
     }
 }
 
@@ -958,13 +961,32 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), (NCT == 1 && sizeof(R) =
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) t3[rt][ct] = zacc<R>();
         if constexpr (sizeof(R) == 4) {
-          // complex64: two chunks of loads in flight before their products
+          // complex64: two operand sets in rotation, so that the next chunk's
+          // loads are in flight while a chunk is multiplied. Inside the loop
+          // over chunk pairs the loads are unconditional (chunk indices
+          // clamped; the last round's are never used) and scheduling barriers
+          // keep their place, so that each product waits for its own operands
+          // only. (The band is tile-aligned, so nch is a multiple of four; an
+          // odd chunk would be taken after the loop.)
           trsm_ops<R, NCT> o0, o1;
-          for (int c = 0; c < nch; c += 2) {
-            trsm_load<R, NCT>(o0, Arow, N, X, nrhs, j0, nc, kbeg + c * KC, lane);
-            if (c + 1 < nch) trsm_load<R, NCT>(o1, Arow, N, X, nrhs, j0, nc, kbeg + (c + 1) * KC, lane);
+          const int n2 = nch & ~1;
+          if (n2 > 0) {
+            trsm_load<R, NCT>(o0, Arow, N, X, nrhs, j0, nc, kbeg, lane);
+            trsm_load<R, NCT>(o1, Arow, N, X, nrhs, j0, nc, kbeg + KC, lane);
+            for (int c = 0; c < n2; c += 2) {
+              __builtin_amdgcn_sched_barrier(0);
+              trsm_mul3<R, NCT>(o0, cre, cim, t3);
+              __builtin_amdgcn_sched_barrier(0);
+              trsm_load<R, NCT>(o0, Arow, N, X, nrhs, j0, nc, kbeg + min(c + 2, n2 - 2) * KC, lane);
+              __builtin_amdgcn_sched_barrier(0);
+              trsm_mul3<R, NCT>(o1, cre, cim, t3);
+              __builtin_amdgcn_sched_barrier(0);
+              trsm_load<R, NCT>(o1, Arow, N, X, nrhs, j0, nc, kbeg + min(c + 3, n2 - 1) * KC, lane);
+            }
+          }
+          if (nch & 1) {
+            trsm_load<R, NCT>(o0, Arow, N, X, nrhs, j0, nc, kbeg + (nch - 1) * KC, lane);
             trsm_mul3<R, NCT>(o0, cre, cim, t3);
-            if (c + 1 < nch) trsm_mul3<R, NCT>(o1, cre, cim, t3);
           }
         } else {
           trsm_ops<R, NCT> o0;
