@@ -57,6 +57,17 @@ template <typename C> __device__ inline C crecip(C a) {
   return cdiv(one, a);
 }
 
+// value of v in lane i (i wave-uniform)
+__device__ inline float read_lane(float v, int i) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
+__device__ inline double read_lane(double v, int i) {
+  const int64_t b = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)b, i);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(b >> 32), i);
+  return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+
 // --------------------------------------------------------------------------
 // panel factorisation
 // --------------------------------------------------------------------------
@@ -94,9 +105,9 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
   for (int s0 = 0; s0 < NB; s0 += W) {
     const int c0 = k0 + s0;
     // (A) top rows of the sub-panel columns: U[k0:c0, c0:c0+W] = L11^{-1} A by
-    // forward substitution, one wave per column, lane l holding the l-th
-    // term of each inner product. L11 rows are final once their pivots are
-    // taken, so the rows of the previous sub-panel are copied into Lt here.
+    // forward substitution, one wave per column, lane l holding row l. L11
+    // rows are final once their pivots are taken, so the rows of the
+    // previous sub-panel are copied into Lt here.
     if (s0 > 0)
       for (int e = tid; e < W * s0; e += PT) {
         const int i = s0 - W + e / s0, l = e % s0;
@@ -104,23 +115,19 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
       }
     __syncthreads();
     if (wv < W && s0 > 0) {
+      // column-oriented: lane l holds row l of the right-hand side; at step
+      // i row i is final, its value is broadcast with readlane and the rows
+      // below subtract L[l][i] x_i (no reduction per step)
       const int cc = c0 + wv;
-      const C mine = lane < s0 ? A[(int64_t)(k0 + lane) * N + cc] : czero<C>();
+      C b = lane < s0 ? A[(int64_t)(k0 + lane) * N + cc] : czero<C>();
       for (int i = 0; i < s0; ++i) {
-        C part = lane < i ? cmulT(Lt[i][lane], Utop[lane][wv]) : czero<C>();
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          part.x += __shfl_xor(part.x, off);
-          part.y += __shfl_xor(part.y, off);
-        }
-        const C ai = make_c<C>(__shfl(mine.x, i), __shfl(mine.y, i));
-        const C x = csubT(ai, part);
-        // one wave: its LDS accesses are performed in order, so the next
-        // iteration's reads see this write
-        if (lane == 0) Utop[i][wv] = x;
-        __builtin_amdgcn_wave_barrier();
+        const C xi = make_c<C>(read_lane(b.x, i), read_lane(b.y, i));
+        if (lane > i && lane < s0) b = csubT(b, cmulT(Lt[lane][i], xi));
       }
-      if (lane < s0) A[(int64_t)(k0 + lane) * N + cc] = Utop[lane][wv];
+      if (lane < s0) {
+        Utop[lane][wv] = b;
+        A[(int64_t)(k0 + lane) * N + cc] = b;
+      }
     }
     __syncthreads();
     // (B) load sub-panel rows [c0, N) and subtract L[r, k0:c0] U[k0:c0, sub]
