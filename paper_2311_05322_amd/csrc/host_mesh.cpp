@@ -639,6 +639,19 @@ std::string build_decomposition(const Topology& T, int32_t nsub, int32_t overlap
     }
     Dc.pcol_ptr[c + 1] = (int64_t)Dc.p_edge.size();
   }
+  // ---- the same entries by destination edge (stable: colour order kept)
+  const size_t np = Dc.p_edge.size();
+  Dc.pg_ptr.assign(T.ne + 1, 0);
+  for (size_t k = 0; k < np; ++k) ++Dc.pg_ptr[Dc.p_edge[k] + 1];
+  for (int64_t e = 0; e < T.ne; ++e) Dc.pg_ptr[e + 1] += Dc.pg_ptr[e];
+  Dc.pg_row.resize(np);
+  Dc.pg_w.resize(np);
+  std::vector<int64_t> fill(Dc.pg_ptr.begin(), Dc.pg_ptr.end() - 1);
+  for (size_t k = 0; k < np; ++k) {
+    const int64_t q = fill[Dc.p_edge[k]]++;
+    Dc.pg_row[q] = Dc.p_row[k];
+    Dc.pg_w[q] = Dc.p_w[k];
+  }
   return "";
 }
 

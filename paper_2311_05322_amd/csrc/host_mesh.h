@@ -89,6 +89,12 @@ struct Decomposition {
   std::vector<int32_t> p_edge;
   std::vector<int64_t> p_row;
   std::vector<double> p_w;
+  // the same entries grouped by destination edge (pg_ptr [ne+1]), in colour
+  // order within an edge: a gather gives every edge its sum in the order
+  // the colour-by-colour accumulation would add it
+  std::vector<int64_t> pg_ptr;
+  std::vector<int64_t> pg_row;
+  std::vector<double> pg_w;
 };
 
 std::string build_decomposition(const Topology& T, int32_t nsub, int32_t overlap, int32_t nb,

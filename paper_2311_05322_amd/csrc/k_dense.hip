@@ -96,6 +96,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
   __shared__ int red_r[PT / 64];
   __shared__ int piv_row;
   __shared__ R piv_abs;
+  __shared__ int spv[PanelW<R>::W];
   __shared__ C Lt[NB][NB + 1];
   __shared__ C Xt[NB][NB + 1];
   __shared__ int sw_dst[MAXSW], sw_src[MAXSW];
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
         }
         piv_row = br;
         piv_abs = b;
-        pv[c] = br;
+        spv[j] = br;
       }
       __syncthreads();
       const int p = piv_row;
@@ -267,6 +268,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
         for (int j = 0; j < W; ++j) A[(int64_t)r * N + c0 + j] = a[i][j];
       }
     }
+    if (tid < W) pv[c0 + tid] = spv[tid];
     __syncthreads();
   }
   // ---- L11 -> L11^{-1} (unit lower, strictly lower part stored)

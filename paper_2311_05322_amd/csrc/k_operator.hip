@@ -510,21 +510,31 @@ __global__ void k_restrict(int64_t nrows, const int32_t* __restrict__ rowsrc, co
   xloc[idx] = from_c128<C>(x);
 }
 
-// z[edge[k]][j] += w[k] * zloc[row[k]][j] for the entries of one colour
-// (edges of one colour are distinct, so there is no write conflict)
+// z[e][j] = sum_k w[k] zloc[row[k]][j] over the entries k of edge e
+// (ptr[e] .. ptr[e+1], in colour order): 32 lanes per edge (lane j: column
+// j, then j + 32, ...), eight edges per workgroup; every edge is written
+// once, so no clearing pass and no write conflict. Workgroups are dealt to
+// the XCDs in contiguous bands of edges as in k_spmm.
 template <typename C>
-__global__ void k_prolong(int64_t n, const int32_t* __restrict__ edge, const int64_t* __restrict__ row,
-                          const double* __restrict__ w, const C* __restrict__ zloc, double2* __restrict__ z,
-                          int nrhs) {
-  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= n * nrhs) return;
-  int64_t k = idx / nrhs;
-  int j = (int)(idx - k * nrhs);
-  double2 s = to_c128(zloc[row[k] * nrhs + j]);
-  double wk = w[k];
-  int64_t o = (int64_t)edge[k] * nrhs + j;
-  double2 zz = z[o];
-  z[o] = make_double2(zz.x + wk * s.x, zz.y + wk * s.y);
+__global__ void __launch_bounds__(256) k_prolong(int64_t ne, const int64_t* __restrict__ ptr,
+                                                 const int64_t* __restrict__ row, const double* __restrict__ w,
+                                                 const C* __restrict__ zloc, double2* __restrict__ z, int nrhs) {
+  const int64_t per = gridDim.x / 8;
+  const int64_t blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t e = blk * 8 + threadIdx.x / 32;
+  if (e >= ne) return;
+  const int lane = threadIdx.x % 32;
+  const int64_t k0 = ptr[e], k1 = ptr[e + 1];
+  for (int j = lane; j < nrhs; j += 32) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t k = k0; k < k1; ++k) {
+      const double2 v = to_c128(zloc[row[k] * nrhs + j]);
+      const double wk = w[k];
+      acc.x += wk * v.x;
+      acc.y += wk * v.y;
+    }
+    z[e * nrhs + j] = acc;
+  }
 }
 
 // Per tetrahedron: gt[T][n] = k0^2 sum_pq M_{T,n}[p][q] W[p][q] with
@@ -712,14 +722,14 @@ template void launch_restrict<float2>(hipStream_t, int64_t, const int32_t*, cons
 template void launch_restrict<double2>(hipStream_t, int64_t, const int32_t*, const double2*, double2*, int);
 
 template <typename C>
-void launch_prolong(hipStream_t s, int64_t n, const int32_t* edge, const int64_t* row, const double* w,
+void launch_prolong(hipStream_t s, int64_t ne, const int64_t* ptr, const int64_t* row, const double* w,
                     const C* zloc, double2* z, int nrhs) {
-  int64_t m = n * nrhs;
-  if (m > 0) hipLaunchKernelGGL(k_prolong<C>, dim3(nblk(m, 256)), dim3(256), 0, s, n, edge, row, w, zloc, z, nrhs);
+  if (ne > 0)
+    hipLaunchKernelGGL(k_prolong<C>, dim3(nblk8(ne, 8)), dim3(256), 0, s, ne, ptr, row, w, zloc, z, nrhs);
 }
-template void launch_prolong<float2>(hipStream_t, int64_t, const int32_t*, const int64_t*, const double*,
+template void launch_prolong<float2>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*,
                                      const float2*, double2*, int);
-template void launch_prolong<double2>(hipStream_t, int64_t, const int32_t*, const int64_t*, const double*,
+template void launch_prolong<double2>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*,
                                       const double2*, double2*, int);
 
 }  // namespace mx

@@ -266,9 +266,9 @@ struct mx_ctx {
   // decomposition
   Decomposition dec;
   bool have_dec = false;
-  DBuf<int32_t> dofs, Npad, order, trsm_order, if_tet, if_lf, lsrc, p_edge, piv, status, pswap, perm, rowsrc, lpos,
+  DBuf<int32_t> dofs, Npad, order, trsm_order, if_tet, if_lf, lsrc, piv, status, pswap, perm, rowsrc, lpos,
       dense_edge;
-  DBuf<int64_t> dof_ptr, mat_off, vec_off, ldest, lptr, p_row;
+  DBuf<int64_t> dof_ptr, mat_off, vec_off, ldest, lptr, pg_ptr, pg_row;
   // band bookkeeping of the factorisation (LuBand) and the triangular-solve
   // ranges derived from it; lu_tiles / trsm_tiles: 64x64 tile products of the
   // last factorisation and of one lower + upper solve per right-hand side
@@ -276,7 +276,7 @@ struct mx_ctx {
   DBuf<int64_t> tptr, band_work;
   int band_np = 0;
   int64_t lu_tiles = 0, trsm_tiles_l = 0, trsm_tiles_u = 0;
-  DBuf<double> p_w;
+  DBuf<double> pg_w;
   std::vector<int32_t> Nsorted;
   DBuf<char> factors;
   int precision = MX_PREC_C128;
@@ -628,13 +628,8 @@ void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2*
     c->prof.end(K_COARSE);
   }
   if (tm) tm->begin(K_PROLONG);
-  launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, z);
-  if (xq) launch_fill_zero<double2>(c->stream, c->topo.ne * (int64_t)nrhs, q);
-  for (int col = 0; col < D.ncolour; ++col) {
-    int64_t a = D.pcol_ptr[col], b = D.pcol_ptr[col + 1];
-    launch_prolong<C>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xl, z, nrhs);
-    if (xq) launch_prolong<C>(c->stream, b - a, c->p_edge.p + a, c->p_row.p + a, c->p_w.p + a, xq, q, nrhs);
-  }
+  launch_prolong<C>(c->stream, c->topo.ne, c->pg_ptr.p, c->pg_row.p, c->pg_w.p, xl, z, nrhs);
+  if (xq) launch_prolong<C>(c->stream, c->topo.ne, c->pg_ptr.p, c->pg_row.p, c->pg_w.p, xq, q, nrhs);
   if (tm) tm->end(K_PROLONG);
 }
 
@@ -792,8 +787,8 @@ uint64_t step_signature(const mx_ctx* c, int nrhs, int m, double rtol) {
   };
   auto val = [&](auto v) { mix(&v, sizeof(v)); };
   const void* ptrs[] = {c->V.p, c->Z.p, c->xloc.p, c->factors.p, c->val.p, c->row_ptr.p, c->col.p,
-                        c->rowsrc.p, c->trsm_order.p, c->mat_off.p, c->Npad.p, c->vec_off.p, c->p_edge.p,
-                        c->p_row.p, c->p_w.p, c->dotpart.p, c->normpart.p, c->h1.p, c->h2.p, c->hn.p, c->H.p,
+                        c->rowsrc.p, c->trsm_order.p, c->mat_off.p, c->Npad.p, c->vec_off.p, c->pg_ptr.p,
+                        c->pg_row.p, c->pg_w.p, c->dotpart.p, c->normpart.p, c->h1.p, c->h2.p, c->hn.p, c->H.p,
                         c->cs.p, c->sn.p, c->g.p, c->bnorm.p, c->conv.p, c->kdone.p, c->res.p, c->trs_lo.p,
                         c->trs_hi.p, c->win_row.p, c->win_cp.p, c->win_ucol.p, c->win_lcol.p};
   mix(ptrs, sizeof(ptrs));
@@ -1620,7 +1615,6 @@ int coarse_prepare(mx_ctx* c) {
   CK(c->cP.alloc((size_t)nrows * NCO));
   launch_coarse_P(c->stream, nrows, c->row_sub.p, c->dofs.p, c->edges_dev.p, c->xyz.p, c->cbox.p, c->cP.p);
   CK(c->cpdp.alloc((size_t)nsub * NCO * NCO));
-  CK(c->p_w.n ? MX_OK : MX_OK);
   DBuf<double> Dw;
   CK(Dw.upload(D.D, c->stream));
   launch_pdp(c->stream, nsub, c->dof_ptr.p, c->cP.p, Dw.p, c->cpdp.p);
@@ -2116,9 +2110,9 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     CK(c->ldest.upload(d.ldest, c->stream));
     CK(c->lptr.upload(d.lptr, c->stream));
     CK(c->lsrc.upload(d.lsrc, c->stream));
-    CK(c->p_edge.upload(d.p_edge, c->stream));
-    CK(c->p_row.upload(d.p_row, c->stream));
-    CK(c->p_w.upload(d.p_w, c->stream));
+    CK(c->pg_ptr.upload(d.pg_ptr, c->stream));
+    CK(c->pg_row.upload(d.pg_row, c->stream));
+    CK(c->pg_w.upload(d.pg_w, c->stream));
     CK(c->lpos.upload(d.lpos, c->stream));
     CK(c->dense_edge.upload(d.dense_edge, c->stream));
     std::vector<int32_t> ord(nsub);

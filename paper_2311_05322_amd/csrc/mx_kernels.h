@@ -102,8 +102,9 @@ void launch_spmm(hipStream_t s, int64_t nrows, const int64_t* rp, const int32_t*
                  const double2* X, double2* Y, int nrhs, int variant = 0, const SpmmWindows* win = nullptr);
 template <typename C>
 void launch_restrict(hipStream_t s, int64_t nrows, const int32_t* rowsrc, const double2* v, C* xloc, int nrhs);
+// z[e] = sum over the entries of edge e (ptr [ne+1]) of w * zloc[row]
 template <typename C>
-void launch_prolong(hipStream_t s, int64_t n, const int32_t* edge, const int64_t* row, const double* w,
+void launch_prolong(hipStream_t s, int64_t ne, const int64_t* ptr, const int64_t* row, const double* w,
                     const C* zloc, double2* z, int nrhs);
 
 // dense subdomain factorisation and solves
