@@ -32,6 +32,22 @@ import workload  # noqa: E402
 import paper_2311_05322_amd as mx  # noqa: E402
 
 
+def solve_phantom(ctx, p, restart, want_E=False, rtol=None):
+    """One phantom of the batch on a context in block mode: topology and
+    partition (timed apart), then operator values, local matrices, LU and
+    the all-transmitter block FGMRES solve. Returns (E or None, info,
+    seconds of topology + partition, seconds of the solve)."""
+    t0 = time.perf_counter()
+    ctx.assemble(p.xyz, p.tet, p.eps, p.eps_kind, p.freq, p.eps_b)
+    ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, factor=False, restart=restart)
+    t_mesh = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx.assemble(None, None, p.eps, p.eps_kind, p.freq, p.eps_b, reuse_mesh=True)
+    ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, restart=restart)
+    E, _, info = ctx.solve(p.src_pos, p.src_mom, rtol=rtol or p.rtol, want_E=want_E)
+    return (E if want_E else None), info, t_mesh, time.perf_counter() - t0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--phantoms", type=int, default=8)
@@ -54,15 +70,7 @@ def main():
                                          nsub=sp["nsub"], overlap=1, nsrc=a.per_ring, rings=a.rings)
             print(f"[phantom {k}] c={sp['c'] * 1000:.2f} mm nsub={sp['nsub']} transmitters={len(p.src_pos)}",
                   file=sys.stderr, flush=True)
-            t0 = time.perf_counter()
-            ctx.assemble(p.xyz, p.tet, p.eps, p.eps_kind, p.freq, p.eps_b)
-            ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, factor=False, restart=a.restart)
-            t_mesh = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            ctx.assemble(None, None, p.eps, p.eps_kind, p.freq, p.eps_b, reuse_mesh=True)
-            ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64, restart=a.restart)
-            _, _, info = ctx.solve(p.src_pos, p.src_mom, rtol=p.rtol, want_E=False)
-            t_solve = time.perf_counter() - t0
+            _, info, t_mesh, t_solve = solve_phantom(ctx, p, a.restart)
             t_all += t_solve
             sz = ctx.sizes()
             _, dp, *_ = ctx.partition()

@@ -774,39 +774,55 @@ __global__ void __launch_bounds__(256, 2) k_lu_update_list(C_t<R>* __restrict__ 
 }
 
 // --------------------------------------------------------------------------
-// U_bb -> U_bb^{-1} in the upper part of every diagonal block
+// U_bb -> U_bb^{-1} in the upper part of every diagonal block. Column j of
+// Y = U^{-1}: Y[j][j] = 1/U[j][j], Y[i][j] = -(sum_{l=i+1}^{j} U[i][l] Y[l][j])
+// / U[i][i] for i < j. Four threads per column (thread 4j + q takes the terms
+// l = q mod 4, summed over the four with shuffles); one LDS array holds U in
+// its upper triangle and Y transposed in its strict lower triangle (Y's
+// diagonal apart), so a workgroup needs 34 KB and four fit on a compute unit.
 // --------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(64) k_inv_upper(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
-                                                  const int32_t* __restrict__ Npad,
-                                                  const int32_t* __restrict__ order) {
+__global__ void __launch_bounds__(256) k_inv_upper(C_t<R>* __restrict__ pool, const int64_t* __restrict__ mat_off,
+                                                   const int32_t* __restrict__ Npad,
+                                                   const int32_t* __restrict__ order) {
   typedef C_t<R> C;
   const int s = order[blockIdx.y];
   const int N = Npad[s];
   const int b0 = blockIdx.x * NB;
   if (b0 >= N) return;
   C* A = pool + mat_off[s];
-  __shared__ C U[NB][NB + 1];
-  __shared__ C Y[NB][NB + 1];
+  __shared__ C M[NB][NB + 1];   // M[i][l] = U[i][l] (l >= i); M[j][i] = Y[i][j] (i < j)
+  __shared__ C dinv[NB];        // 1 / U[i][i] = Y[i][i]
   const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 64) {
-    int i = e / NB, j = e % NB;
-    U[i][j] = A[(int64_t)(b0 + i) * N + b0 + j];
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, l = e % NB;
+    if (l >= i) M[i][l] = A[(int64_t)(b0 + i) * N + b0 + l];
   }
   __syncthreads();
-  const int j = tid;
-  // column j of Y = U^{-1}: Y[j][j] = 1/U[j][j],
-  // Y[i][j] = -(sum_{l=i+1}^{j} U[i][l] Y[l][j]) / U[i][i] for i < j
-  Y[j][j] = crecip(U[j][j]);
+  if (tid < NB) dinv[tid] = crecip(M[tid][tid]);
+  __syncthreads();
+  const int j = tid >> 2, q = tid & 3;
+  // Y[l][j] for l > i: Y[j][j] = dinv[j], otherwise M[j][l] (written below)
   for (int i = j - 1; i >= 0; --i) {
     C acc = czero<C>();
-    for (int l = i + 1; l <= j; ++l) acc = csubT(acc, cmulT(U[i][l], Y[l][j]));
-    Y[i][j] = cmulT(acc, crecip(U[i][i]));
+    for (int l = i + 1 + ((q - (i + 1)) & 3); l <= j; l += 4) {
+      const C y = l == j ? dinv[j] : M[j][l];
+      acc = csubT(acc, cmulT(M[i][l], y));
+    }
+    acc.x += __shfl_xor(acc.x, 1);
+    acc.y += __shfl_xor(acc.y, 1);
+    acc.x += __shfl_xor(acc.x, 2);
+    acc.y += __shfl_xor(acc.y, 2);
+    // one wave holds the four threads of column j: its LDS accesses are
+    // performed in order, so the next step's read of M[j][i] sees this write
+    if (q == 0) M[j][i] = cmulT(acc, dinv[i]);
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += 64) {
-    int i = e / NB, jj = e % NB;
-    if (jj >= i) A[(int64_t)(b0 + i) * N + b0 + jj] = Y[i][jj];
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, jj = e % NB;
+    if (jj > i) A[(int64_t)(b0 + i) * N + b0 + jj] = M[jj][i];
+    else if (jj == i) A[(int64_t)(b0 + i) * N + b0 + i] = dinv[i];
   }
 }
 
@@ -1207,7 +1223,7 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
     update(active(ke), pa, pa + LU_GROUP, ke / NB, ke / NB, 0, g0, LU_GROUP * NB);
   }
   MX_TB(K_LU_INV);
-  hipLaunchKernelGGL((k_inv_upper<R>), dim3(ceil_div(Nmax, NB), (unsigned)Nsorted.size()), dim3(64), 0, st, pool,
+  hipLaunchKernelGGL((k_inv_upper<R>), dim3(ceil_div(Nmax, NB), (unsigned)Nsorted.size()), dim3(256), 0, st, pool,
                      mat_off, Npad, order);
   MX_TE(K_LU_INV);
 }
