@@ -87,6 +87,10 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
   const int Nr = lim[3 * s];
   C* A = pool + mat_off[s];
   int32_t* pv = piv + vec_off[s];
+  // the launch holds PT * RPT rows from k0 (chosen on the host from the
+  // structural band, which bounds Nr); rows beyond would be skipped, so a
+  // bound that does not hold is reported (negative status) instead
+  if (threadIdx.x == 0 && Nr - k0 > PT * RPT) status[s] = -(k0 + 1);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
 
@@ -1128,8 +1132,9 @@ inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) /
 template <typename R>
 static void launch_panel(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad,
                          const int32_t* order, int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
-                         const int32_t* lim, int Nmax, int nact, int k0) {
-  const int m = Nmax - k0;
+                         const int32_t* lim, int Nmax, int nact, int k0, int rows) {
+  // rows of the panel that can be non-zero (structural bound from the host)
+  const int m = std::min(Nmax - k0, rows);
   if (m <= PT * 1)
     hipLaunchKernelGGL((k_lu_panel<R, 1>), dim3(nact), dim3(PT), 0, st, pool, mat_off, Npad, order, piv, vec_off,
                        status, pswap, lim, k0);
@@ -1154,7 +1159,8 @@ constexpr int UPDATE_GRID = 1024;   // workgroups of a tile-list update (2 per C
 template <typename R>
 void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
                int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
-               const std::vector<int32_t>& Nsorted, const LuBand& band, KTimer* tm) {
+               const std::vector<int32_t>& Nsorted, const LuBand& band, const std::vector<int32_t>& panel_rows,
+               KTimer* tm) {
   if (Nsorted.empty()) return;
   const int Nmax = Nsorted[0];
   const int nsub = (int)Nsorted.size();
@@ -1192,7 +1198,8 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
       MX_TB(K_LU_PANEL);
       hipLaunchKernelGGL(k_band_limits, dim3(ceil_div(nact, 256)), dim3(256), 0, st, nact, Npad, order, np, band.band0,
                          band.ext_l, band.ext_u, band.lim, ki);
-      launch_panel<R>(st, pool, mat_off, Npad, order, piv, vec_off, status, pswap, band.lim, Nmax, nact, ki);
+      launch_panel<R>(st, pool, mat_off, Npad, order, piv, vec_off, status, pswap, band.lim, Nmax, nact, ki,
+                      pk < (int)panel_rows.size() ? panel_rows[pk] : Nmax - ki);
       hipLaunchKernelGGL((k_band_l<R>), dim3(nact), dim3(256), 0, st, pool, mat_off, Npad, order, piv, vec_off, np,
                          band.ext_l, band.lim, ki);
       MX_TE(K_LU_PANEL);
@@ -1229,10 +1236,10 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
 }
 template void launch_lu<float>(hipStream_t, float2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
                                const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, const LuBand&,
-                               KTimer*);
+                               const std::vector<int32_t>&, KTimer*);
 template void launch_lu<double>(hipStream_t, double2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
                                 const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, const LuBand&,
-                                KTimer*);
+                                const std::vector<int32_t>&, KTimer*);
 
 void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int32_t* dense_edge,
                  const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc) {

@@ -2196,12 +2196,23 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     MX_HIP_CHECK(hipEventRecord(c->ev_lu[0], c->stream));
     const LuBand band{c->ext_l.p, c->ext_u.p, c->tptr.p, c->tbox.p, c->band_work.p, c->band0.p, c->band_lim.p,
                       c->band_np};
+    // rows a panel can touch: up to the last structural row tile of its own
+    // and all earlier columns (partial pivoting keeps L inside that bound)
+    std::vector<int32_t> panel_rows(c->band_np, 0);
+    for (int i = 0; i < D.nsub; ++i) {
+      const int nt = D.Npad[i] / 64;
+      int hi = -1;
+      for (int p = 0; p < nt; ++p) {
+        hi = std::max(hi, D.band0[(size_t)i * c->band_np + p]);
+        panel_rows[p] = std::max(panel_rows[p], 64 * (std::min(hi, nt - 1) + 1 - p));
+      }
+    }
     if (o.precision == MX_PREC_C64)
       launch_lu<float>(c->stream, (float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
-                       c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, &c->prof);
+                       c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, panel_rows, &c->prof);
     else
       launch_lu<double>(c->stream, (double2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
-                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, &c->prof);
+                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, panel_rows, &c->prof);
     c->prof.begin(K_LU_INV);
     launch_perm(c->stream, D.nsub, c->Npad.p, c->vec_off.p, c->dense_edge.p, c->piv.p, c->perm.p, c->rowsrc.p);
     c->prof.end(K_LU_INV);
@@ -2210,10 +2221,14 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     std::vector<int32_t> st(D.nsub);
     MX_HIP_CHECK(hipMemcpyAsync(st.data(), c->status.p, D.nsub * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     CK(sync(c));
-    for (int i = 0; i < D.nsub; ++i)
+    for (int i = 0; i < D.nsub; ++i) {
+      if (st[i] < 0)
+        return set_err(MX_EHIP, "factorisation of subdomain " + std::to_string(i) + ": rows beyond the structural "
+                                "band bound at column " + std::to_string(-st[i] - 1));
       if (st[i] != 0)
         return set_err(MX_EPIVOT, "zero pivot in subdomain " + std::to_string(i) + " at column " +
                                       std::to_string(st[i] - 1));
+    }
     float lu_ms = 0;
     MX_HIP_CHECK(hipEventElapsedTime(&lu_ms, c->ev_lu[0], c->ev_lu[1]));
     c->t_lu = 1e-3 * lu_ms;
