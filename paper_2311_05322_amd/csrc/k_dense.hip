@@ -36,12 +36,13 @@ constexpr int LU_GROUP = 8;
 constexpr int PT = 1024;     // panel workgroup size
 constexpr int MAXSW = 128;   // max distinct rows touched by one panel's swaps
 
-// register sub-panel width of k_lu_panel (1M chamber, complex64 panels per
-// factorisation: W = 4 -> 71.6 ms, 8 -> 63.4 ms: half the sub-panels, so half
-// the top-row solves and L re-reads)
+// register sub-panel width of k_lu_panel (1M chamber, panels per
+// factorisation: complex64 W = 4 -> 71.6 ms, 8 -> 63.4 ms, 16 -> 60.5 ms with
+// spills in the wider-row variants; complex128 W = 2 -> 121.5 ms, 4 -> 93.6
+// ms: fewer sub-panels, so fewer top-row solves and L re-reads)
 template <typename R> struct PanelW;
 template <> struct PanelW<float> { static constexpr int W = 8; };
-template <> struct PanelW<double> { static constexpr int W = 2; };
+template <> struct PanelW<double> { static constexpr int W = 4; };
 
 template <typename R> __device__ inline Acc_t<R> zacc() {
   Acc_t<R> z;
