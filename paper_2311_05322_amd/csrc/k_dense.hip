@@ -359,10 +359,26 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
   // the LDS, so twice the workgroups per CU)
   __shared__ C X[XR][NB + 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * NB; e += 256) {
-    int q = e / NB, j = e % NB;
-    const int src = mode == 2 ? k0 + q : ps[1 + MAXSW + q];
-    X[q][j] = A[(int64_t)src * N + cb + j];
+  // staging: eight loads per thread in flight before their LDS writes
+  // (complex64; complex128 keeps one at a time, its register allocation
+  // otherwise spills)
+  constexpr int SU = sizeof(R) == 4 ? 8 : 1;
+  for (int e0 = 0; e0 < n * NB; e0 += 256 * SU) {
+    C t[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = e0 + tid + 256 * u;
+      if (e < n * NB) {
+        const int q = e / NB, j = e % NB;
+        const int src = mode == 2 ? k0 + q : ps[1 + MAXSW + q];
+        t[u] = A[(int64_t)src * N + cb + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = e0 + tid + 256 * u;
+      if (e < n * NB) X[e / NB][e % NB] = t[u];
+    }
   }
   __syncthreads();
   if (cb < k0 || mode == 1) {
@@ -383,16 +399,24 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(C_t<R>* __restrict__ pool, 
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) { cre[ct] = zacc<R>(); cim[ct] = zacc<R>(); }
   const int ar = 16 * w + (lane & 15);
-  for (int kk = 0; kk < NB; kk += 4) {
-    const int kcol = kk + (lane >> 4);
-    C av;
-    if (kcol < ar) av = A[(int64_t)(k0 + ar) * N + k0 + kcol];
-    else if (kcol == ar) av = cone<C>();
-    else av = czero<C>();
+  // this lane's elements of L11^{-1} (unit lower), loaded KB steps at a time
+  // before their products (all 16 for complex64, one for complex128)
+  constexpr int KB = sizeof(R) == 4 ? NB / 4 : 1;
+  for (int kq0 = 0; kq0 < NB / 4; kq0 += KB) {
+    C avs[KB];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      C bv = X[kk + (lane >> 4)][16 * ct + (lane & 15)];
-      cmfma<R>(av, bv, cre[ct], cim[ct]);
+    for (int u = 0; u < KB; ++u) {
+      const int kcol = 4 * (kq0 + u) + (lane >> 4);
+      const C v = A[(int64_t)(k0 + ar) * N + k0 + kcol];
+      avs[u] = kcol < ar ? v : (kcol == ar ? cone<C>() : czero<C>());
+    }
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        C bv = X[4 * (kq0 + u) + (lane >> 4)][16 * ct + (lane & 15)];
+        cmfma<R>(avs[u], bv, cre[ct], cim[ct]);
+      }
     }
   }
 #pragma unroll
