@@ -189,7 +189,19 @@ int mx_set_stream(mx_ctx* ctx, void* hip_stream);
  *         with the b-th smallest, 0 = largest first) x right-hand-side
  *         columns per workgroup (32, or 16 with twice the workgroups and
  *         four resident per compute unit).
- * enable = 0 switches it off and restores variant 0 / paired order / 32. */
+ * and, at the first factorisation (mx_setup_schwarz) of a shape bucket
+ * (precision, subdomain count, largest subdomain / 4096 unknowns):
+ *   factorisation: panels per trailing-update pass of the banded LU
+ *         (1, 2, 4 or 8), each timed on a whole factorisation of the
+ *         problem's own local matrices (the set-up then factors once more
+ *         with the fastest).
+ * Tuning cache: when the environment variable MX_TUNE_CACHE names a file,
+ * results are looked up there first (a hit skips the timing) and new ones
+ * are added to it; the file is a JSON object, one entry per line, keyed by
+ * "solve:<hash of the problem shape>" and "lu:<precision>:<subdomains>:
+ * <largest subdomain / 4096>", written through a temporary file and a rename.
+ * enable = 0 switches it off and restores variant 0 / paired order / 32 /
+ * two panels per pass. */
 typedef struct {
   int32_t spmm_variant;
   int32_t trsm_paired;
@@ -198,8 +210,17 @@ typedef struct {
                           1e30 if the variant does not apply)               */
   double trsm_ms[4];   /* one lower + upper solve: [largest first / 32 columns,
                           paired / 32, largest first / 16, paired / 16]      */
+  int32_t lu_group;    /* panels per trailing-update pass of the factorisation */
+  double lu_ms[4];     /* one factorisation with 1, 2, 4, 8 panels per pass
+                          (0 if not timed)                                   */
+  int32_t from_cache;  /* bit 0: SpMM / solve variants, bit 1: panel group,
+                          taken from the tuning cache                        */
 } mx_tuning;
 int mx_set_autotune(mx_ctx* ctx, int enable);
+/* Fix the factorisation's panels per trailing-update pass (1..16; the
+ * factors differ only by rounding), or 0 to let the autotuner pick it again.
+ * Takes effect at the next mx_setup_schwarz. Errors: MX_EINVAL. */
+int mx_set_lu_group(mx_ctx* ctx, int32_t group);
 /* Fix the variants (switches the autotuner off): spmm_variant 0/1/2,
  * trsm_paired 0/1, trsm_cols 16/32. Results do not depend on the variants
  * beyond rounding. Errors: MX_EINVAL. */

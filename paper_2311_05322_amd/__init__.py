@@ -26,7 +26,7 @@ MX_KRYLOV_PSEUDO_BLOCK, MX_KRYLOV_BLOCK, MX_KRYLOV_BLOCK_CGS2 = 0, 1, 2
 EXPORTS = ["mx_create", "mx_destroy", "mx_assemble", "mx_setup_schwarz", "mx_solve", "mx_solve_rhs",
            "mx_apply_operator", "mx_apply_preconditioner", "mx_apply_preconditioner_noalloc", "mx_get_sizes", "mx_get_topology",
            "mx_get_matrix_values", "mx_get_partition", "mx_get_local_matrix", "mx_point_functionals",
-           "mx_set_stream", "mx_set_autotune", "mx_set_tuning", "mx_get_tuning", "mx_set_graphs", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_coarse_num_params", "mx_coarse_init",
+           "mx_set_stream", "mx_set_autotune", "mx_set_lu_group", "mx_set_tuning", "mx_get_tuning", "mx_set_graphs", "mx_set_profiling", "mx_get_kernel_times", "mx_gradient", "mx_coarse_num_params", "mx_coarse_init",
            "mx_coarse_set_weights", "mx_coarse_get_weights", "mx_coarse_features", "mx_coarse_forward",
            "mx_coarse_loss_grad", "mx_coarse_hidden", "mx_coarse_adam_step", "mx_coarse_collect", "mx_coarse_clear", "mx_coarse_train", "mx_set_ports",
            "mx_solve_ports", "mx_set_krylov", "mx_last_error"]
@@ -86,7 +86,8 @@ class Sizes(ct.Structure):
 
 class Tuning(ct.Structure):
     _fields_ = [("spmm_variant", ct.c_int32), ("trsm_paired", ct.c_int32), ("trsm_cols", ct.c_int32),
-                ("spmm_ms", ct.c_double * 3), ("trsm_ms", ct.c_double * 4)]
+                ("spmm_ms", ct.c_double * 3), ("trsm_ms", ct.c_double * 4), ("lu_group", ct.c_int32),
+                ("lu_ms", ct.c_double * 4), ("from_cache", ct.c_int32)]
 
 
 class KernelTimes(ct.Structure):
@@ -124,6 +125,7 @@ def lib():
             "mx_set_profiling": [vp, ct.c_int],
             "mx_set_graphs": [vp, ct.c_int],
             "mx_set_autotune": [vp, ct.c_int],
+            "mx_set_lu_group": [vp, i32],
             "mx_set_tuning": [vp, i32, i32, i32],
             "mx_get_tuning": [vp, vp],
             "mx_get_kernel_times": [vp, ct.POINTER(KernelTimes)],
@@ -229,13 +231,20 @@ class Context:
         """Fix the kernel variants (the autotuner is switched off)."""
         _check(lib().mx_set_tuning(self._h, int(spmm_variant), int(trsm_paired), int(trsm_cols)))
 
+    def set_lu_group(self, group=0):
+        """Fix the factorisation's panels per trailing-update pass (1..16), or
+        0 to let the autotuner pick it; takes effect at the next set-up."""
+        _check(lib().mx_set_lu_group(self._h, int(group)))
+
     def tuning(self):
         """Variants picked by the autotuner and their measured times (ms)."""
         t = Tuning()
         _check(lib().mx_get_tuning(self._h, ct.byref(t)))
         return {"spmm_variant": t.spmm_variant, "trsm_paired": t.trsm_paired, "trsm_cols": t.trsm_cols,
                 "spmm_ms": list(t.spmm_ms),
-                "trsm_ms_first32_paired32_first16_paired16": list(t.trsm_ms)}
+                "trsm_ms_first32_paired32_first16_paired16": list(t.trsm_ms),
+                "lu_group": t.lu_group, "lu_ms_groups_1_2_4_8": list(t.lu_ms),
+                "from_cache": {"solve": bool(t.from_cache & 1), "lu": bool(t.from_cache & 2)}}
 
     def set_krylov(self, block=True, two_pass=False):
         """Block FGMRES (one Krylov space for all right-hand sides; two_pass:

@@ -21,7 +21,8 @@
 //                  and forms U12 = L11^{-1} A12 (MFMA); k_lu_rowswap the
 //                  permutation alone;
 //   k_lu_update    A22 -= L21 U12 on 64x64 tiles (MFMA, LDS-staged operands),
-//                  the trailing matrix once per group of LU_GROUP panels.
+//                  the trailing matrix once per group of panels (group
+//                  size a launch parameter, picked by the autotuner).
 #include "mx_device.h"
 #include "mx_kernels.h"
 
@@ -32,7 +33,6 @@ namespace {
 constexpr int NB = 64;
 // panels per pass over the trailing matrix (1M chamber, complex64 update:
 // 2 -> 1.54 s, 4 -> 1.44 s, 8 -> 1.38 s, 16 -> 1.37 s per factorisation)
-constexpr int LU_GROUP = 8;
 constexpr int PT = 1024;     // panel workgroup size
 constexpr int MAXSW = 128;   // max distinct rows touched by one panel's swaps
 
@@ -1188,8 +1188,8 @@ template <typename R>
 void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
                int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
                const std::vector<int32_t>& Nsorted, const LuBand& band, const std::vector<int32_t>& panel_rows,
-               KTimer* tm) {
-  if (Nsorted.empty()) return;
+               int group, KTimer* tm) {
+  if (Nsorted.empty() || group < 1) return;
   const int Nmax = Nsorted[0];
   const int nsub = (int)Nsorted.size();
   auto active = [&](int k) {  // subdomains with N > k (Nsorted is descending)
@@ -1209,15 +1209,15 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
                        band.tptr, band.tbox, ct0, kl, kd);
     MX_TE(K_LU_UPDATE);
   };
-  // Panels are taken in groups of LU_GROUP: the trailing matrix gets one
-  // LU_GROUP*64-deep pass per group. Inside a group, panel i (i > 0) first
+  // Panels are taken in groups of `group`: the trailing matrix gets one
+  // group*64-deep pass per group. Inside a group, panel i (i > 0) first
   // receives the group's earlier panels' update of its own column block
   // (rows below it), is factored, permutes the rows outside it, receives the
   // earlier panels' update of its own row block right of it, and then forms
   // its U12.
-  for (int g0 = 0; g0 < Nmax; g0 += LU_GROUP * NB) {
+  for (int g0 = 0; g0 < Nmax; g0 += group * NB) {
     const int pa = g0 / NB;
-    for (int i = 0; i < LU_GROUP; ++i) {
+    for (int i = 0; i < group; ++i) {
       const int ki = g0 + i * NB;
       if (ki >= Nmax) break;
       const int nact = active(ki);
@@ -1253,9 +1253,9 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
                          band.lim, ki);
       MX_TE(K_LU_ROWPANEL);
     }
-    const int ke = g0 + LU_GROUP * NB;
+    const int ke = g0 + group * NB;
     if (ke >= Nmax) break;
-    update(active(ke), pa, pa + LU_GROUP, ke / NB, ke / NB, 0, g0, LU_GROUP * NB);
+    update(active(ke), pa, pa + group, ke / NB, ke / NB, 0, g0, group * NB);
   }
   MX_TB(K_LU_INV);
   hipLaunchKernelGGL((k_inv_upper<R>), dim3(ceil_div(Nmax, NB), (unsigned)Nsorted.size()), dim3(256), 0, st, pool,
@@ -1264,10 +1264,10 @@ void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32
 }
 template void launch_lu<float>(hipStream_t, float2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
                                const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, const LuBand&,
-                               const std::vector<int32_t>&, KTimer*);
+                               const std::vector<int32_t>&, int, KTimer*);
 template void launch_lu<double>(hipStream_t, double2*, const int64_t*, const int32_t*, const int32_t*, int32_t*,
                                 const int64_t*, int32_t*, int32_t*, const std::vector<int32_t>&, const LuBand&,
-                                const std::vector<int32_t>&, KTimer*);
+                                const std::vector<int32_t>&, int, KTimer*);
 
 void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int32_t* dense_edge,
                  const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc) {

@@ -15,10 +15,16 @@
 #include "host_mesh.h"
 #include "mx_device.h"
 #include "mx_kernels.h"
+#include "tune_cache.h"
 
 namespace mx {
 
 thread_local std::string g_err;
+
+// candidate panel groups of the factorisation autotuner (panels per
+// trailing-update pass of the banded LU); the default without it
+constexpr int kLuGroups[4] = {1, 2, 4, 8};
+constexpr int kLuGroupDefault = 2;
 
 int set_err(int code, const std::string& msg) {
   g_err = msg;
@@ -353,6 +359,13 @@ struct mx_ctx {
   int tune_trsm_paired = 1;    // 1: size-paired workgroup order, 0: largest first
   int tune_trsm_cols = 32;     // right-hand-side columns per triangular-solve workgroup
   double tune_spmm_ms[3] = {0, 0, 0}, tune_trsm_ms[4] = {0, 0, 0, 0};
+  // panels per trailing-update pass of the banded factorisation, picked by
+  // timing whole factorisations at the first set-up of a shape bucket
+  bool lu_autotune = true;
+  uint64_t tune_lu_key = 0;
+  int tune_lu_group = kLuGroupDefault;
+  double tune_lu_ms[4] = {0, 0, 0, 0};
+  bool tune_from_cache = false, tune_lu_from_cache = false;
   bool graphs_on = true;
   uint64_t g_sig = 0;         // signature of the buffers, sizes and tolerance captured
   std::vector<hipGraphExec_t> gexec;
@@ -743,6 +756,24 @@ int autotune(mx_ctx* c, int nrhs) {
   mixv(c->precision);
   mixv(nrhs);
   if (key == c->tune_key) return MX_OK;
+  char hex[32];
+  std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)key);
+  const std::string ckey = std::string("solve:") + hex;
+  TuneFields tf;
+  if (c->factored && tune_cache_get(ckey, tf) && tf.count("spmm") && tf.count("trsm_paired") && tf.count("trsm_cols")) {
+    const long long v = tf["spmm"], pr = tf["trsm_paired"], tc = tf["trsm_cols"];
+    if (v >= 0 && v <= 2 && !(v == 1 && nrhs > 32) && !(v == 2 && !c->win_ok) && (pr == 0 || pr == 1) &&
+        (tc == 16 || tc == 32)) {
+      c->tune_spmm = (int)v;
+      c->tune_trsm_paired = (int)pr;
+      c->tune_trsm_cols = (int)tc;
+      for (double& t : c->tune_spmm_ms) t = 0;
+      for (double& t : c->tune_trsm_ms) t = 0;
+      c->tune_from_cache = true;
+      c->tune_key = key;
+      return MX_OK;
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   MX_HIP_CHECK(hipEventCreate(&e0));
   MX_HIP_CHECK(hipEventCreate(&e1));
@@ -774,7 +805,13 @@ int autotune(mx_ctx* c, int nrhs) {
     rc = c->precision == MX_PREC_C64 ? autotune_trsm<float>(c, nrhs, e0, e1) : autotune_trsm<double>(c, nrhs, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (rc == MX_OK) c->tune_key = key;
+  if (rc == MX_OK) {
+    c->tune_key = key;
+    c->tune_from_cache = false;
+    if (c->factored)
+      tune_cache_put(ckey, {{"spmm", c->tune_spmm}, {"trsm_paired", c->tune_trsm_paired},
+                            {"trsm_cols", c->tune_trsm_cols}});
+  }
   return rc;
 }
 
@@ -1940,12 +1977,24 @@ int mx_set_stream(mx_ctx* c, void* hip_stream) {
 int mx_set_autotune(mx_ctx* c, int enable) {
   if (!c) return set_err(MX_EINVAL, "NULL context");
   c->autotune_on = enable != 0;
+  c->lu_autotune = true;
   if (!c->autotune_on) {
     c->tune_key = 0;
     c->tune_spmm = 0;
     c->tune_trsm_paired = 1;
     c->tune_trsm_cols = 32;
+    c->tune_lu_key = 0;
+    c->tune_lu_group = kLuGroupDefault;
   }
+  return MX_OK;
+}
+
+int mx_set_lu_group(mx_ctx* c, int32_t group) {
+  if (!c) return set_err(MX_EINVAL, "NULL context");
+  if (group < 0 || group > 16) return set_err(MX_EINVAL, "panel group: 1..16, or 0 for the autotuner");
+  c->tune_lu_key = 0;
+  c->lu_autotune = group == 0;
+  c->tune_lu_group = group == 0 ? kLuGroupDefault : group;
   return MX_OK;
 }
 
@@ -1971,6 +2020,9 @@ int mx_get_tuning(mx_ctx* c, mx_tuning* out) {
   out->trsm_cols = c->tune_trsm_cols;
   for (int i = 0; i < 3; ++i) out->spmm_ms[i] = c->tune_spmm_ms[i];
   for (int i = 0; i < 4; ++i) out->trsm_ms[i] = c->tune_trsm_ms[i];
+  out->lu_group = c->tune_lu_group;
+  for (int i = 0; i < 4; ++i) out->lu_ms[i] = c->tune_lu_ms[i];
+  out->from_cache = (c->tune_from_cache ? 1 : 0) | (c->tune_lu_from_cache ? 2 : 0);
   return MX_OK;
 }
 
@@ -2081,6 +2133,127 @@ int mx_assemble(mx_ctx* c, const mx_mesh* mesh, const mx_c128* eps, int eps_kind
   return MX_OK;
 }
 
+// local ORAS matrices of this permittivity gathered into the factor pool
+// (the precision of c->precision); tm: per-kernel profiler or NULL
+int build_local(mx_ctx* c, KTimer* tm) {
+  const Decomposition& D = c->dec;
+  const size_t nent = (size_t)D.mat_off[D.nsub];
+  const int64_t nloc = (int64_t)D.ldest.size();
+  if (tm) tm->begin(K_LOCAL);
+  const bool c64 = c->precision == MX_PREC_C64;
+  if (c64) {
+    float2* F = (float2*)c->factors.p;
+    launch_fill_zero<float2>(c->stream, nent, F);
+    launch_gather_dense<float2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
+    launch_pad_identity<float2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
+  } else {
+    double2* F = (double2*)c->factors.p;
+    launch_fill_zero<double2>(c->stream, nent, F);
+    launch_gather_dense<double2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
+    launch_pad_identity<double2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
+  }
+  if (pec_active(c)) {
+    if (!c->pec_local_ready) {
+      // local indices of metallic edges per subdomain
+      std::vector<char> pec(c->topo.ne, 0);
+      for (int32_t e : c->pec_list) pec[e] = 1;
+      std::vector<int64_t> ptr(1, 0);
+      std::vector<int32_t> idx;
+      for (int sd = 0; sd < D.nsub; ++sd) {
+        for (int64_t r = D.dof_ptr[sd]; r < D.dof_ptr[sd + 1]; ++r)
+          if (pec[D.dofs[r]]) idx.push_back(D.lpos[r]);
+        ptr.push_back((int64_t)idx.size());
+      }
+      CK(c->pl_ptr.upload(ptr, c->stream));
+      CK(c->pl_idx.upload(idx.empty() ? std::vector<int32_t>(1, 0) : idx, c->stream));
+      c->pec_local_ready = true;
+    }
+    if (c64)
+      launch_pec_local<float2>(c->stream, D.nsub, c->Npad.p, c->mat_off.p, c->pl_ptr.p, c->pl_idx.p,
+                               (float2*)c->factors.p);
+    else
+      launch_pec_local<double2>(c->stream, D.nsub, c->Npad.p, c->mat_off.p, c->pl_ptr.p, c->pl_idx.p,
+                                (double2*)c->factors.p);
+  }
+  if (tm) tm->end(K_LOCAL);
+  MX_HIP_CHECK(hipGetLastError());
+  return MX_OK;
+}
+
+// one banded factorisation (and the row permutation of the restriction) of
+// the local matrices in the pool with `group` panels per trailing-update
+// pass; ms: its device time; tm: per-kernel profiler or NULL
+int factor_once(mx_ctx* c, int group, const std::vector<int32_t>& panel_rows, KTimer* tm, float* ms) {
+  const Decomposition& D = c->dec;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((D.nsub + 255) / 256)), dim3(256), 0, c->stream, D.nsub,
+                     c->status.p);
+  MX_HIP_CHECK(hipEventRecord(c->ev_lu[0], c->stream));
+  const LuBand band{c->ext_l.p, c->ext_u.p, c->tptr.p, c->tbox.p, c->band_work.p, c->band0.p, c->band_lim.p,
+                    c->band_np};
+  if (c->precision == MX_PREC_C64)
+    launch_lu<float>(c->stream, (float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p, c->vec_off.p,
+                     c->status.p, c->pswap.p, c->Nsorted, band, panel_rows, group, tm);
+  else
+    launch_lu<double>(c->stream, (double2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
+                      c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, panel_rows, group, tm);
+  if (tm) tm->begin(K_LU_INV);
+  launch_perm(c->stream, D.nsub, c->Npad.p, c->vec_off.p, c->dense_edge.p, c->piv.p, c->perm.p, c->rowsrc.p);
+  if (tm) tm->end(K_LU_INV);
+  MX_HIP_CHECK(hipEventRecord(c->ev_lu[1], c->stream));
+  MX_HIP_CHECK(hipGetLastError());
+  std::vector<int32_t> st(D.nsub);
+  MX_HIP_CHECK(hipMemcpyAsync(st.data(), c->status.p, D.nsub * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  CK(sync(c));
+  for (int i = 0; i < D.nsub; ++i) {
+    if (st[i] < 0)
+      return set_err(MX_EHIP, "factorisation of subdomain " + std::to_string(i) + ": rows beyond the structural "
+                              "band bound at column " + std::to_string(-st[i] - 1));
+    if (st[i] != 0)
+      return set_err(MX_EPIVOT, "zero pivot in subdomain " + std::to_string(i) + " at column " +
+                                    std::to_string(st[i] - 1));
+  }
+  MX_HIP_CHECK(hipEventElapsedTime(ms, c->ev_lu[0], c->ev_lu[1]));
+  return MX_OK;
+}
+
+// Factorisation autotuner: at the first set-up of a shape bucket (precision,
+// subdomain count, largest subdomain / 4096 unknowns) every candidate panel
+// group is timed on a whole factorisation of this problem's own local
+// matrices and the fastest is kept (and stored in the tuning cache under the
+// bucket's key, or taken from it). *tuned: the candidates ran, so the pool
+// holds factors and the caller rebuilds the local matrices.
+int autotune_lu(mx_ctx* c, const std::vector<int32_t>& panel_rows, bool* tuned) {
+  *tuned = false;
+  if (!c->autotune_on || !c->lu_autotune) return MX_OK;
+  const int nmax = c->Nsorted.empty() ? 0 : c->Nsorted[0];
+  const uint64_t key = ((uint64_t)(c->precision + 1) << 48) | ((uint64_t)c->dec.nsub << 16) | (uint64_t)(nmax >> 12);
+  if (key == c->tune_lu_key) return MX_OK;
+  const std::string ckey = "lu:" + std::to_string(c->precision) + ":" + std::to_string(c->dec.nsub) + ":" +
+                           std::to_string(nmax >> 12);
+  TuneFields tf;
+  if (tune_cache_get(ckey, tf) && tf.count("group") && tf["group"] >= 1 && tf["group"] <= 16) {
+    c->tune_lu_group = (int)tf["group"];
+    for (double& t : c->tune_lu_ms) t = 0;
+    c->tune_lu_from_cache = true;
+    c->tune_lu_key = key;
+    return MX_OK;
+  }
+  int best = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (i > 0) CK(build_local(c, nullptr));
+    float ms = 0;
+    *tuned = true;
+    CK(factor_once(c, kLuGroups[i], panel_rows, nullptr, &ms));
+    c->tune_lu_ms[i] = ms;
+    if (ms < c->tune_lu_ms[best]) best = i;
+  }
+  c->tune_lu_group = kLuGroups[best];
+  c->tune_lu_from_cache = false;
+  c->tune_lu_key = key;
+  tune_cache_put(ckey, {{"group", c->tune_lu_group}});
+  return MX_OK;
+}
+
 int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_opts* opts) {
   if (!c) return set_err(MX_EINVAL, "NULL context");
   if (!c->assembled) return set_err(MX_ESTATE, "mx_assemble must come first");
@@ -2151,51 +2324,9 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
   if (c->precision != o.precision) c->factors.release();
   c->precision = o.precision;
   CK(c->factors.alloc(nent * elem_bytes(o.precision)));
-  const int64_t nloc = (int64_t)D.ldest.size();
-  c->prof.begin(K_LOCAL);
-  if (o.precision == MX_PREC_C64) {
-    float2* F = (float2*)c->factors.p;
-    launch_fill_zero<float2>(c->stream, nent, F);
-    launch_gather_dense<float2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
-    launch_pad_identity<float2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
-  } else {
-    double2* F = (double2*)c->factors.p;
-    launch_fill_zero<double2>(c->stream, nent, F);
-    launch_gather_dense<double2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
-    launch_pad_identity<double2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
-  }
-  if (pec_active(c)) {
-    if (!c->pec_local_ready) {
-      // local indices of metallic edges per subdomain
-      std::vector<char> pec(c->topo.ne, 0);
-      for (int32_t e : c->pec_list) pec[e] = 1;
-      std::vector<int64_t> ptr(1, 0);
-      std::vector<int32_t> idx;
-      for (int sd = 0; sd < D.nsub; ++sd) {
-        for (int64_t r = D.dof_ptr[sd]; r < D.dof_ptr[sd + 1]; ++r)
-          if (pec[D.dofs[r]]) idx.push_back(D.lpos[r]);
-        ptr.push_back((int64_t)idx.size());
-      }
-      CK(c->pl_ptr.upload(ptr, c->stream));
-      CK(c->pl_idx.upload(idx.empty() ? std::vector<int32_t>(1, 0) : idx, c->stream));
-      c->pec_local_ready = true;
-    }
-    if (o.precision == MX_PREC_C64)
-      launch_pec_local<float2>(c->stream, D.nsub, c->Npad.p, c->mat_off.p, c->pl_ptr.p, c->pl_idx.p,
-                               (float2*)c->factors.p);
-    else
-      launch_pec_local<double2>(c->stream, D.nsub, c->Npad.p, c->mat_off.p, c->pl_ptr.p, c->pl_idx.p,
-                                (double2*)c->factors.p);
-  }
-  c->prof.end(K_LOCAL);
-  MX_HIP_CHECK(hipGetLastError());
+  CK(build_local(c, &c->prof));
   c->local_ready = true;
   if (o.factor) {
-    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((D.nsub + 255) / 256)), dim3(256), 0, c->stream, D.nsub,
-                       c->status.p);
-    MX_HIP_CHECK(hipEventRecord(c->ev_lu[0], c->stream));
-    const LuBand band{c->ext_l.p, c->ext_u.p, c->tptr.p, c->tbox.p, c->band_work.p, c->band0.p, c->band_lim.p,
-                      c->band_np};
     // rows a panel can touch: up to the last structural row tile of its own
     // and all earlier columns (partial pivoting keeps L inside that bound)
     std::vector<int32_t> panel_rows(c->band_np, 0);
@@ -2207,30 +2338,11 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
         panel_rows[p] = std::max(panel_rows[p], 64 * (std::min(hi, nt - 1) + 1 - p));
       }
     }
-    if (o.precision == MX_PREC_C64)
-      launch_lu<float>(c->stream, (float2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
-                       c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, panel_rows, &c->prof);
-    else
-      launch_lu<double>(c->stream, (double2*)c->factors.p, c->mat_off.p, c->Npad.p, c->order.p, c->piv.p,
-                        c->vec_off.p, c->status.p, c->pswap.p, c->Nsorted, band, panel_rows, &c->prof);
-    c->prof.begin(K_LU_INV);
-    launch_perm(c->stream, D.nsub, c->Npad.p, c->vec_off.p, c->dense_edge.p, c->piv.p, c->perm.p, c->rowsrc.p);
-    c->prof.end(K_LU_INV);
-    MX_HIP_CHECK(hipEventRecord(c->ev_lu[1], c->stream));
-    MX_HIP_CHECK(hipGetLastError());
-    std::vector<int32_t> st(D.nsub);
-    MX_HIP_CHECK(hipMemcpyAsync(st.data(), c->status.p, D.nsub * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    CK(sync(c));
-    for (int i = 0; i < D.nsub; ++i) {
-      if (st[i] < 0)
-        return set_err(MX_EHIP, "factorisation of subdomain " + std::to_string(i) + ": rows beyond the structural "
-                                "band bound at column " + std::to_string(-st[i] - 1));
-      if (st[i] != 0)
-        return set_err(MX_EPIVOT, "zero pivot in subdomain " + std::to_string(i) + " at column " +
-                                      std::to_string(st[i] - 1));
-    }
+    bool tuned = false;
+    CK(autotune_lu(c, panel_rows, &tuned));
+    if (tuned) CK(build_local(c, nullptr));  // the candidates' factorisations consumed the local matrices
     float lu_ms = 0;
-    MX_HIP_CHECK(hipEventElapsedTime(&lu_ms, c->ev_lu[0], c->ev_lu[1]));
+    CK(factor_once(c, c->tune_lu_group, panel_rows, &c->prof, &lu_ms));
     c->t_lu = 1e-3 * lu_ms;
     CK(triangular_ranges(c));
     c->factored = true;

@@ -129,12 +129,13 @@ struct LuBand {
 };
 // panel_rows[p]: bound on the rows from panel p's first row that can hold
 // non-zeros in its columns, over all subdomains (from the structural band);
-// status[s] < 0 reports a panel whose rows exceeded it
+// status[s] < 0 reports a panel whose rows exceeded it; group: panels per
+// trailing-update pass (>= 1)
 template <typename R>
 void launch_lu(hipStream_t st, C_t<R>* pool, const int64_t* mat_off, const int32_t* Npad, const int32_t* order,
                int32_t* piv, const int64_t* vec_off, int32_t* status, int32_t* pswap,
                const std::vector<int32_t>& Nsorted, const LuBand& band, const std::vector<int32_t>& panel_rows,
-               KTimer* tm);
+               int group, KTimer* tm);
 void launch_perm(hipStream_t st, int32_t nsub, const int32_t* Npad, const int64_t* vec_off, const int32_t* dense_edge,
                  const int32_t* piv, int32_t* perm_scratch, int32_t* rowsrc);
 template <typename R>

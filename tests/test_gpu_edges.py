@@ -236,6 +236,10 @@ def test_context_on_caller_stream():
     for stream in (None, st.cuda_stream):
         ctx = mx.Context(0, stream=stream)
         try:
+            # same kernel variants in both contexts (the autotuner's timing
+            # could pick different ones, which agree only to rounding)
+            ctx.set_tuning(1, 1, 32)
+            ctx.set_lu_group(2)
             ctx.assemble(p.xyz, p.tet, p.eps, p.eps_kind, p.freq, p.eps_b)
             ctx.setup_schwarz(p.nsub, p.overlap)
             E, S, info = ctx.solve(p.src_pos, p.src_mom, rtol=1e-10)
@@ -244,3 +248,41 @@ def test_context_on_caller_stream():
         finally:
             ctx.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_tuning_cache(tmp_path, monkeypatch):
+    """With MX_TUNE_CACHE set, the first context times the variants and the
+    panel groups and stores its picks; a second context on the same problem
+    takes them from the file without timing and computes bitwise the same
+    fields (same kernels in the same order)."""
+    import json
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("MX_TUNE_CACHE", str(path))
+    print("[case] edges: tuning cache c=30mm nsub=8", flush=True)
+    p = workload.chamber_problem(c=0.03, nsub=8, overlap=1, nsrc=4)
+    outs = []
+    for _ in range(2):
+        ctx = mx.Context(0)
+        try:
+            ctx.assemble(p.xyz, p.tet, p.eps, p.eps_kind, p.freq, p.eps_b)
+            ctx.setup_schwarz(p.nsub, p.overlap, precision=mx.MX_PREC_C64)
+            E, S, info = ctx.solve(p.src_pos, p.src_mom, rtol=1e-10)
+            assert info["converged"]
+            outs.append((E, ctx.tuning()))
+        finally:
+            ctx.close()
+    (E0, t0), (E1, t1) = outs
+    print(t0, t1, flush=True)
+    assert t0["from_cache"] == {"solve": False, "lu": False}
+    assert min(t0["lu_ms_groups_1_2_4_8"]) > 0
+    assert t1["from_cache"] == {"solve": True, "lu": True}
+    assert t1["lu_ms_groups_1_2_4_8"] == [0.0] * 4
+    for k in ("spmm_variant", "trsm_paired", "trsm_cols", "lu_group"):
+        assert t1[k] == t0[k], k
+    assert np.array_equal(E0, E1)
+    data = json.loads(path.read_text())
+    lu = [v for k, v in data.items() if k.startswith("lu:1:8:")]
+    sv = [v for k, v in data.items() if k.startswith("solve:")]
+    assert len(lu) == 1 and lu[0] == {"group": t0["lu_group"]}
+    assert len(sv) == 1 and sv[0] == {"spmm": t0["spmm_variant"], "trsm_paired": t0["trsm_paired"],
+                                      "trsm_cols": t0["trsm_cols"]}

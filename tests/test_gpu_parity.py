@@ -107,6 +107,28 @@ def test_preconditioner_application(case, prec, tol):
     assert err.max() <= tol, err
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
+def test_preconditioner_every_panel_group(case, prec, tol):
+    """The factorisation's panels per trailing-update pass (the autotuner's
+    choice) changes only the rounding: one ORAS application per group
+    against the oracle's."""
+    p = case.p
+    dec = schwarz.Decomposition(case.t, p.nsub, p.overlap)
+    M = schwarz.ORAS(dec, p.eps, p.eps_kind, p.freq, p.eps_b, dense=True)
+    X = workload.seeded_complex((case.t.ne, 8), 12)
+    ref = M.apply(X)
+    try:
+        for g in (1, 3, 4, 8, 16):
+            case.ctx.set_lu_group(g)
+            case.ctx.setup_schwarz(p.nsub, p.overlap, precision=prec)
+            Z = case.ctx.apply_preconditioner(X)
+            err = np.linalg.norm(Z - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            print("group", g, "err", err.max(), flush=True)
+            assert err.max() <= tol, (g, err)
+    finally:
+        case.ctx.set_lu_group(0)
+
+
 @pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-5)])
 def test_fields_match_direct_solve(case, prec, tol):
     p = case.p
