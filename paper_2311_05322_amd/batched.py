@@ -14,7 +14,7 @@ phantom are built before its solve and timed apart (they do not depend on the
 permittivity). The phantoms are staged: one context holds one phantom's
 factors and Krylov space at a time (the largest needs about 0.24 TB).
 
-python -m paper_2311_05322_amd.batched [--phantoms 8] [--rings 5] [--out profiles/batched_c3.md]
+python -m paper_2311_05322_amd.batched [--phantoms 8] [--rings 5] [--tune-cache FILE] [--out profiles/batched_c3.md]
 Prints one JSON line per phantom and a summary line.
 """
 from __future__ import annotations
@@ -58,7 +58,12 @@ def main():
                     help="restart length in block steps (10 keeps the 160-column Krylov space of the largest "
                          "phantom near 0.08 TB)")
     ap.add_argument("--out", default=None, help="markdown summary file")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuning cache file (MX_TUNE_CACHE): picks found there are not timed again")
     a = ap.parse_args()
+    if a.tune_cache:
+        os.environ["MX_TUNE_CACHE"] = a.tune_cache
+    warm = bool(a.tune_cache) and os.path.exists(a.tune_cache)
     specs = workload.batched_specs(a.phantoms, a.seed)
     ctx = mx.Context(0)
     ctx.set_krylov(True)
@@ -96,10 +101,14 @@ def main():
     if a.out:
         lines = ["# Batched form: 8 phantoms x 160 transmitters, staged through one MI355X", "",
                  "Command (repository root on the MI355X box):", "", "```",
-                 "python3 -u -m paper_2311_05322_amd.batched --out profiles/batched_c3.md", "```", "",
+                 "python3 -u -m paper_2311_05322_amd.batched " + " ".join(sys.argv[1:]), "```", "",
                  "Per phantom: own seeded mesh and tear, 5 shifted rings x 32 z-dipoles, complex64 banded LU, "
                  "block FGMRES (groups of 32 in lockstep), rtol 1e-8 (true residual). `solve` = operator values + "
-                 "local matrices + LU + iterations; topology and partition are built before it and timed apart.",
+                 "local matrices + LU + iterations; topology and partition are built before it and timed apart. "
+                 + ("Tuning cache: " + ("warm (picks read from the file, nothing timed)" if warm else
+                                         "cold (the autotuner times each new shape bucket inside that phantom's solve)")
+                    if a.tune_cache else
+                    "No tuning cache: the autotuner times each new shape bucket inside that phantom's solve."),
                  "",
                  "| phantom | c (mm) | edges | subdomains | n_i | block steps | max relres | topology+partition s | "
                  "solve s | of which LU s | iterations s |",

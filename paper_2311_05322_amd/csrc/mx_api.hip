@@ -4,6 +4,7 @@
 #include <chrono>
 #include <complex>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <random>
 #include <cmath>
@@ -366,6 +367,10 @@ struct mx_ctx {
   int tune_lu_group = kLuGroupDefault;
   double tune_lu_ms[4] = {0, 0, 0, 0};
   bool tune_from_cache = false, tune_lu_from_cache = false;
+  // every key this context has tuned, so that alternating shapes (phantoms
+  // of a batch) are not timed again
+  std::map<uint64_t, int> lu_tuned;
+  std::map<uint64_t, std::vector<int>> solve_tuned;
   bool graphs_on = true;
   uint64_t g_sig = 0;         // signature of the buffers, sizes and tolerance captured
   std::vector<hipGraphExec_t> gexec;
@@ -756,6 +761,14 @@ int autotune(mx_ctx* c, int nrhs) {
   mixv(c->precision);
   mixv(nrhs);
   if (key == c->tune_key) return MX_OK;
+  const auto seen = c->solve_tuned.find(key);
+  if (c->factored && seen != c->solve_tuned.end() && !(seen->second[0] == 2 && !c->win_ok)) {
+    c->tune_spmm = seen->second[0];
+    c->tune_trsm_paired = seen->second[1];
+    c->tune_trsm_cols = seen->second[2];
+    c->tune_key = key;
+    return MX_OK;
+  }
   char hex[32];
   std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)key);
   const std::string ckey = std::string("solve:") + hex;
@@ -771,6 +784,7 @@ int autotune(mx_ctx* c, int nrhs) {
       for (double& t : c->tune_trsm_ms) t = 0;
       c->tune_from_cache = true;
       c->tune_key = key;
+      c->solve_tuned[key] = {c->tune_spmm, c->tune_trsm_paired, c->tune_trsm_cols};
       return MX_OK;
     }
   }
@@ -808,6 +822,7 @@ int autotune(mx_ctx* c, int nrhs) {
   if (rc == MX_OK) {
     c->tune_key = key;
     c->tune_from_cache = false;
+    if (c->factored) c->solve_tuned[key] = {c->tune_spmm, c->tune_trsm_paired, c->tune_trsm_cols};
     if (c->factored)
       tune_cache_put(ckey, {{"spmm", c->tune_spmm}, {"trsm_paired", c->tune_trsm_paired},
                             {"trsm_cols", c->tune_trsm_cols}});
@@ -1985,6 +2000,8 @@ int mx_set_autotune(mx_ctx* c, int enable) {
     c->tune_trsm_cols = 32;
     c->tune_lu_key = 0;
     c->tune_lu_group = kLuGroupDefault;
+    c->lu_tuned.clear();
+    c->solve_tuned.clear();
   }
   return MX_OK;
 }
@@ -1993,6 +2010,7 @@ int mx_set_lu_group(mx_ctx* c, int32_t group) {
   if (!c) return set_err(MX_EINVAL, "NULL context");
   if (group < 0 || group > 16) return set_err(MX_EINVAL, "panel group: 1..16, or 0 for the autotuner");
   c->tune_lu_key = 0;
+  c->lu_tuned.clear();
   c->lu_autotune = group == 0;
   c->tune_lu_group = group == 0 ? kLuGroupDefault : group;
   return MX_OK;
@@ -2228,6 +2246,12 @@ int autotune_lu(mx_ctx* c, const std::vector<int32_t>& panel_rows, bool* tuned) 
   const int nmax = c->Nsorted.empty() ? 0 : c->Nsorted[0];
   const uint64_t key = ((uint64_t)(c->precision + 1) << 48) | ((uint64_t)c->dec.nsub << 16) | (uint64_t)(nmax >> 12);
   if (key == c->tune_lu_key) return MX_OK;
+  const auto seen = c->lu_tuned.find(key);
+  if (seen != c->lu_tuned.end()) {
+    c->tune_lu_group = seen->second;
+    c->tune_lu_key = key;
+    return MX_OK;
+  }
   const std::string ckey = "lu:" + std::to_string(c->precision) + ":" + std::to_string(c->dec.nsub) + ":" +
                            std::to_string(nmax >> 12);
   TuneFields tf;
@@ -2236,6 +2260,7 @@ int autotune_lu(mx_ctx* c, const std::vector<int32_t>& panel_rows, bool* tuned) 
     for (double& t : c->tune_lu_ms) t = 0;
     c->tune_lu_from_cache = true;
     c->tune_lu_key = key;
+    c->lu_tuned[key] = c->tune_lu_group;
     return MX_OK;
   }
   int best = 0;
@@ -2250,6 +2275,7 @@ int autotune_lu(mx_ctx* c, const std::vector<int32_t>& panel_rows, bool* tuned) 
   c->tune_lu_group = kLuGroups[best];
   c->tune_lu_from_cache = false;
   c->tune_lu_key = key;
+  c->lu_tuned[key] = c->tune_lu_group;
   tune_cache_put(ckey, {{"group", c->tune_lu_group}});
   return MX_OK;
 }
