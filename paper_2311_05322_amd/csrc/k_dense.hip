@@ -36,13 +36,15 @@ constexpr int NB = 64;
 constexpr int PT = 1024;     // panel workgroup size
 constexpr int MAXSW = 128;   // max distinct rows touched by one panel's swaps
 
-// register sub-panel width of k_lu_panel (1M chamber, panels per
-// factorisation: complex64 W = 4 -> 71.6 ms, 8 -> 63.4 ms, 16 -> 60.5 ms with
-// spills in the wider-row variants; complex128 W = 2 -> 121.5 ms, 4 -> 93.6
-// ms: fewer sub-panels, so fewer top-row solves and L re-reads)
-template <typename R> struct PanelW;
-template <> struct PanelW<float> { static constexpr int W = 8; };
-template <> struct PanelW<double> { static constexpr int W = 4; };
+// register sub-panel width of k_lu_panel by rows per thread (fewer, wider
+// sub-panels: fewer top-row solves and L re-reads). 1M chamber, panels per
+// factorisation: complex64 W = 4 -> 71.6 ms, 8 -> 63.4 ms, 16 -> 60.5 ms;
+// complex128 W = 2 -> 121.5 ms, 4 -> 93.6 ms, 8 -> 81.7 ms. The wider widths
+// fit the 128-register budget of a 1,024-thread workgroup only with one row
+// per thread (32 / 16 columns spill there; 16 / 8 spill with more rows).
+template <typename R, int RPT> struct PanelW;
+template <int RPT> struct PanelW<float, RPT> { static constexpr int W = RPT == 1 ? 16 : 8; };
+template <int RPT> struct PanelW<double, RPT> { static constexpr int W = RPT == 1 ? 8 : 4; };
 
 template <typename R> __device__ inline Acc_t<R> zacc() {
   Acc_t<R> z;
@@ -82,7 +84,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
                                                  int32_t* __restrict__ status, int32_t* __restrict__ pswap,
                                                  const int32_t* __restrict__ lim, int k0) {
   typedef C_t<R> C;
-  constexpr int W = PanelW<R>::W;
+  constexpr int W = PanelW<R, RPT>::W;
   const int s = order[blockIdx.x];
   const int N = Npad[s];
   if (k0 >= N) return;
@@ -104,7 +106,7 @@ __global__ void __launch_bounds__(PT) k_lu_panel(C_t<R>* __restrict__ pool, cons
   __shared__ int red_r[PT / 64];
   __shared__ int piv_row;
   __shared__ R piv_abs;
-  __shared__ int spv[PanelW<R>::W];
+  __shared__ int spv[PanelW<R, RPT>::W];
   __shared__ C Lt[NB][NB + 1];
   __shared__ C Xt[NB][NB + 1];
   __shared__ int sw_dst[MAXSW], sw_src[MAXSW];
