@@ -70,70 +70,96 @@ __global__ void k_coarse_P(int64_t nrows, const int32_t* __restrict__ row_sub, c
 
 // X[(j*nsub + i)][k] (+192 for Im) = sum_l w_l P[l][k] v[dofs[l]][j] / s_j for the
 // right-hand sides j0 .. j0+nj-1 (nj <= 32); w = D weights or 1.
-__global__ void __launch_bounds__(256) k_pool(int nsub, const int64_t* __restrict__ dof_ptr,
-                                              const int32_t* __restrict__ dofs, const float* __restrict__ P,
-                                              const double* __restrict__ wts, const double2* __restrict__ v,
-                                              int nrhs, int j0, int nj, const double* __restrict__ scale,
-                                              float* __restrict__ X, int64_t xrows_stride) {
-  // one workgroup per subdomain; thread (kg, j): right-hand side j, lattice
-  // coefficients k = kg + 8m (m < 24); the subdomain's rows are staged
-  // through LDS 32 at a time (P rows with the optional weight, v rows cast)
-  constexpr int RCH = 32;
-  __shared__ float Ps[RCH][NCO];
-  __shared__ float2 Vs[RCH][32];
-  const int i = blockIdx.x;
+// Two kernels: k_pool_part splits each subdomain's rows into PS slices, one
+// workgroup per (subdomain, slice), and writes the slice's sums; k_pool_sum
+// adds the slices in a fixed order and scales (so the result does not depend
+// on scheduling). k_pool_part forms the slice's (192 coefficients) x (64 =
+// 32 right-hand sides x [re, im]) product P^T V on the FP32 matrix cores,
+// 4 rows per step: wave w holds the coefficient tiles 3w .. 3w+2 against all
+// four column tiles; P rows (times the optional weight) and V rows (cast to
+// FP32, column n = 2 j + [re, im]) go straight into MFMA operands.
+constexpr int PS = 8;
+__global__ void __launch_bounds__(256) k_pool_part(int nsub, const int64_t* __restrict__ dof_ptr,
+                                                   const int32_t* __restrict__ dofs, const float* __restrict__ P,
+                                                   const double* __restrict__ wts, const double2* __restrict__ v,
+                                                   int nrhs, int j0, int nj, float* __restrict__ Xp) {
+  const int i = blockIdx.x, y = blockIdx.y;
   const int tid = threadIdx.x;
-  const int j = tid & 31, kg = tid >> 5;
-  float ar[24], ai[24];
+  const int lane = tid & 63, w = tid >> 6;
+  f32x4 acc[3][4];
 #pragma unroll
-  for (int m = 0; m < 24; ++m) { ar[m] = 0.f; ai[m] = 0.f; }
-  const int64_t r0 = dof_ptr[i], r1 = dof_ptr[i + 1];
-  for (int64_t rb = r0; rb < r1; rb += RCH) {
-    const int nr = (int)min((int64_t)RCH, r1 - rb);
-    __syncthreads();
-    for (int e = tid; e < RCH * NCO; e += 256) {
-      const int r = e / NCO, k = e % NCO;
-      float pw = 0.f;
-      if (r < nr) {
-        pw = P[(rb + r) * NCO + k];
-        if (wts) pw *= (float)wts[rb + r];
-      }
-      Ps[r][k] = pw;
-    }
-    for (int e = tid; e < RCH * 32; e += 256) {
-      const int r = e / 32, jj = e % 32;
-      float2 x = make_float2(0.f, 0.f);
-      if (r < nr && jj < nj) {
-        const double2 d = v[(int64_t)dofs[rb + r] * nrhs + j0 + jj];
-        x = make_float2((float)d.x, (float)d.y);
-      }
-      Vs[r][jj] = x;
-    }
-    __syncthreads();
-    for (int r = 0; r < nr; ++r) {
-      const float2 x = Vs[r][j];
+  for (int mt = 0; mt < 3; ++mt)
 #pragma unroll
-      for (int m = 0; m < 24; ++m) {
-        const float pw = Ps[r][kg + 8 * m];
-        ar[m] += pw * x.x;
-        ai[m] += pw * x.y;
-      }
-    }
+    for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t a0 = dof_ptr[i], a1 = dof_ptr[i + 1];
+  const int64_t len = (a1 - a0 + PS - 1) / PS;
+  const int64_t r0 = a0 + y * len, r1 = min(a1, r0 + len);
+  // B operand columns of this lane: n = 16 nt + lane % 16 -> j = n / 2, part n % 2
+  int jb[4];
+  bool bok[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int n = 16 * nt + (lane & 15);
+    jb[nt] = n >> 1;
+    bok[nt] = (n >> 1) < nj;
   }
-  if (j < nj) {
-    const double sj = scale[j0 + j];
-    const float inv = sj > 0 ? (float)(1.0 / sj) : 0.f;
-    float* xr = X + ((int64_t)(j0 + j) * nsub + i) * xrows_stride;
+  const int part = lane & 1;
+  for (int64_t kr = r0; kr < r1; kr += 4) {
+    // A[m][k] = P[row k][coef m], B[k][n] = w_row V[row k][n], k = lane / 16
+    const int64_t row = kr + (lane >> 4);
+    const bool ok = row < r1;
+    const int64_t rr = ok ? row : r0;
+    const float wr = ok ? (wts ? (float)wts[rr] : 1.f) : 0.f;
+    float a[3], b[4];
 #pragma unroll
-    for (int m = 0; m < 24; ++m) {
-      xr[kg + 8 * m] = ar[m] * inv;
-      xr[NCO + kg + 8 * m] = ai[m] * inv;
+    for (int mt = 0; mt < 3; ++mt) a[mt] = P[rr * NCO + 16 * (3 * w + mt) + (lane & 15)];
+    const double2* vr = v + (int64_t)dofs[rr] * nrhs + j0;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const double2 d = vr[bok[nt] ? jb[nt] : 0];
+      b[nt] = bok[nt] ? wr * (float)(part ? d.y : d.x) : 0.f;
     }
+#pragma unroll
+    for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
   }
+  // acc[mt][nt][r]: coefficient 16 (3w + mt) + 4 (lane / 16) + r, column 16 nt + lane % 16; every slice
+  // writes all 32 right-hand sides (those beyond nj hold zeros)
+  float* xp = Xp + (int64_t)y * 32 * nsub * NIN;
+#pragma unroll
+  for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int coef = 16 * (3 * w + mt) + acc_row<float>(lane, r);
+        xp[((int64_t)jb[nt] * nsub + i) * NIN + part * NCO + coef] = acc[mt][nt][r];
+      }
+}
+
+// X[(j0 + jj) * nsub + i][k] = (sum over slices y in order of Xp[y][jj * nsub + i][k]) / s_(j0+jj)
+__global__ void __launch_bounds__(256) k_pool_sum(int nsub, int j0, int nj, const double* __restrict__ scale,
+                                                  const float* __restrict__ Xp, float* __restrict__ X,
+                                                  int64_t xrows_stride) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nj * nsub * NIN) return;
+  const int64_t row = e / NIN;
+  const int k = (int)(e % NIN);
+  const int jj = (int)(row / nsub), i = (int)(row % nsub);
+  float sum = 0.f;
+  for (int y = 0; y < PS; ++y) sum += Xp[((int64_t)y * 32 * nsub + row) * NIN + k];
+  const double sj = scale[j0 + jj];
+  const float inv = sj > 0 ? (float)(1.0 / sj) : 0.f;
+  X[((int64_t)(j0 + jj) * nsub + i) * xrows_stride + k] = sum * inv;
 }
 
 // xloc[vec_off[i] + lpos[l]][j] += alpha * s_j * sum_k P[l][k] (c_re[k] + j c_im[k])
-// (lpos: dense row of the subdomain DOF row l)
+// (lpos: dense row of the subdomain DOF row l). On the FP32 matrix cores:
+// per 16-row block of the subdomain, (16 rows x 192) P times (192 x 64)
+// coefficients, column n = 2 j + [re, im]; the coefficients of the block of
+// right-hand sides (scaled by alpha s_j) are staged in LDS as [k][n]; each
+// wave takes every fourth 16-row block of its workgroup's share.
 template <typename C>
 __global__ void __launch_bounds__(256) k_coarse_apply(const int32_t* __restrict__ lpos,
                                                       const int64_t* __restrict__ dof_ptr,
@@ -141,41 +167,46 @@ __global__ void __launch_bounds__(256) k_coarse_apply(const int32_t* __restrict_
                                                       const float* __restrict__ Cn, int nsub, int nrhs, int j0, int nj,
                                                       const double* __restrict__ scale, float alpha,
                                                       C* __restrict__ xloc) {
-  // workgroup (subdomain i, row slice): the subdomain's coefficients for the
-  // block of right-hand sides staged in LDS as [k][j]; thread (row group,
-  // j) walks its rows with the P row broadcast over the j lanes
-  __shared__ float2 Cs[NCO][32];
+  typedef decltype(C().x) R;
+  __shared__ float Cs[NCO][64];
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
-  const int j = tid & 31, rg = tid >> 5;
-  for (int e = tid; e < NCO * 32; e += 256) {
-    const int k = e / 32, jj = e % 32;
-    float2 c = make_float2(0.f, 0.f);
-    if (jj < nj) {
-      const float* cr = Cn + ((int64_t)(j0 + jj) * nsub + i) * NIN;
-      c = make_float2(cr[k], cr[NCO + k]);
-    }
-    Cs[k][jj] = c;
+  const int lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < NCO * 64; e += 256) {
+    const int k = e >> 6, n = e & 63, jj = n >> 1;
+    float c = 0.f;
+    if (jj < nj) c = alpha * (float)scale[j0 + jj] * Cn[((int64_t)(j0 + jj) * nsub + i) * NIN + (n & 1) * NCO + k];
+    Cs[k][n] = c;
   }
   __syncthreads();
-  if (j >= nj) return;
-  const float f = alpha * (float)scale[j0 + j];
   const int64_t r0 = dof_ptr[i], r1 = dof_ptr[i + 1];
-  for (int64_t row = r0 + (int64_t)blockIdx.y * 8 + rg; row < r1; row += 8 * (int64_t)gridDim.y) {
-    const float4* pr = reinterpret_cast<const float4*>(P + row * NCO);
-    float re = 0.f, im = 0.f;
+  const int64_t step = 16 * 4 * (int64_t)gridDim.y;
+  for (int64_t rb = r0 + 16 * ((int64_t)blockIdx.y * 4 + w); rb < r1; rb += step) {
+    // A[m][k] = P[row rb + m][k] (rows past the end read the last row; not written)
+    const float* pr = P + min(rb + (lane & 15), r1 - 1) * NCO + (lane >> 4);
+    f32x4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
-    for (int k4 = 0; k4 < NCO / 4; ++k4) {
-      const float4 p = pr[k4];
-      const float2 c0 = Cs[4 * k4][j], c1 = Cs[4 * k4 + 1][j], c2 = Cs[4 * k4 + 2][j], c3 = Cs[4 * k4 + 3][j];
-      re += p.x * c0.x + p.y * c1.x + p.z * c2.x + p.w * c3.x;
-      im += p.x * c0.y + p.y * c1.y + p.z * c2.y + p.w * c3.y;
+    for (int s4 = 0; s4 < NCO / 4; ++s4) {
+      const float a = pr[4 * s4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma(a, Cs[4 * s4 + (lane >> 4)][16 * nt + (lane & 15)], acc[nt]);
     }
-    const int64_t o = (vec_off[i] + lpos[row]) * nrhs + j0 + j;
-    C x = xloc[o];
-    x.x += f * re;
-    x.y += f * im;
-    xloc[o] = x;
+    // acc[nt][r]: row rb + 4 (lane / 16) + r, column 16 nt + lane % 16 -> j, part
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int n = 16 * nt + (lane & 15), jj = n >> 1;
+      if (jj >= nj) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = rb + acc_row<float>(lane, r);
+        if (row < r1) {
+          R* x = reinterpret_cast<R*>(xloc + (vec_off[i] + lpos[row]) * nrhs + j0 + jj) + (n & 1);
+          *x += (R)acc[nt][r];
+        }
+      }
+    }
   }
 }
 
@@ -417,12 +448,16 @@ void launch_coarse_P(hipStream_t s, int64_t nrows, const int32_t* row_sub, const
     hipLaunchKernelGGL(k_coarse_P, dim3(nblk(nrows, 128)), dim3(128), 0, s, nrows, row_sub, dofs, edges, xyz, box, P);
 }
 
+int64_t pool_scratch_floats(int nsub) { return (int64_t)PS * 32 * nsub * NIN; }
+
 void launch_pool(hipStream_t s, int nsub, const int64_t* dof_ptr, const int32_t* dofs, const float* P,
-                 const double* wts, const double2* v, int nrhs, const double* scale, float* X) {
+                 const double* wts, const double2* v, int nrhs, const double* scale, float* X, float* part) {
   for (int j0 = 0; j0 < nrhs; j0 += 32) {
     int nj = nrhs - j0 < 32 ? nrhs - j0 : 32;
-    hipLaunchKernelGGL(k_pool, dim3(nsub), dim3(256), 0, s, nsub, dof_ptr, dofs, P, wts, v, nrhs, j0, nj, scale, X,
-                       (int64_t)NIN);
+    hipLaunchKernelGGL(k_pool_part, dim3(nsub, PS), dim3(256), 0, s, nsub, dof_ptr, dofs, P, wts, v, nrhs, j0, nj,
+                       part);
+    hipLaunchKernelGGL(k_pool_sum, dim3(nblk((int64_t)nj * nsub * NIN, 256)), dim3(256), 0, s, nsub, j0, nj, scale,
+                       part, X, (int64_t)NIN);
   }
 }
 

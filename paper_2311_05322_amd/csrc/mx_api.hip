@@ -315,7 +315,7 @@ struct mx_ctx {
   DBuf<double2> qv, aq, tv, thdot;
   DBuf<double> thnrm, thtn;
   DBuf<char> xloc2;
-  DBuf<float> cP, theta, gtheta, adam_m, adam_v, nbuf, gwork, dsX, dsY;
+  DBuf<float> cP, theta, gtheta, adam_m, adam_v, nbuf, gwork, dsX, dsY, cpart;
   DBuf<double> cbox, cG, cscale, cpdp, msepart;
   DBuf<int32_t> row_sub, edges_dev, cnbrs, bgraph, cflag;
   DBuf<int64_t> cnbr_ptr;
@@ -605,7 +605,7 @@ void coarse_correct(mx_ctx* c, const double2* v, C* xl, int nrhs) {
   // s_j = ||v_j|| / sqrt(ne)
   launch_norm(s, c->topo.ne, nrhs, v, c->normpart.p, c->cscale.p);
   launch_scale_rhs_norm(c, nrhs);
-  launch_pool(s, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, nullptr, v, nrhs, c->cscale.p, B.X);
+  launch_pool(s, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, nullptr, v, nrhs, c->cscale.p, B.X, c->cpart.p);
   launch_scale_f(s, (int64_t)nrhs * D.nsub * NIN, B.X, (float)(1.0 / c->sx));
   net_forward(c, nrhs, B);
   launch_nonfinite(s, (int64_t)nrhs * D.nsub * NIN, B.OUT, c->cflag.p);
@@ -1665,6 +1665,7 @@ int coarse_prepare(mx_ctx* c) {
   CK(c->cnbr_ptr.upload(D.nbr_ptr, c->stream));
   CK(c->cnbrs.upload(D.nbrs.empty() ? std::vector<int32_t>(1, 0) : D.nbrs, c->stream));
   CK(c->cP.alloc((size_t)nrows * NCO));
+  CK(c->cpart.alloc((size_t)pool_scratch_floats(nsub)));
   launch_coarse_P(c->stream, nrows, c->row_sub.p, c->dofs.p, c->edges_dev.p, c->xyz.p, c->cbox.p, c->cP.p);
   CK(c->cpdp.alloc((size_t)nsub * NCO * NCO));
   DBuf<double> Dw;
@@ -2869,7 +2870,7 @@ int mx_coarse_features(mx_ctx* c, const mx_c128* v, int32_t nrhs, float* X) {
   CK(c->normpart.alloc((size_t)dot_blocks(c->topo.ne) * nrhs));
   launch_norm(c->stream, c->topo.ne, nrhs, vin.p, c->normpart.p, c->cscale.p);
   launch_scale_rhs_norm(c, nrhs);
-  launch_pool(c->stream, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, nullptr, vin.p, nrhs, c->cscale.p, Xd.p);
+  launch_pool(c->stream, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, nullptr, vin.p, nrhs, c->cscale.p, Xd.p, c->cpart.p);
   MX_HIP_CHECK(hipGetLastError());
   MX_HIP_CHECK(hipMemcpyAsync(X, Xd.p, (size_t)nrhs * D.nsub * NIN * 4, hipMemcpyDeviceToHost, c->stream));
   return sync(c);
@@ -2998,12 +2999,12 @@ int mx_coarse_collect(mx_ctx* c, const mx_sources* tx, int32_t snap_every, int32
     float* Yo = c->dsY.p + c->ds_graphs * per_graph;
     launch_norm(s, c->topo.ne, ntx, c->r.p, c->normpart.p, c->cscale.p);
     launch_scale_rhs_norm(c, ntx);
-    launch_pool(s, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, nullptr, c->r.p, ntx, c->cscale.p, Xo);
+    launch_pool(s, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, nullptr, c->r.p, ntx, c->cscale.p, Xo, c->cpart.p);
     double2* mr = c->Z.p;
     double2* t = c->V.p + blk;
     CK(apply_precond(c, c->r.p, mr, ntx));
     hipLaunchKernelGGL(k_axpy_err, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, blk, xs.p, c->x.p, mr, t);
-    launch_pool(s, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, Dw.p, t, ntx, c->cscale.p, B.X);
+    launch_pool(s, D.nsub, c->dof_ptr.p, c->dofs.p, c->cP.p, Dw.p, t, ntx, c->cscale.p, B.X, c->cpart.p);
     launch_gapply(s, D.nsub, ntx, c->cG.p, B.X, Yo);
     MX_HIP_CHECK(hipGetLastError());
     c->ds_graphs += ntx;

@@ -58,7 +58,9 @@ void launch_grad_vertex(hipStream_t s, int32_t nv, const int64_t* v2t_ptr, const
 void launch_coarse_P(hipStream_t s, int64_t nrows, const int32_t* row_sub, const int32_t* dofs, const int32_t* edges,
                      const double* xyz, const double* box, float* P);
 void launch_pool(hipStream_t s, int nsub, const int64_t* dof_ptr, const int32_t* dofs, const float* P,
-                 const double* wts, const double2* v, int nrhs, const double* scale, float* X);
+                 const double* wts, const double2* v, int nrhs, const double* scale, float* X, float* part);
+// floats of the partial-sum scratch launch_pool needs (part)
+int64_t pool_scratch_floats(int nsub);
 template <typename C>
 void launch_coarse_apply(hipStream_t s, int64_t nrows, const int32_t* lpos, const int64_t* dof_ptr,
                          const int64_t* vec_off, const float* P, const float* Cn, int nsub, int nrhs,
