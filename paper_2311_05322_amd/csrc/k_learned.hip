@@ -182,16 +182,30 @@ __global__ void __launch_bounds__(256) k_coarse_apply(const int32_t* __restrict_
   const int64_t r0 = dof_ptr[i], r1 = dof_ptr[i + 1];
   const int64_t step = 16 * 4 * (int64_t)gridDim.y;
   for (int64_t rb = r0 + 16 * ((int64_t)blockIdx.y * 4 + w); rb < r1; rb += step) {
-    // A[m][k] = P[row rb + m][k] (rows past the end read the last row; not written)
-    const float* pr = P + min(rb + (lane & 15), r1 - 1) * NCO + (lane >> 4);
+    // A[m][k] = P[row rb + m][k] (rows past the end read the last row; not
+    // written). K is taken in blocks of 64 with lane group g = lane / 16
+    // holding k = 64 kb + 16 g + t at step t, so that a lane reads its 16
+    // coefficients of the block as four 16-byte loads.
+    const float4* pr = reinterpret_cast<const float4*>(P + min(rb + (lane & 15), r1 - 1) * NCO) + 4 * (lane >> 4);
     f32x4 acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-    for (int s4 = 0; s4 < NCO / 4; ++s4) {
-      const float a = pr[4 * s4];
+#pragma unroll 1
+    for (int kb = 0; kb < NCO / 64; ++kb) {
+      float a[16];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma(a, Cs[4 * s4 + (lane >> 4)][16 * nt + (lane & 15)], acc[nt]);
+      for (int q = 0; q < 4; ++q) {
+        const float4 t4 = pr[16 * kb + q];
+        a[4 * q] = t4.x;
+        a[4 * q + 1] = t4.y;
+        a[4 * q + 2] = t4.z;
+        a[4 * q + 3] = t4.w;
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+          acc[nt] = mfma(a[t], Cs[64 * kb + 16 * (lane >> 4) + t][16 * nt + (lane & 15)], acc[nt]);
     }
     // acc[nt][r]: row rb + 4 (lane / 16) + r, column 16 nt + lane % 16 -> j, part
 #pragma unroll
