@@ -150,7 +150,8 @@ __global__ void __launch_bounds__(BT) k_bdot_narrow(int64_t nrows, int64_t rows_
   }
 }
 
-// Wout = beta Win + alpha A H on the FP64 matrix cores: a workgroup takes 128
+// Wout = beta Win + alpha A H (also written to Wout2 when given) on the FP64
+// matrix cores: a workgroup takes 128
 // rows (wave w: rows 32w..32w+31 as two 16-row MFMA tiles) and all 32
 // columns; H is staged through LDS 64 rows at a time (32 KB, so that LDS
 // admits four workgroups per CU, the register cap's occupancy: four waves per
@@ -159,7 +160,8 @@ __global__ void __launch_bounds__(BT) k_bdot_narrow(int64_t nrows, int64_t rows_
 __global__ void __launch_bounds__(BT, 4) k_bupd_mfma(int64_t nrows, int ka, int s, const double2* __restrict__ A,
                                                   int64_t lda, const double2* __restrict__ H,
                                                   const double2* Win, int64_t ldwin, double2* Wout,
-                                                  int64_t ldwout, double alpha, double beta) {
+                                                  int64_t ldwout, double alpha, double beta, double2* Wout2,
+                                                  int64_t ldwout2) {
   __shared__ double2 Hs[UA][32];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
@@ -222,6 +224,7 @@ __global__ void __launch_bounds__(BT, 4) k_bupd_mfma(int64_t nrows, int ka, int 
           im = fma(beta, v.y, im);
         }
         Wout[r * ldwout + b] = make_double2(re, im);
+        if (Wout2) Wout2[r * ldwout2 + b] = make_double2(re, im);
       }
 }
 
@@ -288,10 +291,11 @@ void launch_bdot(hipStream_t st, int64_t nrows, int ka, int s, const double2* A,
 }
 
 void launch_bupd(hipStream_t st, int64_t nrows, int ka, int s, const double2* A, int64_t lda, const double2* H,
-                 const double2* Win, int64_t ldwin, double2* Wout, int64_t ldwout, double alpha, double beta) {
+                 const double2* Win, int64_t ldwin, double2* Wout, int64_t ldwout, double alpha, double beta,
+                 double2* Wout2, int64_t ldwout2) {
   if (nrows <= 0 || s <= 0) return;
   hipLaunchKernelGGL(k_bupd_mfma, dim3((unsigned)((nrows + UR - 1) / UR)), dim3(BT), 0, st, nrows, ka, s, A, lda, H,
-                     Win, ldwin, Wout, ldwout, alpha, beta);
+                     Win, ldwin, Wout, ldwout, alpha, beta, Wout2, ldwout2);
 }
 
 void launch_bcopy(hipStream_t st, int64_t nrows, int s, const double2* src, int64_t lds, double2* dst, int64_t ldd) {

@@ -930,9 +930,10 @@ int ensure_block_host(mx_ctx* c, size_t n) {
 // second time unless the scaled block is well conditioned: Q written to out,
 // tmp scratch, R (upper, row-major) on the host. ok = false when the block
 // has numerical rank below s (out is then not written).
-// G1 (host, optional): W^H W when the caller already has it.
+// G1 (host, optional): W^H W when the caller already has it. out2, ld2
+// (optional): a second destination of Q (the block's place in the basis).
 int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, int64_t ld, std::vector<cd>& R,
-            bool& ok, const double2* G1 = nullptr) {
+            bool& ok, const double2* G1 = nullptr, double2* out2 = nullptr, int64_t ld2 = 0) {
   const int64_t ne = c->topo.ne;
   hipStream_t st = c->stream;
   const size_t ss = (size_t)s * s;
@@ -955,7 +956,7 @@ int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, int6
   if (pmin >= 1e-4) {
     // the scaled block has condition number below ~100: one pass leaves Q
     // orthonormal to ~1e-12, the second is skipped
-    launch_bupd(st, ne, s, s, W, ld, c->bT.p, nullptr, 0, out, ld, 1.0, 0.0);
+    launch_bupd(st, ne, s, s, W, ld, c->bT.p, nullptr, 0, out, ld, 1.0, 0.0, out2, ld2);
     MX_HIP_CHECK(hipGetLastError());
     R = R1;
     return MX_OK;
@@ -969,7 +970,7 @@ int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, int6
   if (!ok) return MX_OK;
   upper_inverse(R2, s, hT);
   MX_HIP_CHECK(hipMemcpyAsync(c->bT.p, hT, ss * sizeof(double2), hipMemcpyHostToDevice, st));
-  launch_bupd(st, ne, s, s, tmp, ld, c->bT.p, nullptr, 0, out, ld, 1.0, 0.0);
+  launch_bupd(st, ne, s, s, tmp, ld, c->bT.p, nullptr, 0, out, ld, 1.0, 0.0, out2, ld2);
   MX_HIP_CHECK(hipGetLastError());
   R.assign(ss, 0.0);  // R = R2 R1
   for (int i = 0; i < s; ++i)
@@ -1174,13 +1175,13 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x
       kk[g] = 0;
       if (!active[g]) continue;
       bool ok = false;
-      CK(cholqr2(c, gs[g], c->r.p + g0[g], c->bw1.p + g0[g], c->bw2.p + g0[g], S, Rk, ok));
+      CK(cholqr2(c, gs[g], c->r.p + g0[g], c->bw1.p + g0[g], c->bw2.p + g0[g], S, Rk, ok, nullptr, Vg(g),
+                 (int64_t)(m + 1) * gs[g]));
       if (!ok) {
         c->prof.end(K_CGS);
         if (total > 0) return set_err(MX_ENOTCONV, "block FGMRES: a residual block lost rank");
         return kBlockFallback;
       }
-      launch_bcopy(st, ne, gs[g], c->bw2.p + g0[g], S, Vg(g), (int64_t)(m + 1) * gs[g]);
       ls[g].reset(gs[g], m, Rk);
       running[g] = 1;
     }
@@ -1211,7 +1212,8 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x
           launch_bdot(st, ne, ka, s, Vg(g), LV, W, S, c->bpart.p, c->bH.p);
           MX_HIP_CHECK(hipMemcpyAsync(hh2, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
           launch_bupd(st, ne, ka, s, Vg(g), LV, c->bH.p, W, S, W, S, -1.0, 1.0);
-          CK(cholqr2(c, s, W, c->bw1.p + g0[g], c->bw2.p + g0[g], S, Rk, ok));
+          CK(cholqr2(c, s, W, c->bw1.p + g0[g], c->bw2.p + g0[g], S, Rk, ok, nullptr, Vg(g) + (int64_t)(k + 1) * s,
+                     LV));
         } else {
           // one projection pass, repeated only when W lay almost entirely in
           // the basis (its column norms fell by more than 1e4 in the pass, so
@@ -1240,13 +1242,13 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x
             MX_HIP_CHECK(hipMemcpyAsync(hh2, c->bH.p, (size_t)ka * s * sizeof(double2), hipMemcpyDeviceToHost, st));
             launch_bupd(st, ne, ka, s, Vg(g), LV, c->bH.p, W, S, W, S, -1.0, 1.0);
           }
-          CK(cholqr2(c, s, W, c->bw1.p + g0[g], c->bw2.p + g0[g], S, Rk, ok, reorth ? nullptr : hG1));
+          CK(cholqr2(c, s, W, c->bw1.p + g0[g], c->bw2.p + g0[g], S, Rk, ok, reorth ? nullptr : hG1,
+                     Vg(g) + (int64_t)(k + 1) * s, LV));
         }
         if (!ok) {  // W lost rank: this step of the group is not used, the group restarts
           running[g] = 0;
           continue;
         }
-        launch_bcopy(st, ne, s, c->bw2.p + g0[g], S, Vg(g) + (int64_t)(k + 1) * s, LV);
         P.assign((size_t)(k + 2) * ss, 0.0);
         if (two_pass || reorth)
           for (size_t e = 0; e < (size_t)ka * s; ++e) P[e] = cd(hh1[e].x + hh2[e].x, hh1[e].y + hh2[e].y);

@@ -180,8 +180,10 @@ void launch_receivers(hipStream_t s, int nrx, int nrhs, const int64_t* ptr, cons
 int64_t block_partial_max(int ka_max, int s);
 void launch_bdot(hipStream_t st, int64_t nrows, int ka, int s, const double2* A, int64_t lda, const double2* B,
                  int64_t ldb, double2* P, double2* out);
+// (Wout2, ldwout2: an optional second destination of the same result)
 void launch_bupd(hipStream_t st, int64_t nrows, int ka, int s, const double2* A, int64_t lda, const double2* H,
-                 const double2* Win, int64_t ldwin, double2* Wout, int64_t ldwout, double alpha, double beta);
+                 const double2* Win, int64_t ldwin, double2* Wout, int64_t ldwout, double alpha, double beta,
+                 double2* Wout2 = nullptr, int64_t ldwout2 = 0);
 void launch_bcopy(hipStream_t st, int64_t nrows, int s, const double2* src, int64_t lds, double2* dst, int64_t ldd);
 
 }  // namespace mx
