@@ -518,7 +518,8 @@ __global__ void k_restrict(int64_t nrows, const int32_t* __restrict__ rowsrc, co
 template <typename C>
 __global__ void __launch_bounds__(256) k_prolong(int64_t ne, const int64_t* __restrict__ ptr,
                                                  const int64_t* __restrict__ row, const double* __restrict__ w,
-                                                 const C* __restrict__ zloc, double2* __restrict__ z, int nrhs) {
+                                                 const C* __restrict__ zloc, double2* __restrict__ z, int nrhs,
+                                                 double2* __restrict__ z2, int64_t ld2) {
   const int64_t per = gridDim.x / 8;
   const int64_t blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
   const int64_t e = blk * 8 + threadIdx.x / 32;
@@ -534,6 +535,7 @@ __global__ void __launch_bounds__(256) k_prolong(int64_t ne, const int64_t* __re
       acc.y += wk * v.y;
     }
     z[e * nrhs + j] = acc;
+    if (z2) z2[e * ld2 + j] = acc;
   }
 }
 
@@ -723,13 +725,13 @@ template void launch_restrict<double2>(hipStream_t, int64_t, const int32_t*, con
 
 template <typename C>
 void launch_prolong(hipStream_t s, int64_t ne, const int64_t* ptr, const int64_t* row, const double* w,
-                    const C* zloc, double2* z, int nrhs) {
+                    const C* zloc, double2* z, int nrhs, double2* z2, int64_t ld2) {
   if (ne > 0)
-    hipLaunchKernelGGL(k_prolong<C>, dim3(nblk8(ne, 8)), dim3(256), 0, s, ne, ptr, row, w, zloc, z, nrhs);
+    hipLaunchKernelGGL(k_prolong<C>, dim3(nblk8(ne, 8)), dim3(256), 0, s, ne, ptr, row, w, zloc, z, nrhs, z2, ld2);
 }
 template void launch_prolong<float2>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*,
-                                     const float2*, double2*, int);
+                                     const float2*, double2*, int, double2*, int64_t);
 template void launch_prolong<double2>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*,
-                                      const double2*, double2*, int);
+                                      const double2*, double2*, int, double2*, int64_t);
 
 }  // namespace mx

@@ -617,9 +617,11 @@ void coarse_correct(mx_ctx* c, const double2* v, C* xl, int nrhs) {
 // given, returned separately in q (z then holds plain ORAS)
 // local: the restricted-vector buffer ([sum N_i][nrhs] in the factor
 // precision); NULL uses the context's own, any other buffer runs the same
-// kernels without the profiler (no event is created or recorded)
+// kernels without the profiler (no event is created or recorded); z2, ld2:
+// an optional second destination of z (row stride ld2)
 template <typename R>
-void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr, void* local = nullptr) {
+void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr, void* local = nullptr,
+                     double2* z2 = nullptr, int64_t ld2 = 0) {
   typedef C_t<R> C;
   const Decomposition& D = c->dec;
   const int64_t nrows = D.vec_off[D.nsub];
@@ -646,16 +648,17 @@ void apply_precond_t(mx_ctx* c, const double2* v, double2* z, int nrhs, double2*
     c->prof.end(K_COARSE);
   }
   if (tm) tm->begin(K_PROLONG);
-  launch_prolong<C>(c->stream, c->topo.ne, c->pg_ptr.p, c->pg_row.p, c->pg_w.p, xl, z, nrhs);
+  launch_prolong<C>(c->stream, c->topo.ne, c->pg_ptr.p, c->pg_row.p, c->pg_w.p, xl, z, nrhs, z2, ld2);
   if (xq) launch_prolong<C>(c->stream, c->topo.ne, c->pg_ptr.p, c->pg_row.p, c->pg_w.p, xq, q, nrhs);
   if (tm) tm->end(K_PROLONG);
 }
 
-int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr, void* local = nullptr) {
+int apply_precond(mx_ctx* c, const double2* v, double2* z, int nrhs, double2* q = nullptr, void* local = nullptr,
+                  double2* z2 = nullptr, int64_t ld2 = 0) {
   if (c->precision == MX_PREC_C64)
-    apply_precond_t<float>(c, v, z, nrhs, q, local);
+    apply_precond_t<float>(c, v, z, nrhs, q, local, z2, ld2);
   else
-    apply_precond_t<double>(c, v, z, nrhs, q, local);
+    apply_precond_t<double>(c, v, z, nrhs, q, local, z2, ld2);
   MX_HIP_CHECK(hipGetLastError());
   return MX_OK;
 }
@@ -1191,10 +1194,14 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x
       for (int g = 0; g < G; ++g) any = any || running[g];
       if (!any) break;
       // bw2: V_k of every group; bw1: Z_k; r: W (whole width)
-      CK(apply_precond(c, c->bw2.p, c->bw1.p, S));
-      for (int g = 0; g < G; ++g)
-        if (running[g])
-          launch_bcopy(st, ne, gs[g], c->bw1.p + g0[g], S, Zg(g) + (int64_t)k * gs[g], (int64_t)m * gs[g]);
+      if (G == 1) {  // one group: the preconditioner writes Z_k into the basis as well
+        CK(apply_precond(c, c->bw2.p, c->bw1.p, S, nullptr, nullptr, Zg(0) + (int64_t)k * gs[0], (int64_t)m * gs[0]));
+      } else {
+        CK(apply_precond(c, c->bw2.p, c->bw1.p, S));
+        for (int g = 0; g < G; ++g)
+          if (running[g])
+            launch_bcopy(st, ne, gs[g], c->bw1.p + g0[g], S, Zg(g) + (int64_t)k * gs[g], (int64_t)m * gs[g]);
+      }
       CK(spmm(c, c->bw1.p, c->r.p, S));
       c->prof.begin(K_CGS);
       for (int g = 0; g < G; ++g) {

@@ -107,7 +107,8 @@ void launch_restrict(hipStream_t s, int64_t nrows, const int32_t* rowsrc, const 
 // z[e] = sum over the entries of edge e (ptr [ne+1]) of w * zloc[row]
 template <typename C>
 void launch_prolong(hipStream_t s, int64_t ne, const int64_t* ptr, const int64_t* row, const double* w,
-                    const C* zloc, double2* z, int nrhs);
+                    const C* zloc, double2* z, int nrhs,
+                    double2* z2 = nullptr, int64_t ld2 = 0);
 
 // dense subdomain factorisation and solves
 // Band bookkeeping of the factorisation (device arrays, np = N_max / 64 per
