@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libmx.so")
 ARCH = os.environ.get("MX_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["k_operator.hip", "k_dense.hip", "k_krylov.hip", "k_learned.hip", "k_block.hip", "mx_api.hip"]
-CPP_SOURCES = ["host_mesh.cpp", "tune_cache.cpp"]
+CPP_SOURCES = ["host_mesh.cpp", "tune_cache.cpp", "block_lsq.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -265,6 +265,33 @@ __global__ void k_fill_zero(int64_t n, C* __restrict__ out) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += stride) out[k] = zero_value<C>();
 }
 
+// Zeroes the entries of the dense subdomain matrices that a completed banded
+// factorisation can have left non-zero, 64x64 tiles of the factor layout:
+// for each panel p, row tiles p .. ext_l[p] of its column block (the diagonal
+// block and L) and column tiles p+1 .. ext_u[p] of its row block (U). The
+// extents are those the factorisation recorded by scanning its own data, and
+// nothing outside them is non-zero afterwards, so this returns the storage to
+// all zeros while writing only the band. One workgroup per (panel, subdomain).
+template <typename C>
+__global__ void __launch_bounds__(256) k_clear_envelope(const int32_t* __restrict__ Npad,
+                                                        const int64_t* __restrict__ mat_off, int np,
+                                                        const int32_t* __restrict__ ext_l,
+                                                        const int32_t* __restrict__ ext_u, C* __restrict__ A) {
+  constexpr int T = 64;
+  const int s = blockIdx.y, p = blockIdx.x;
+  const int N = Npad[s];
+  const int nt = N / T;
+  if (p >= nt) return;
+  C* M = A + mat_off[s];
+  const int el = min(max(ext_l[(int64_t)s * np + p], p), nt - 1);
+  const int eu = min(max(ext_u[(int64_t)s * np + p], p), nt - 1);
+  const C z = zero_value<C>();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r = T * p + w; r < T * (el + 1); r += 4) M[(int64_t)r * N + T * p + lane] = z;
+  for (int r = T * p + w; r < T * (p + 1); r += 4)
+    for (int col = T * (p + 1) + lane; col < T * (eu + 1); col += 64) M[(int64_t)r * N + col] = z;
+}
+
 // identity on the padded diagonal part of each dense subdomain matrix
 template <typename C>
 __global__ void k_pad_identity(int32_t nsub, const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ Npad,
@@ -685,6 +712,16 @@ void launch_fill_zero(hipStream_t s, int64_t n, C* out) {
 template void launch_fill_zero<float2>(hipStream_t, int64_t, float2*);
 template void launch_fill_zero<double2>(hipStream_t, int64_t, double2*);
 template void launch_fill_zero<float>(hipStream_t, int64_t, float*);
+template <typename C>
+void launch_clear_envelope(hipStream_t s, int32_t nsub, int np, const int32_t* Npad, const int64_t* mat_off,
+                           const int32_t* ext_l, const int32_t* ext_u, C* A) {
+  if (nsub > 0 && np > 0)
+    hipLaunchKernelGGL(k_clear_envelope<C>, dim3(np, nsub), dim3(256), 0, s, Npad, mat_off, np, ext_l, ext_u, A);
+}
+template void launch_clear_envelope<float2>(hipStream_t, int32_t, int, const int32_t*, const int64_t*,
+                                            const int32_t*, const int32_t*, float2*);
+template void launch_clear_envelope<double2>(hipStream_t, int32_t, int, const int32_t*, const int64_t*,
+                                             const int32_t*, const int32_t*, double2*);
 template <typename C>
 void launch_pad_identity(hipStream_t s, int32_t nsub, const int64_t* dof_ptr, const int32_t* Npad,
                          const int64_t* mat_off, C* A) {

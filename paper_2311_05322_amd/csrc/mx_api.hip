@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "mx.h"
+#include "block_lsq.h"
 #include "host_mesh.h"
 #include "mx_device.h"
 #include "mx_kernels.h"
@@ -345,6 +346,7 @@ struct mx_ctx {
   DBuf<double2> face_k, pt_val, pr_val;
   DBuf<int32_t> pr_edge;
   bool pec_local_ready = false;            // pl_ptr / pl_idx match the decomposition
+  bool pool_envelope = false;  // factor pool zero outside the tiles ext_l / ext_u of its last factorisation
   // block FGMRES (mx_set_krylov): device blocks and pinned host staging
   int krylov_mode = MX_KRYLOV_PSEUDO_BLOCK;
   int64_t block_reorth = 0;                // one-pass block steps that took a second pass
@@ -985,112 +987,6 @@ int cholqr2(mx_ctx* c, int s, const double2* W, double2* tmp, double2* out, int6
   return MX_OK;
 }
 
-// Least squares of block FGMRES: the block Hessenberg matrix reduced to upper
-// triangular form by complex Givens rotations as its block columns arrive,
-// the same rotations applied to the right-hand side block [S0; 0].
-struct BlockLsq {
-  int s = 0, m = 0;
-  int64_t nrow = 0, ncol = 0;
-  std::vector<cd> Hr;     // rotated block Hessenberg, row-major [(m+1)s][ms]
-  std::vector<cd> G;      // rotated right-hand sides, row-major [(m+1)s][s]
-  std::vector<int32_t> ri, rj;
-  std::vector<double> rc;
-  std::vector<cd> rsn;
-  int kdone = 0;
-  void reset(int s_, int m_, const std::vector<cd>& S0) {
-    s = s_;
-    m = m_;
-    nrow = (int64_t)(m + 1) * s;
-    ncol = (int64_t)m * s;
-    Hr.assign((size_t)(nrow * ncol), 0.0);
-    G.assign((size_t)(nrow * s), 0.0);
-    for (size_t e = 0; e < (size_t)s * s; ++e) G[e] = S0[e];
-    ri.clear(); rj.clear(); rc.clear(); rsn.clear();
-    kdone = 0;
-  }
-  // [a; b] <- [c, sn; -conj(sn), c] [a; b], in real arithmetic (no library
-  // complex multiplication in the O(k s^3) loops)
-  static void rot(cd& a, cd& b, double c, cd sn) {
-    const double ar = a.real(), ai = a.imag(), br = b.real(), bi = b.imag();
-    const double sr = sn.real(), si = sn.imag();
-    a = cd(c * ar + sr * br - si * bi, c * ai + sr * bi + si * br);
-    b = cd(c * br - sr * ar - si * ai, c * bi - sr * ai + si * ar);
-  }
-  // block column k: P row-major [(k+2)s][s], rows (k+1)s.. hold R_{k+1} (upper)
-  void add(int k, std::vector<cd>& P) {
-    const int64_t rows = (int64_t)(k + 2) * s;
-    // rotations of the previous block columns, on all s columns at once
-    const size_t nold = ri.size();
-    for (size_t t = 0; t < nold; ++t) {
-      cd* a = &P[(size_t)ri[t] * s];
-      cd* b = &P[(size_t)rj[t] * s];
-      const double c = rc[t];
-      const cd sn = rsn[t];
-      for (int q = 0; q < s; ++q) rot(a[q], b[q], c, sn);
-    }
-    // triangularise this block column
-    for (int jj = 0; jj < s; ++jj) {
-      const int64_t cc = (int64_t)k * s + jj;
-      for (int64_t r = cc + 1; r <= (int64_t)(k + 1) * s + jj; ++r) {
-        cd& a = P[(size_t)cc * s + jj];
-        cd& b = P[(size_t)r * s + jj];
-        double c;
-        cd sn;
-        if (b == 0.0) {
-          c = 1.0;
-          sn = 0.0;
-        } else if (a == 0.0) {
-          c = 0.0;
-          sn = std::conj(b) / std::abs(b);
-        } else {
-          const double den = std::hypot(std::abs(a), std::abs(b));
-          c = std::abs(a) / den;
-          sn = (a / std::abs(a)) * std::conj(b) / den;
-        }
-        for (int q = jj; q < s; ++q) rot(P[(size_t)cc * s + q], P[(size_t)r * s + q], c, sn);
-        P[(size_t)r * s + jj] = 0.0;
-        for (int q = 0; q < s; ++q) rot(G[(size_t)cc * s + q], G[(size_t)r * s + q], c, sn);
-        ri.push_back((int32_t)cc);
-        rj.push_back((int32_t)r);
-        rc.push_back(c);
-        rsn.push_back(sn);
-      }
-    }
-    for (int64_t i = 0; i < rows; ++i)
-      for (int q = 0; q < s; ++q) Hr[(size_t)(i * ncol + (int64_t)k * s + q)] = P[(size_t)i * s + q];
-    kdone = k + 1;
-  }
-  // residual norm of right-hand side b after the last block column
-  double colres(int b) const {
-    double t = 0;
-    for (int64_t i = (int64_t)kdone * s; i < (int64_t)(kdone + 1) * s; ++i) t += std::norm(G[(size_t)i * s + b]);
-    return std::sqrt(t);
-  }
-  // Y [(kdone s) x s] by back substitution
-  void solve(double2* Y) const {
-    const int64_t n = (int64_t)kdone * s;
-    std::vector<cd> y((size_t)(n * s), 0.0);
-    std::vector<double> vr(s), vi(s);
-    for (int64_t i = n - 1; i >= 0; --i) {
-      const cd d = Hr[(size_t)(i * ncol + i)];
-      for (int q = 0; q < s; ++q) {
-        vr[q] = G[(size_t)i * s + q].real();
-        vi[q] = G[(size_t)i * s + q].imag();
-      }
-      for (int64_t j = i + 1; j < n; ++j) {
-        const double hr = Hr[(size_t)(i * ncol + j)].real(), hi = Hr[(size_t)(i * ncol + j)].imag();
-        const cd* yj = &y[(size_t)j * s];
-        for (int q = 0; q < s; ++q) {
-          vr[q] -= hr * yj[q].real() - hi * yj[q].imag();
-          vi[q] -= hr * yj[q].imag() + hi * yj[q].real();
-        }
-      }
-      for (int q = 0; q < s; ++q) y[(size_t)i * s + q] = d != 0.0 ? cd(vr[q], vi[q]) / d : cd(0.0);
-    }
-    for (size_t e = 0; e < y.size(); ++e) Y[e] = make_double2(y[e].real(), y[e].imag());
-  }
-};
-
 // Block right-preconditioned FGMRES on b (device) -> x (device, ctx->x) with
 // the one-level preconditioner. The right-hand sides are split into groups of
 // at most 32 columns; every group has its own block Krylov space, and the
@@ -1277,7 +1173,7 @@ int block_fgmres(mx_ctx* c, int S, double rtol, mx_solve_info* info, bool from_x
       if (!active[g]) continue;
       if (kk[g] == 0) return set_err(MX_ENOTCONV, "block FGMRES: the first block of a cycle lost rank");
       const int s = gs[g];
-      ls[g].solve(c->hb + 2 * 32 * 32);
+      ls[g].solve(reinterpret_cast<double*>(c->hb + 2 * 32 * 32));
       MX_HIP_CHECK(hipMemcpyAsync(c->bH.p, c->hb + 2 * 32 * 32, (size_t)kk[g] * s * s * sizeof(double2),
                                   hipMemcpyHostToDevice, st));
       launch_bupd(st, ne, kk[g] * s, s, Zg(g), (int64_t)m * s, c->bH.p, c->x.p + g0[g], S, c->x.p + g0[g], S, 1.0,
@@ -2169,14 +2065,25 @@ int build_local(mx_ctx* c, KTimer* tm) {
   const int64_t nloc = (int64_t)D.ldest.size();
   if (tm) tm->begin(K_LOCAL);
   const bool c64 = c->precision == MX_PREC_C64;
+  // after a completed factorisation only the tiles inside its recorded
+  // extents can be non-zero: clearing those suffices (a fraction of the bytes)
+  const bool envelope = c->pool_envelope;
+  c->pool_envelope = false;
   if (c64) {
     float2* F = (float2*)c->factors.p;
-    launch_fill_zero<float2>(c->stream, nent, F);
+    if (envelope)
+      launch_clear_envelope<float2>(c->stream, D.nsub, c->band_np, c->Npad.p, c->mat_off.p, c->ext_l.p, c->ext_u.p, F);
+    else
+      launch_fill_zero<float2>(c->stream, nent, F);
     launch_gather_dense<float2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
     launch_pad_identity<float2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
   } else {
     double2* F = (double2*)c->factors.p;
-    launch_fill_zero<double2>(c->stream, nent, F);
+    if (envelope)
+      launch_clear_envelope<double2>(c->stream, D.nsub, c->band_np, c->Npad.p, c->mat_off.p, c->ext_l.p, c->ext_u.p,
+                                     F);
+    else
+      launch_fill_zero<double2>(c->stream, nent, F);
     launch_gather_dense<double2>(c->stream, nloc, c->ldest.p, c->lptr.p, c->lsrc.p, c->pool.p, F);
     launch_pad_identity<double2>(c->stream, D.nsub, c->dof_ptr.p, c->Npad.p, c->mat_off.p, F);
   }
@@ -2241,6 +2148,7 @@ int factor_once(mx_ctx* c, int group, const std::vector<int32_t>& panel_rows, KT
                                     std::to_string(st[i] - 1));
   }
   MX_HIP_CHECK(hipEventElapsedTime(ms, c->ev_lu[0], c->ev_lu[1]));
+  c->pool_envelope = true;
   return MX_OK;
 }
 
@@ -2348,6 +2256,7 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
     CK(c->band_work.alloc(1));
     c->have_dec = true;
     c->pec_local_ready = false;
+    c->pool_envelope = false;
     c->ws_nrhs = 0;
     c->coarse_geom = false;
     c->ds_graphs = 0;
@@ -2357,9 +2266,14 @@ int mx_setup_schwarz(mx_ctx* c, int32_t nsub, int32_t overlap, const mx_schwarz_
   c->have_forward = false;
   CK(fill_pool(c));  // interface-face blocks for this permittivity
   const size_t nent = (size_t)D.mat_off[D.nsub];
-  if (c->precision != o.precision) c->factors.release();
+  if (c->precision != o.precision) {
+    c->factors.release();
+    c->pool_envelope = false;
+  }
   c->precision = o.precision;
+  const void* const pool_before = c->factors.p;
   CK(c->factors.alloc(nent * elem_bytes(o.precision)));
+  if (c->factors.p != pool_before) c->pool_envelope = false;
   CK(build_local(c, &c->prof));
   c->local_ready = true;
   if (o.factor) {

@@ -43,6 +43,11 @@ template <typename C>
 void launch_gather_dense(hipStream_t s, int64_t n, const int64_t* dest, const int64_t* ptr, const int32_t* src,
                          const double2* pool, C* out);
 template <typename C> void launch_fill_zero(hipStream_t s, int64_t n, C* out);
+// the factor tiles inside the extents ext_l / ext_u ([nsub][np]) recorded by
+// the last completed factorisation set back to zero
+template <typename C>
+void launch_clear_envelope(hipStream_t s, int32_t nsub, int np, const int32_t* Npad, const int64_t* mat_off,
+                           const int32_t* ext_l, const int32_t* ext_u, C* A);
 template <typename C>
 void launch_pad_identity(hipStream_t s, int32_t nsub, const int64_t* dof_ptr, const int32_t* Npad,
                          const int64_t* mat_off, C* A);

@@ -129,6 +129,39 @@ def test_preconditioner_every_panel_group(case, prec, tol):
         case.ctx.set_lu_group(0)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_setup_after_factorisation(case, prec):
+    """A set-up that follows a completed factorisation clears only the factor
+    tiles inside that factorisation's recorded extents before it gathers the
+    new local matrices. A factorisation of another permittivity in between
+    must leave no trace: the preconditioner of the original permittivity
+    comes out bit for bit as before, and the dense local matrices of a later
+    unfactored set-up equal the oracle's entry by entry."""
+    p = case.p
+    X = workload.seeded_complex((case.t.ne, 8), 13)
+    case.ctx.set_tuning(1, 1, 32)
+    try:
+        case.ctx.setup_schwarz(p.nsub, p.overlap, precision=prec)
+        Z1 = case.ctx.apply_preconditioner(X)
+        case.ctx.assemble(None, None, p.eps * (1.7 - 0.4j), p.eps_kind, p.freq, p.eps_b, reuse_mesh=True)
+        case.ctx.setup_schwarz(p.nsub, p.overlap, precision=prec)
+        Zo = case.ctx.apply_preconditioner(X)
+        assert not np.array_equal(Zo, Z1)
+        case.ctx.assemble(None, None, p.eps, p.eps_kind, p.freq, p.eps_b, reuse_mesh=True)
+        case.ctx.setup_schwarz(p.nsub, p.overlap, precision=prec)
+        Z2 = case.ctx.apply_preconditioner(X)
+        assert np.array_equal(Z1, Z2)
+        case.ctx.setup_schwarz(p.nsub, p.overlap, precision=prec, factor=False)
+        dec = schwarz.Decomposition(case.t, p.nsub, p.overlap)
+        tol = 1e-13 if prec == 0 else 2.0 ** -23  # complex64 storage: one rounding per entry
+        for i in range(p.nsub):
+            B = case.ctx.local_matrix(i)
+            ref = dec.local_matrix(i, p.eps, p.eps_kind, p.freq, p.eps_b).toarray()
+            assert np.all(np.abs(B - ref) <= tol * np.abs(ref) + 1e-13 * np.abs(ref).max()), i
+    finally:
+        case.ctx.set_autotune(True)
+
+
 @pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-5)])
 def test_fields_match_direct_solve(case, prec, tol):
     p = case.p
