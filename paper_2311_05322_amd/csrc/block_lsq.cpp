@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <stdexcept>
 
 namespace mx {
 
@@ -201,6 +202,9 @@ MX_ISA_VERSIONS(back_subst,
 }  // namespace
 
 void BlockLsq::reset(int s, int m, const std::vector<cd>& S0) {
+  // the register-held rows of the rotations and the back substitution hold 32
+  // values (block FGMRES splits wider blocks into groups of at most 32)
+  if (s < 1 || s > 32 || m < 1) throw std::invalid_argument("BlockLsq: block width must be 1..32, m >= 1");
   s_ = s;
   m_ = m;
   kdone_ = 0;
