@@ -89,13 +89,16 @@ __global__ void __launch_bounds__(BT, 3) k_bdot_mfma(int64_t nrows, int64_t rows
 
 // The narrow products (ka <= 32, e.g. Gram matrices) on the FP64 matrix
 // cores: every wave computes the whole 32 x 32 output over every fourth group
-// of 4 rows of the chunk, and the four waves' sums are added in wave order
-// through LDS before the chunk's partial is written.
-__global__ void __launch_bounds__(BT) k_bdot_narrow(int64_t nrows, int64_t rows_per_chunk, int ka, int s,
+// of 4 rows of the chunk, and the four waves' sums are added in a fixed order
+// through LDS before the chunk's partial is written. 32 KB of LDS and the
+// occupancy bound keep the accumulators in ordinary registers (with 64 KB and
+// no bound the compiler held them in the accumulation registers and copied
+// all 96 of them out and back on every step of the loop).
+__global__ void __launch_bounds__(BT, 4) k_bdot_narrow(int64_t nrows, int64_t rows_per_chunk, int ka, int s,
                                                     const double2* __restrict__ A, int64_t lda,
                                                     const double2* __restrict__ B, int64_t ldb,
                                                     double2* __restrict__ P) {
-  __shared__ double2 red[4][32][32];
+  __shared__ double2 red[2][32][32];
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
   const int64_t r1 = min(nrows, r0 + rows_per_chunk);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -128,25 +131,37 @@ __global__ void __launch_bounds__(BT) k_bdot_narrow(int64_t nrows, int64_t rows_
         t3[t][u] = mfma(ad[t], bs[u], t3[t][u]);
       }
   }
+  // the four waves' sums added in a fixed order through one 32 KB array:
+  // (w0 + w2) + (w1 + w3)
+  if (w >= 2) {
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        red[w][16 * t + acc_row<double>(lane, q)][16 * u + cl] =
-            make_double2(t1[t][u][q] + t2[t][u][q], t3[t][u][q] - t1[t][u][q] + t2[t][u][q]);
+        for (int q = 0; q < 4; ++q)
+          red[w - 2][16 * t + acc_row<double>(lane, q)][16 * u + cl] =
+              make_double2(t1[t][u][q] + t2[t][u][q], t3[t][u][q] - t1[t][u][q] + t2[t][u][q]);
+  }
+  __syncthreads();
+  if (w < 2) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double2& e = red[w][16 * t + acc_row<double>(lane, q)][16 * u + cl];
+          const double2 o = e;
+          e = make_double2(t1[t][u][q] + t2[t][u][q] + o.x, t3[t][u][q] - t1[t][u][q] + t2[t][u][q] + o.y);
+        }
+  }
   __syncthreads();
   double2* out = P + (int64_t)blockIdx.x * ka * s;
   for (int e = threadIdx.x; e < 32 * 32; e += BT) {
     const int a = e / 32, b = e % 32;
     if (a >= ka || b >= s) continue;
-    double re = 0, im = 0;
-    for (int ww = 0; ww < 4; ++ww) {
-      re += red[ww][a][b].x;
-      im += red[ww][a][b].y;
-    }
-    out[(int64_t)a * s + b] = make_double2(re, im);
+    out[(int64_t)a * s + b] = make_double2(red[0][a][b].x + red[1][a][b].x, red[0][a][b].y + red[1][a][b].y);
   }
 }
 
