@@ -77,9 +77,14 @@ __global__ void k_coarse_P(int64_t nrows, const int32_t* __restrict__ row_sub, c
 // 32 right-hand sides x [re, im]) product P^T V on the FP32 matrix cores,
 // 4 rows per step: wave w holds the coefficient tiles 3w .. 3w+2 against all
 // four column tiles; P rows (times the optional weight) and V rows (cast to
-// FP32, column n = 2 j + [re, im]) go straight into MFMA operands.
+// FP32, column n = 2 j + [re, im]) go straight into MFMA operands. Every
+// load of a step is unconditional (rows past the slice read row r0, columns
+// past nj column j0) and the unused values are cleared by bit masks: with
+// selects the compiler moved each V load into its own masked branch that
+// waited for it, five dependent memory round trips per step.
 constexpr int PS = 8;
-__global__ void __launch_bounds__(256) k_pool_part(int nsub, const int64_t* __restrict__ dof_ptr,
+template <bool WEIGHTED>
+__global__ void __launch_bounds__(256, 5) k_pool_part(int nsub, const int64_t* __restrict__ dof_ptr,
                                                    const int32_t* __restrict__ dofs, const float* __restrict__ P,
                                                    const double* __restrict__ wts, const double2* __restrict__ v,
                                                    int nrhs, int j0, int nj, float* __restrict__ Xp) {
@@ -94,14 +99,21 @@ __global__ void __launch_bounds__(256) k_pool_part(int nsub, const int64_t* __re
   const int64_t a0 = dof_ptr[i], a1 = dof_ptr[i + 1];
   const int64_t len = (a1 - a0 + PS - 1) / PS;
   const int64_t r0 = a0 + y * len, r1 = min(a1, r0 + len);
+  // the slice's DOF indices (at most 8192 / PS rows: subdomains hold at most
+  // 8192 unknowns) staged in LDS, so that a step's V loads wait on an LDS
+  // read instead of a dependent global load
+  __shared__ int32_t sdof[8192 / PS];
+  for (int64_t r = r0 + tid; r < r1; r += 256) sdof[r - r0] = dofs[r];
+  __syncthreads();
   // B operand columns of this lane: n = 16 nt + lane % 16 -> j = n / 2, part n % 2
   int jb[4];
-  bool bok[4];
+  uint32_t bmask[4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     const int n = 16 * nt + (lane & 15);
-    jb[nt] = n >> 1;
-    bok[nt] = (n >> 1) < nj;
+    const bool bok = (n >> 1) < nj;
+    jb[nt] = bok ? n >> 1 : 0;
+    bmask[nt] = bok ? 0xffffffffu : 0u;
   }
   const int part = lane & 1;
   for (int64_t kr = r0; kr < r1; kr += 4) {
@@ -109,16 +121,18 @@ __global__ void __launch_bounds__(256) k_pool_part(int nsub, const int64_t* __re
     const int64_t row = kr + (lane >> 4);
     const bool ok = row < r1;
     const int64_t rr = ok ? row : r0;
-    const float wr = ok ? (wts ? (float)wts[rr] : 1.f) : 0.f;
+    const uint32_t rmask = ok ? 0xffffffffu : 0u;
     float a[3], b[4];
+    double d[4];
 #pragma unroll
     for (int mt = 0; mt < 3; ++mt) a[mt] = P[rr * NCO + 16 * (3 * w + mt) + (lane & 15)];
-    const double2* vr = v + (int64_t)dofs[rr] * nrhs + j0;
+    const double* vr = reinterpret_cast<const double*>(v + (int64_t)sdof[rr - r0] * nrhs + j0) + part;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const double2 d = vr[bok[nt] ? jb[nt] : 0];
-      b[nt] = bok[nt] ? wr * (float)(part ? d.y : d.x) : 0.f;
-    }
+    for (int nt = 0; nt < 4; ++nt) d[nt] = vr[2 * jb[nt]];
+    const float wr = WEIGHTED ? (float)wts[rr] : 1.f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+      b[nt] = __uint_as_float(__float_as_uint(wr * (float)d[nt]) & (bmask[nt] & rmask));
 #pragma unroll
     for (int mt = 0; mt < 3; ++mt)
 #pragma unroll
@@ -134,7 +148,7 @@ __global__ void __launch_bounds__(256) k_pool_part(int nsub, const int64_t* __re
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int coef = 16 * (3 * w + mt) + acc_row<float>(lane, r);
-        xp[((int64_t)jb[nt] * nsub + i) * NIN + part * NCO + coef] = acc[mt][nt][r];
+        xp[((int64_t)((16 * nt + (lane & 15)) >> 1) * nsub + i) * NIN + part * NCO + coef] = acc[mt][nt][r];
       }
 }
 
@@ -161,7 +175,7 @@ __global__ void __launch_bounds__(256) k_pool_sum(int nsub, int j0, int nj, cons
 // right-hand sides (scaled by alpha s_j) are staged in LDS as [k][n]; each
 // wave takes every fourth 16-row block of its workgroup's share.
 template <typename C>
-__global__ void __launch_bounds__(256) k_coarse_apply(const int32_t* __restrict__ lpos,
+__global__ void __launch_bounds__(256, 3) k_coarse_apply(const int32_t* __restrict__ lpos,
                                                       const int64_t* __restrict__ dof_ptr,
                                                       const int64_t* __restrict__ vec_off, const float* __restrict__ P,
                                                       const float* __restrict__ Cn, int nsub, int nrhs, int j0, int nj,
@@ -180,45 +194,62 @@ __global__ void __launch_bounds__(256) k_coarse_apply(const int32_t* __restrict_
   }
   __syncthreads();
   const int64_t r0 = dof_ptr[i], r1 = dof_ptr[i + 1];
+  const int64_t voff = vec_off[i];
   const int64_t step = 16 * 4 * (int64_t)gridDim.y;
   for (int64_t rb = r0 + 16 * ((int64_t)blockIdx.y * 4 + w); rb < r1; rb += step) {
     // A[m][k] = P[row rb + m][k] (rows past the end read the last row; not
     // written). K is taken in blocks of 64 with lane group g = lane / 16
     // holding k = 64 kb + 16 g + t at step t, so that a lane reads its 16
-    // coefficients of the block as four 16-byte loads.
+    // coefficients of a block as four 16-byte loads; all twelve are issued
+    // before the first product.
     const float4* pr = reinterpret_cast<const float4*>(P + min(rb + (lane & 15), r1 - 1) * NCO) + 4 * (lane >> 4);
+    float4 p4[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) p4[q] = pr[16 * (q >> 2) + (q & 3)];
+    // destination rows of this lane's results (clamped, so that every load
+    // below is in bounds; only rows < r1 are written)
+    int64_t xoff[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = rb + acc_row<float>(lane, r);
+      xoff[r] = (voff + lpos[row < r1 ? row : r1 - 1]) * nrhs + j0;
+    }
     f32x4 acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-    for (int kb = 0; kb < NCO / 64; ++kb) {
-      float a[16];
+#pragma unroll
+    for (int kb = 0; kb < NCO / 64; ++kb)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float4 t4 = pr[16 * kb + q];
-        a[4 * q] = t4.x;
-        a[4 * q + 1] = t4.y;
-        a[4 * q + 2] = t4.z;
-        a[4 * q + 3] = t4.w;
+        const float4 t4 = p4[4 * kb + q];
+        const float a[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt)
+            acc[nt] = mfma(a[e], Cs[64 * kb + 16 * (lane >> 4) + 4 * q + e][16 * nt + (lane & 15)], acc[nt]);
+        // keep the scheduler from hoisting every LDS operand of the 192
+        // products at once (their registers would spill)
+        __builtin_amdgcn_sched_barrier(0);
       }
-#pragma unroll
-      for (int t = 0; t < 16; ++t)
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-          acc[nt] = mfma(a[t], Cs[64 * kb + 16 * (lane >> 4) + t][16 * nt + (lane & 15)], acc[nt]);
-    }
-    // acc[nt][r]: row rb + 4 (lane / 16) + r, column 16 nt + lane % 16 -> j, part
+    // acc[nt][r]: row rb + 4 (lane / 16) + r, column 16 nt + lane % 16 -> j, part.
+    // Read-modify-write of xloc with every load issued before the first
+    // store (a load after a store to the same array would wait for it).
+    R xv[4][4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       const int n = 16 * nt + (lane & 15), jj = n >> 1;
-      if (jj >= nj) continue;
+      const int jc = jj < nj ? jj : 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xv[nt][r] = reinterpret_cast<const R*>(xloc + xoff[r] + jc)[n & 1];
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int n = 16 * nt + (lane & 15), jj = n >> 1;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = rb + acc_row<float>(lane, r);
-        if (row < r1) {
-          R* x = reinterpret_cast<R*>(xloc + (vec_off[i] + lpos[row]) * nrhs + j0 + jj) + (n & 1);
-          *x += (R)acc[nt][r];
-        }
+        if (jj < nj && row < r1) reinterpret_cast<R*>(xloc + xoff[r] + jj)[n & 1] = xv[nt][r] + (R)acc[nt][r];
       }
     }
   }
@@ -275,7 +306,7 @@ constexpr int GK = 32;       // K chunk
 constexpr int GKP = GK + 8;  // LDS row pitch (bf16 values): 80 bytes
 
 template <bool TA, bool TB>
-__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
+__global__ void __launch_bounds__(256, 4) k_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
                                               const float* __restrict__ B, int ldb, float* __restrict__ Cm, int ldc,
                                               int beta, const float* __restrict__ bias, int act,
                                               float* __restrict__ Z) {
@@ -468,8 +499,12 @@ void launch_pool(hipStream_t s, int nsub, const int64_t* dof_ptr, const int32_t*
                  const double* wts, const double2* v, int nrhs, const double* scale, float* X, float* part) {
   for (int j0 = 0; j0 < nrhs; j0 += 32) {
     int nj = nrhs - j0 < 32 ? nrhs - j0 : 32;
-    hipLaunchKernelGGL(k_pool_part, dim3(nsub, PS), dim3(256), 0, s, nsub, dof_ptr, dofs, P, wts, v, nrhs, j0, nj,
-                       part);
+    if (wts)
+      hipLaunchKernelGGL(k_pool_part<true>, dim3(nsub, PS), dim3(256), 0, s, nsub, dof_ptr, dofs, P, wts, v, nrhs, j0,
+                         nj, part);
+    else
+      hipLaunchKernelGGL(k_pool_part<false>, dim3(nsub, PS), dim3(256), 0, s, nsub, dof_ptr, dofs, P, wts, v, nrhs,
+                         j0, nj, part);
     hipLaunchKernelGGL(k_pool_sum, dim3(nblk((int64_t)nj * nsub * NIN, 256)), dim3(256), 0, s, nsub, j0, nj, scale,
                        part, X, (int64_t)NIN);
   }
