@@ -453,12 +453,16 @@ __global__ void __launch_bounds__(256) k_lu_rowswap(C_t<R>* __restrict__ pool, c
   C* A = pool + mat_off[s];
   const int32_t* ps = pswap + (int64_t)s * (2 * MAXSW + 1);
   const int n = ps[0];
+  if (n == 0) return;  // the whole workgroup
   const int tid = threadIdx.x;
+  // every load unconditional (entries past the swap list repeat its first
+  // row; they are not stored), so that they are all in flight together
   C v[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = tid + 256 * u;
-    if (e < n * NB) v[u] = A[(int64_t)ps[1 + MAXSW + e / NB] * N + cb + e % NB];
+    const int ec = e < n * NB ? e : e % NB;
+    v[u] = A[(int64_t)ps[1 + MAXSW + ec / NB] * N + cb + ec % NB];
   }
   __syncthreads();
 #pragma unroll
