@@ -53,24 +53,52 @@ __global__ void __launch_bounds__(BT, 3) k_bdot_mfma(int64_t nrows, int64_t rows
       for (int q = 0; q < 4; ++q) t1[t][u][q] = t2[t][u][q] = t3[t][u][q] = 0.0;
   const bool aok0 = abase + cl < ka, aok1 = abase + 16 + cl < ka;
   const bool bok0 = cl < s, bok1 = 16 + cl < s;
-  for (int64_t rs = r0; rs < r1; rs += 4) {
-    const int64_t r = rs + kq;
-    const bool rok = r < r1;
-    double2 av[2], bv[2];
-    av[0] = rok && aok0 ? A[r * lda + abase + cl] : make_double2(0.0, 0.0);
-    av[1] = rok && aok1 ? A[r * lda + abase + 16 + cl] : make_double2(0.0, 0.0);
-    bv[0] = rok && bok0 ? B[r * ldb + cl] : make_double2(0.0, 0.0);
-    bv[1] = rok && bok1 ? B[r * ldb + 16 + cl] : make_double2(0.0, 0.0);
-    const double ad[2] = {av[0].x - av[0].y, av[1].x - av[1].y};
-    const double bs[2] = {bv[0].x + bv[0].y, bv[1].x + bv[1].y};
+  // every load unconditional, from a clamped (valid) row and column, with the
+  // values outside the product cleared afterwards by selects; two operand
+  // sets in rotation (no register copies, which would wait for the loads):
+  // each group of 4 rows is loaded while the previous one is multiplied, so
+  // each wave keeps two groups' loads in flight. A group past the chunk's end
+  // contributes exact zeros.
+  const double2* Ap0 = A + min(abase + cl, ka - 1);
+  const double2* Ap1 = A + min(abase + 16 + cl, ka - 1);
+  const double2* Bp0 = B + min(cl, s - 1);
+  const double2* Bp1 = B + min(16 + cl, s - 1);
+  const double2 z2 = make_double2(0.0, 0.0);
+  auto load = [&](int64_t rs, double2 (&a)[2], double2 (&b)[2]) {
+    const int64_t r = min(rs + kq, r1 - 1);
+    a[0] = Ap0[r * lda];
+    a[1] = Ap1[r * lda];
+    b[0] = Bp0[r * ldb];
+    b[1] = Bp1[r * ldb];
+  };
+  auto multiply = [&](int64_t rs, const double2 (&a)[2], const double2 (&b)[2]) {
+    const bool rok = rs + kq < r1;
+    const double2 ac[2] = {rok && aok0 ? a[0] : z2, rok && aok1 ? a[1] : z2};
+    const double2 bc[2] = {rok && bok0 ? b[0] : z2, rok && bok1 ? b[1] : z2};
+    const double ad[2] = {ac[0].x - ac[0].y, ac[1].x - ac[1].y};
+    const double bs[2] = {bc[0].x + bc[0].y, bc[1].x + bc[1].y};
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        t1[t][u] = mfma(av[t].x, bv[u].x, t1[t][u]);
-        t2[t][u] = mfma(av[t].y, bv[u].y, t2[t][u]);
+        t1[t][u] = mfma(ac[t].x, bc[u].x, t1[t][u]);
+        t2[t][u] = mfma(ac[t].y, bc[u].y, t2[t][u]);
         t3[t][u] = mfma(ad[t], bs[u], t3[t][u]);
       }
+  };
+  if (r0 < r1) {
+    double2 a0[2], b0[2], a1[2], b1[2];
+    load(r0, a0, b0);
+    for (int64_t rs = r0; rs < r1; rs += 8) {
+      load(rs + 4, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      multiply(rs, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(rs + 8, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      multiply(rs + 4, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   double2* out = P + (int64_t)blockIdx.x * ka * s;
 #pragma unroll
@@ -172,7 +200,7 @@ __global__ void __launch_bounds__(BT, 4) k_bdot_narrow(int64_t nrows, int64_t ro
 // admits four workgroups per CU, the register cap's occupancy: four waves per
 // SIMD, with two values spilled outside the loops); lane l holds A's row
 // l & 15 of each tile at column 4c + (l >> 4).
-__global__ void __launch_bounds__(BT, 4) k_bupd_mfma(int64_t nrows, int ka, int s, const double2* __restrict__ A,
+__global__ void __launch_bounds__(BT, 3) k_bupd_mfma(int64_t nrows, int ka, int s, const double2* __restrict__ A,
                                                   int64_t lda, const double2* __restrict__ H,
                                                   const double2* Win, int64_t ldwin, double2* Wout,
                                                   int64_t ldwout, double alpha, double beta, double2* Wout2,
@@ -192,8 +220,33 @@ __global__ void __launch_bounds__(BT, 4) k_bupd_mfma(int64_t nrows, int ka, int 
 #pragma unroll
       for (int q = 0; q < 4; ++q) t1[t][u][q] = t2[t][u][q] = t3[t][u][q] = 0.0;
   const bool rok0 = rw + cl < nrows, rok1 = rw + 16 + cl < nrows;
-  const double2* A0 = A + (rw + cl) * lda;
-  const double2* A1 = A + (rw + 16 + cl) * lda;
+  // A's loads unconditional from clamped (valid) rows and columns, cleared
+  // afterwards by selects; two operand sets in rotation, so that each group
+  // of 4 columns is loaded while the previous one is multiplied
+  const double2* A0 = A + min(rw + cl, nrows - 1) * lda;
+  const double2* A1 = A + min(rw + 16 + cl, nrows - 1) * lda;
+  const double2 z2 = make_double2(0.0, 0.0);
+  auto load = [&](int a, double2 (&av)[2]) {
+    const int ac = min(a + kq, ka - 1);
+    av[0] = A0[ac];
+    av[1] = A1[ac];
+  };
+  auto multiply = [&](int aa, int na, const double2 (&av)[2]) {
+    const bool aok = aa + kq < na;
+    const double2 ac[2] = {rok0 && aok ? av[0] : z2, rok1 && aok ? av[1] : z2};
+    const int ah = min(aa + kq, UA - 1);
+    const double2 hv[2] = {Hs[ah][cl], Hs[ah][16 + cl]};
+    const double as[2] = {ac[0].x + ac[0].y, ac[1].x + ac[1].y};
+    const double hs[2] = {hv[0].x + hv[0].y, hv[1].x + hv[1].y};
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        t1[t][u] = mfma(ac[t].x, hv[u].x, t1[t][u]);
+        t2[t][u] = mfma(ac[t].y, hv[u].y, t2[t][u]);
+        t3[t][u] = mfma(as[t], hs[u], t3[t][u]);
+      }
+  };
   for (int a0 = 0; a0 < ka; a0 += UA) {
     const int na = min(UA, ka - a0);
     __syncthreads();
@@ -202,28 +255,35 @@ __global__ void __launch_bounds__(BT, 4) k_bupd_mfma(int64_t nrows, int ka, int 
       Hs[aa][bb] = (aa < na && bb < s) ? H[(int64_t)(a0 + aa) * s + bb] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int aa = 0; aa < na; aa += 4) {
-      const int a = a0 + aa + kq;
-      const bool aok = aa + kq < na;
-      double2 av[2], hv[2];
-      av[0] = rok0 && aok ? A0[a] : make_double2(0.0, 0.0);
-      av[1] = rok1 && aok ? A1[a] : make_double2(0.0, 0.0);
-      hv[0] = Hs[aa + kq][cl];
-      hv[1] = Hs[aa + kq][16 + cl];
-      const double as[2] = {av[0].x + av[0].y, av[1].x + av[1].y};
-      const double hs[2] = {hv[0].x + hv[0].y, hv[1].x + hv[1].y};
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          t1[t][u] = mfma(av[t].x, hv[u].x, t1[t][u]);
-          t2[t][u] = mfma(av[t].y, hv[u].y, t2[t][u]);
-          t3[t][u] = mfma(as[t], hs[u], t3[t][u]);
-        }
+    double2 x0[2], x1[2];
+    load(a0, x0);
+    for (int aa = 0; aa < na; aa += 8) {
+      load(a0 + aa + 4, x1);
+      __builtin_amdgcn_sched_barrier(0);
+      multiply(aa, na, x0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(a0 + aa + 8, x0);
+      __builtin_amdgcn_sched_barrier(0);
+      multiply(aa + 4, na, x1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
+  // epilogue per 16-row tile: the 8 values of Win it needs are loaded
+  // together (clamped, valid addresses) before any is used, one memory round
+  // trip instead of eight; each element is read and written by one lane, so
+  // Win may be Wout
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < 2; ++t) {
+    double2 wv[2][4];
+    if (beta != 0.0) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t r = min(rw + 16 * t + acc_row<double>(lane, q), nrows - 1);
+          wv[u][q] = Win[r * ldwin + min(16 * u + cl, s - 1)];
+        }
+    }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -234,13 +294,13 @@ __global__ void __launch_bounds__(BT, 4) k_bupd_mfma(int64_t nrows, int ka, int 
         double re = alpha * (t1[t][u][q] - t2[t][u][q]);
         double im = alpha * (t3[t][u][q] - t1[t][u][q] - t2[t][u][q]);
         if (beta != 0.0) {
-          const double2 v = Win[r * ldwin + b];
-          re = fma(beta, v.x, re);
-          im = fma(beta, v.y, im);
+          re = fma(beta, wv[u][q].x, re);
+          im = fma(beta, wv[u][q].y, im);
         }
         Wout[r * ldwout + b] = make_double2(re, im);
         if (Wout2) Wout2[r * ldwout2 + b] = make_double2(re, im);
       }
+  }
 }
 
 // out[i] = sum over chunks c of P[c][i], i < n; a workgroup takes 32
