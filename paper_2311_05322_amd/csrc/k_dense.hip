@@ -1073,6 +1073,21 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), (NCT == 1 && sizeof(R) =
             cim[rt][ct] = t3[rt][ct] - t1 - t2;
           }
       }
+      // the super-block's own right-hand-side rows, all loaded before any is
+      // used (columns beyond nc read the last column and are cleared by a
+      // select): one memory round trip, where a guarded load per value had
+      // compiled to a masked branch that waited for each load in turn
+      C xv[TRT][NCT][4];
+#pragma unroll
+      for (int rt = 0; rt < TRT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * TRT * w + 16 * rt + acc_row<R>(lane, r);
+            const int col = min(16 * ct + (lane & 15), nc - 1);
+            xv[rt][ct][r] = X[(int64_t)(b0 + row) * nrhs + j0 + col];
+          }
 #pragma unroll
       for (int rt = 0; rt < TRT; ++rt)
 #pragma unroll
@@ -1081,7 +1096,7 @@ __global__ void __launch_bounds__(64 * trsm_waves<R>(), (NCT == 1 && sizeof(R) =
           for (int r = 0; r < 4; ++r) {
             const int row = 16 * TRT * w + 16 * rt + acc_row<R>(lane, r);
             const int col = 16 * ct + (lane & 15);
-            C x = col < nc ? X[(int64_t)(b0 + row) * nrhs + j0 + col] : czero<C>();
+            C x = col < nc ? xv[rt][ct][r] : czero<C>();
             x.x -= cre[rt][ct][r];
             x.y -= cim[rt][ct][r];
             Tb[row][col] = x;
